@@ -1,0 +1,149 @@
+"""Seeded synthetic vortex workloads.
+
+This module only draws random inputs (positions, circulations, kernel cores,
+unit vectors).  It holds none of the method's arithmetic and is shared by the
+HIP path's tests/benchmark and the oracle's tests.  All draws are float64 from
+``numpy.random.default_rng(seed)``; callers cast once to the dtype they need.
+
+State vectors use the SoA layout ``xy = [x_0..x_{N-1}, y_0..y_{N-1}]``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Cloud:
+    xy: np.ndarray          # [2N] float64
+    gamma: np.ndarray       # [N] float64
+    delta: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.gamma.size
+
+
+def _soa(x, y):
+    return np.concatenate([x, y])
+
+
+def uniform_disk(n, seed, radius=1.0):
+    """Points uniform in a disk: r = R sqrt(U), theta = 2 pi U'."""
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.random(n))
+    th = 2.0 * np.pi * rng.random(n)
+    return rng, _soa(r * np.cos(th), r * np.sin(th))
+
+
+def disk_cloud(n=1024, seed=1001, delta=0.02):
+    """Uniform unit disk, Gamma ~ N(0,1) shifted to sum zero."""
+    rng, xy = uniform_disk(n, seed)
+    g = rng.standard_normal(n)
+    g = g - g.mean()
+    return Cloud(xy, g, delta, dict(kind="disk"))
+
+
+def gaussian_patch(n=65536, seed=1002, sigma=0.25, delta=0.01, gamma0=1.0, width=0.1):
+    """Gaussian vortex patch: x ~ N(0, sigma^2 I), Gamma_i = Gamma0 exp(-|x_i|^2/width)/N."""
+    rng = np.random.default_rng(seed)
+    x = sigma * rng.standard_normal(n)
+    y = sigma * rng.standard_normal(n)
+    g = gamma0 * np.exp(-(x * x + y * y) / width) / n
+    return Cloud(_soa(x, y), g, delta, dict(kind="gaussian_patch", sigma=sigma))
+
+
+def counter_rotating_patches(n=16384, seed=1003, sigma=0.15, delta=0.01, sep=0.5):
+    """Two Gaussian patches at (-sep, 0) with Gamma = +1/(n/2) each and at
+    (+sep, 0) with Gamma = -1/(n/2) each."""
+    rng = np.random.default_rng(seed)
+    h = n // 2
+    x = np.concatenate([-sep + sigma * rng.standard_normal(h), sep + sigma * rng.standard_normal(n - h)])
+    y = sigma * rng.standard_normal(n)
+    g = np.concatenate([np.full(h, 1.0 / h), np.full(n - h, -1.0 / (n - h))])
+    return Cloud(_soa(x, y), g, delta, dict(kind="counter_rotating", sigma=sigma))
+
+
+def shear_layer(n=131072, seed=1005, delta=0.01, thickness=0.05, amp=1e-3):
+    """Perturbed circular shear layer: theta ~ U[0,2pi), r = 1 + t(U - 1/2) + amp xi,
+    Gamma = 1/N."""
+    rng = np.random.default_rng(seed)
+    th = 2.0 * np.pi * rng.random(n)
+    r = 1.0 + thickness * (rng.random(n) - 0.5) + amp * rng.standard_normal(n)
+    return Cloud(_soa(r * np.cos(th), r * np.sin(th)), np.full(n, 1.0 / n), delta, dict(kind="shear_layer"))
+
+
+def unit_vectors(n, k, seed):
+    """k random unit vectors of length 2n (Gaussian, normalized)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((k, 2 * n))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def random_vectors(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((k, 2 * n))
+
+
+@dataclass
+class Batch:
+    offsets: np.ndarray     # [B+1] int64, instance b owns bodies offsets[b]..offsets[b+1]
+    xy: np.ndarray          # [2 * total] float64: per-instance SoA blocks [x_b, y_b] back to back
+    gamma: np.ndarray       # [total] float64
+    delta: np.ndarray       # [B] float64
+    scale: np.ndarray       # [B] float64
+
+
+def batched_patches(B=256, seed=1004, nmin=2048, nmax=32768, dmin=0.005, dmax=0.05,
+                    smin=0.5, smax=2.0, sigma=0.25, width=0.1):
+    """Parametric batch: N_b = round(exp(U[ln nmin, ln nmax])), delta_b ~ U[dmin, dmax],
+    scale s_b ~ U[smin, smax]; Gaussian patch positions, Gamma_i = s_b exp(-|x|^2/width)/N_b.
+
+    Layout of ``xy``: instance b occupies [2*offsets[b], 2*offsets[b+1]) as
+    its own SoA block [x_0..x_{Nb-1}, y_0..y_{Nb-1}]."""
+    rng = np.random.default_rng(seed)
+    nb = np.rint(np.exp(rng.uniform(np.log(nmin), np.log(nmax), B))).astype(np.int64)
+    dl = rng.uniform(dmin, dmax, B)
+    sc = rng.uniform(smin, smax, B)
+    off = np.zeros(B + 1, dtype=np.int64)
+    off[1:] = np.cumsum(nb)
+    xy = np.empty(2 * off[-1])
+    g = np.empty(off[-1])
+    for b in range(B):
+        n = int(nb[b])
+        x = sigma * rng.standard_normal(n)
+        y = sigma * rng.standard_normal(n)
+        xy[2 * off[b]: 2 * off[b] + n] = x
+        xy[2 * off[b] + n: 2 * off[b + 1]] = y
+        g[off[b]: off[b + 1]] = sc[b] * np.exp(-(x * x + y * y) / width) / n
+    return Batch(off, xy, g, dl, sc)
+
+
+# ---------------------------------------------------------------------------
+# named workloads (sizes of the five benchmark configurations)
+# ---------------------------------------------------------------------------
+
+CONFIGS = {
+    "c1_disk_fp64": dict(n=1024, seed=1001, delta=0.02, dt=1e-3, steps=100),
+    "c2_gaussian_patch": dict(n=65536, seed=1002, delta=0.01, dt=5e-4, steps=50, njvp=8),
+    "c3_ptrom_pipeline": dict(n=16384, seed=1003, delta=0.01, dt=1e-3, snapshots=400, M=8, Mr=16,
+                              ns=16, depth=6, pc=1.0, tol=1e-4, max_iter=100, steps=400),
+    "c4_batched": dict(B=256, seed=1004, dt=1e-3, steps=20),
+    "c5_adjoint": dict(n=131072, seed=1005, delta=0.01, dt=5e-4, steps=200, every=20),
+}
+
+
+def config_cloud(name, n=None):
+    c = CONFIGS[name]
+    n = c["n"] if n is None else n
+    if name == "c1_disk_fp64":
+        return disk_cloud(n, c["seed"], c["delta"])
+    if name == "c2_gaussian_patch":
+        return gaussian_patch(n, c["seed"], delta=c["delta"])
+    if name == "c3_ptrom_pipeline":
+        return counter_rotating_patches(n, c["seed"], delta=c["delta"])
+    if name == "c5_adjoint":
+        return shear_layer(n, c["seed"], delta=c["delta"])
+    raise KeyError(name)

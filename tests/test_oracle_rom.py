@@ -1,0 +1,157 @@
+"""Pins of the oracle's PTROM pieces (offline training and the online
+Gauss-Newton / HyperPair step) against special cases whose answer is known
+without the ROM: no clustering reproduces the exact pair sum (GNAT limit of an
+infinitely wide neighbourhood), cluster surrogates are linear in xhat, full-rank
+LSPG reproduces the trapezoid FOM, the greedy sampler on hand-made bases."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import offline as off
+from paper_2103_01983_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def small_problem():
+    cl = W.counter_rotating_patches(192, seed=77, delta=0.05)
+    S = off.trapezoid_snapshots(cl.xy, cl.gamma, cl.delta, 2e-3, 24)
+    Phi, sig = off.pod(S, 6)
+    tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+    return cl, S, Phi, sig, tree
+
+
+def test_pod_basis_properties(small_problem):
+    cl, S, Phi, sig, _ = small_problem
+    np.testing.assert_allclose(Phi.T @ Phi, np.eye(Phi.shape[1]), atol=1e-12)
+    # columns are eigenvectors of S S^T with eigenvalues sigma^2
+    np.testing.assert_allclose(S @ (S.T @ Phi), Phi * sig ** 2, rtol=0, atol=1e-9 * sig[0] ** 2)
+    assert np.all(np.diff(sig) <= 0)
+
+
+def test_quadtree_partition(small_problem):
+    cl, _, Phi, sig, tree = small_problem
+    P = off.weighted_points(Phi, sig)
+    n = cl.n
+    seen = np.zeros(n, int)
+    for nd in tree.nodes:
+        if not nd.children:
+            for j in nd.members:
+                seen[j] += 1
+                assert np.all(P[j] >= nd.lo - 1e-15) and np.all(P[j] <= nd.hi + 1e-15)
+            assert len(nd.members) == 1 or nd.level == tree.max_level
+        else:
+            assert sorted(sum((c.members for c in nd.children), [])) == sorted(nd.members)
+        assert nd.level <= tree.max_level
+    assert np.all(seen == 1)
+
+
+def test_surrogates_are_weighted_means_for_every_xhat(small_problem):
+    # x0_c + Phit_c xhat equals the |Gamma|-weighted mean of the members'
+    # x0 + Phi xhat, for any xhat; the root carries the total circulation.
+    cl, _, Phi, sig, tree = small_problem
+    n = cl.n
+    rng = np.random.default_rng(0)
+    xh = rng.standard_normal(Phi.shape[1])
+    x = cl.xy + Phi @ xh
+    for nd in tree.nodes[:40]:
+        x0c, phc, gc = off.node_surrogates(nd, cl.xy, Phi, cl.gamma)
+        w = np.abs(cl.gamma[nd.members])
+        mean = np.array([np.sum(w * x[nd.members]), np.sum(w * x[n + np.array(nd.members)])]) / w.sum()
+        np.testing.assert_allclose(x0c + phc @ xh, mean, atol=1e-13)
+    assert off.node_surrogates(tree.root, cl.xy, Phi, cl.gamma)[2] == pytest.approx(cl.gamma.sum(), abs=1e-15)
+
+
+def test_no_clustering_gives_exact_sampled_rows(small_problem):
+    # An infinitely wide neighbourhood prunes nothing: every target sees every
+    # other body, so HyperPair's velocity must equal the full pair sum at
+    # x0 + Phi xhat on the sampled rows (the GNAT limit).
+    cl, _, Phi, sig, tree = small_problem
+    n = cl.n
+    sample = np.array([0, 5, 90, 191])
+    art = off.rom_artifacts(sample, tree, np.inf, cl.xy, Phi, cl.gamma, cl.delta, 1e-3)
+    assert art["Gt"].size == n and np.all(np.diff(art["off"]) == n - 1)
+    rom = oracle.Rom(art)
+    xh = np.random.default_rng(1).standard_normal(Phi.shape[1]) * 0.1
+    xbar, fbar, rbar, C = rom.hyperpair(xh, np.zeros(8), np.zeros(8))
+    x = cl.xy + Phi @ xh
+    np.testing.assert_allclose(xbar, x[off.sampled_rows(sample, n)], atol=1e-14)
+    np.testing.assert_allclose(fbar, oracle.velocity_at(x, cl.gamma, cl.delta, sample), rtol=1e-12, atol=1e-14)
+    # exact-mode C = (I - dt/2 J) Phi on the sampled rows
+    rom1 = oracle.Rom(art, jac_mode=1)
+    _, _, _, C1 = rom1.hyperpair(xh, np.zeros(8), np.zeros(8))
+    JPhi = np.stack([oracle.jvp(x, cl.gamma, cl.delta, Phi[:, q]) for q in range(Phi.shape[1])], axis=1)
+    expect = Phi - 0.5e-3 * JPhi
+    np.testing.assert_allclose(C1, expect[off.sampled_rows(sample, n)], rtol=1e-11, atol=1e-13)
+
+
+def test_pruned_lists_cover_every_body_once(small_problem):
+    cl, _, Phi, sig, tree = small_problem
+    keys_nodes = {nd.key: nd for nd in tree.nodes}
+    for i in [0, 17, 100, 191]:
+        members = []
+        for k in off.find_clusters(tree, i, 1.0):
+            members.extend([k[1]] if k[0] == 0 else keys_nodes[k].members)
+        assert sorted(members) == [j for j in range(cl.n) if j != i]
+
+
+def test_full_rank_lspg_reproduces_trapezoid_fom():
+    # With Phi spanning the centred trapezoid snapshots, no clustering and no
+    # hyper-reduction, the LSPG minimiser is the FOM state (zero residual).
+    cl = W.gaussian_patch(64, seed=3, delta=0.05)
+    g = cl.gamma * 64
+    dt, T = 2e-3, 6
+    S = off.trapezoid_snapshots(cl.xy, g, cl.delta, dt, T)
+    Phi, sig = off.pod(S, T, x0=cl.xy)
+    tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+    art = off.rom_artifacts(np.arange(64), tree, np.inf, cl.xy, Phi, g, cl.delta, dt)
+    out = oracle.Rom(art, jac_mode=1).run(T, tol=1e-13, max_iter=30)
+    assert out["status"] == 0
+    rec = cl.xy[:, None] + Phi @ out["hist"].T
+    np.testing.assert_allclose(rec, S, rtol=0, atol=1e-9)
+
+
+def test_gauss_newton_stops_on_relative_gradient():
+    cl = W.gaussian_patch(48, seed=5, delta=0.05)
+    g = cl.gamma * 48
+    S = off.trapezoid_snapshots(cl.xy, g, cl.delta, 2e-3, 8)
+    Phi, sig = off.pod(S, 3, x0=cl.xy)
+    tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+    art = off.rom_artifacts(np.arange(48), tree, 1.0, cl.xy, Phi, g, cl.delta, 2e-3)
+    rom = oracle.Rom(art)
+    out = rom.run(4, tol=1e-3, max_iter=100)
+    assert out["status"] == 0 and np.all(out["iters"] >= 2)
+    capped = rom.run(4, tol=0.0, max_iter=3)
+    assert capped["status"] == 1 and np.all(capped["iters"] == 3)
+
+
+def test_greedy_hand_made_basis():
+    n = 10
+    Phi_r = np.zeros((2 * n, 2))
+    Phi_r[3, 0] = 1.0            # body 3, chi row
+    Phi_r[n + 7, 1] = 1.0        # body 7, psi row
+    assert list(off.greedy_sample(Phi_r, 2)) == [3, 7]
+    # ties go to the lowest body index
+    Phi_r2 = np.zeros((2 * n, 1)); Phi_r2[[2, 5, n + 8], 0] = 1.0
+    assert list(off.greedy_sample(Phi_r2, 1)) == [2]
+
+
+def test_greedy_full_sample_and_gappy_operator():
+    rng = np.random.default_rng(2)
+    n = 12
+    Phi_r = np.linalg.qr(rng.standard_normal((2 * n, 6)))[0]
+    assert list(off.greedy_sample(Phi_r, n)) == list(range(n))
+    s = off.greedy_sample(Phi_r, 4)
+    A = off.gappy_operator(Phi_r, s)
+    # gappy reconstruction is exact for vectors in the span of Phi_r
+    z = rng.standard_normal(6)
+    r = Phi_r @ z
+    np.testing.assert_allclose(A @ r[off.sampled_rows(s, n)], z, atol=1e-10)
+
+
+def test_full_pipeline_small():
+    cl = W.counter_rotating_patches(128, seed=9, delta=0.05)
+    art, ex = off.train(cl, dt=2e-3, nsnap=12, M=4, Mr=8, ns=8, depth=6, pc=1.0)
+    assert art["A"].shape == (8, 16) and art["Phibar"].shape == (16, 4)
+    out = oracle.Rom(art).run(12, tol=1e-4)
+    assert out["status"] == 0
+    assert np.all(np.isfinite(out["hist"]))
