@@ -1,0 +1,334 @@
+#!/usr/bin/env python3
+"""Benchmark of the regularized Biot-Savart hot path on one MI355X.
+
+Timed step (Gaussian vortex patch, N = 65536, sigma 0.25,
+Gamma_i = exp(-|x_i|^2/0.1)/N, delta = 0.01): one velocity evaluation, eight
+Jacobian-vector products with random unit vectors, then 50 backward-Euler
+steps (dt 5e-4) solved by Newton-GMRES over the Jacobian-product kernel.  The
+state is reset at the start of every step so each step does the same work.
+
+value = pair interactions evaluated in the timed steps (velocity and
+Jacobian-product kernels, N(N-1) per evaluation) / timed wall time.
+
+Also reported ("forms"): the batched persistent stepper (256 instances,
+20 RK4 steps), the checkpointed adjoint (N = 131072, 200 RK4 steps, forward
++ backward) and the online PTROM step, each as pair interactions per second
+on the same GPU; "roofline" for the dominant kernel (the Jacobian product);
+"cpu_baseline" = the FP64 oracle timed on a bounded sample on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic FP32 work per pair interaction (FMA = 2, reciprocal = 1), counted
+# from the formulas the kernels evaluate
+FLOP_PER_PAIR = {"velocity": 12, "jvp": 28, "vjp": 36, "block_jacobian": 22}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--no-forms", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,rom)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2103_01983_amd import native
+    from paper_2103_01983_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = W.CONFIGS["c2_gaussian_patch"]
+    cl = W.config_cloud("c2_gaussian_patch")
+    n = cl.n
+    x0 = torch.tensor(cl.xy, dtype=torch.float32, device=dev)
+    g = torch.tensor(cl.gamma, dtype=torch.float32, device=dev)
+    V = torch.tensor(W.unit_vectors(n, cfg["njvp"], 1002), dtype=torch.float32, device=dev)
+    x = x0.clone()
+    f = torch.empty_like(x0)
+    jv = torch.empty_like(x0)
+    d, dt = float(cl.delta), float(cfg["dt"])
+    pairs = float(n) * (n - 1)
+    stream = torch.cuda.current_stream(dev)
+
+    timings = {"velocity": [], "jvp": []}
+    counts = {"vel": 0, "jvp": 0, "newton": 0}
+
+    def step(record):
+        x.copy_(x0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        native.velocity(x, g, d, out=f)
+        e1.record(stream)
+        ev = []
+        for k in range(cfg["njvp"]):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            native.jvp(x, g, d, V[k], out=jv)
+            b.record(stream)
+            ev.append((a, b))
+        st = native.implicit(x, g, d, dt, cfg["steps"])
+        if record:
+            torch.cuda.synchronize()
+            timings["velocity"].append(e0.elapsed_time(e1))
+            timings["jvp"].extend(a.elapsed_time(b) for a, b in ev)
+            counts["vel"] += 1 + cfg["steps"] + st.newton_iters
+            counts["jvp"] += cfg["njvp"] + st.krylov_iters
+            counts["newton"] += st.newton_iters
+        return st
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("timed steps", args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_pairs = pairs * (counts["vel"] + counts["jvp"])
+    value = total_pairs / wall
+    ms_step = 1e3 * wall / args.steps
+
+    jvp_ms = float(np.mean(timings["jvp"]))
+    vel_ms = float(np.mean(timings["velocity"]))
+    roof = {
+        "bound": "alu",
+        "kernel": "pair_kernel<jvp> (Jacobian-vector product, N=65536)",
+        "achieved": FLOP_PER_PAIR["jvp"] * pairs / (jvp_ms * 1e-3) / 1e12,
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "avg_launch_ms": jvp_ms,
+        "flop_per_pair": FLOP_PER_PAIR["jvp"],
+        "traffic": None,
+    }
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic_for("jvp")
+    roof_vel = {
+        "kernel": "pair_kernel<velocity> (N=65536)",
+        "achieved": FLOP_PER_PAIR["velocity"] * pairs / (vel_ms * 1e-3) / 1e12,
+        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "avg_launch_ms": vel_ms,
+        "pairs_per_s": pairs / (vel_ms * 1e-3), "flop_per_pair": FLOP_PER_PAIR["velocity"],
+    }
+    roof_vel["frac"] = roof_vel["achieved"] / roof_vel["peak"]
+
+    out = {
+        "metric": "Biot-Savart pair-interactions/s at <=1e-5 rel err; batched & adjoint vs plain",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gaussian_patch_n65536: velocity + 8 JVP + 50 backward-Euler Newton-GMRES steps",
+                   "N": n, "delta": d, "dt": dt, "be_steps": cfg["steps"], "jvp_vectors": cfg["njvp"],
+                   "velocity_evals_per_step": counts["vel"] / args.steps,
+                   "jvp_evals_per_step": counts["jvp"] / args.steps,
+                   "newton_iters_per_step": counts["newton"] / args.steps},
+        "roofline": roof,
+        "roofline_velocity": roof_vel,
+    }
+
+    if not args.no_forms:
+        only = set(s for s in args.only.split(",") if s)
+        out["forms"] = run_forms(native, W, dev, only, pairs / (vel_ms * 1e-3))
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cl, f, native, x0, g, d)
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    from hashlib import sha256
+    src = os.path.join(ROOT, "paper_2103_01983_amd", "csrc", "pair_core.h")
+    with open(src, "rb") as fh:
+        h = sha256(fh.read()).hexdigest()[:16]
+    ent = t.get(kernel)
+    if not ent or ent.get("source_sha") != h:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_forms(native, W, dev, only, plain_pairs_per_s):
+    import torch
+    forms = {"plain_velocity_pairs_per_s": plain_pairs_per_s}
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps=1):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+
+    if not only or "batched" in only:
+        log("form: batched")
+        bt = W.batched_patches()
+        c4 = W.CONFIGS["c4_batched"]
+        xb0 = torch.tensor(bt.xy, dtype=torch.float32, device=dev)
+        gb = torch.tensor(bt.gamma, dtype=torch.float32, device=dev)
+        xb = xb0.clone()
+        nb = np.diff(bt.offsets).astype(np.float64)
+        pairs_eval = float(np.sum(nb * (nb - 1)))
+        native.rk4_batched(bt.offsets, xb, gb, bt.delta, c4["dt"], 1)  # plan + graph
+        xb.copy_(xb0)
+        sec = timed(lambda: native.rk4_batched(bt.offsets, xb, gb, bt.delta, c4["dt"], c4["steps"]))
+        forms["batched"] = {"instances": int(nb.size), "bodies": int(nb.sum()), "rk4_steps": c4["steps"],
+                            "seconds": sec, "pairs_per_s": 4 * c4["steps"] * pairs_eval / sec,
+                            "ratio_to_plain": 4 * c4["steps"] * pairs_eval / sec / plain_pairs_per_s}
+        xb.copy_(xb0)
+        sec1 = timed(lambda: native.velocity_batched(bt.offsets, xb, gb, bt.delta), reps=3)
+        forms["batched"]["velocity_eval_pairs_per_s"] = pairs_eval / sec1
+        del xb0, xb, gb
+
+    if not only or "adjoint" in only:
+        log("form: adjoint")
+        c5 = W.CONFIGS["c5_adjoint"]
+        cl = W.config_cloud("c5_adjoint")
+        n = cl.n
+        x0 = torch.tensor(cl.xy, dtype=torch.float32, device=dev)
+        g = torch.tensor(cl.gamma, dtype=torch.float32, device=dev)
+        steps, every, dt, d = c5["steps"], c5["every"], c5["dt"], cl.delta
+        pairs = float(n) * (n - 1)
+        holder = {}
+
+        def fwd():
+            holder["ck"], holder["xT"] = native.rk4_fwd_ckpt(x0, g, d, dt, steps, every)
+
+        sec_f = timed(fwd)
+        lamT = torch.ones_like(x0)
+
+        def bwd():
+            native.rk4_bwd(holder["ck"], g, d, dt, steps, every, lamT)
+
+        sec_b = timed(bwd)
+        forms["adjoint"] = {"N": n, "rk4_steps": steps, "checkpoint_every": every,
+                            "forward_seconds": sec_f, "backward_seconds": sec_b,
+                            "forward_pairs_per_s": 4 * steps * pairs / sec_f,
+                            "backward_pairs_per_s": 4 * steps * 2 * pairs / sec_b,
+                            "backward_over_forward_time": sec_b / sec_f,
+                            "note": "backward = recompute (velocity) + vector-Jacobian pair kernels"}
+        del holder
+
+    if not only or "rom" in only:
+        log("form: rom")
+        try:
+            forms["rom"] = rom_form(native, W, dev, timed)
+        except Exception as e:  # reported, not fatal to the headline line
+            forms["rom"] = {"error": repr(e)}
+    return forms
+
+
+def rom_form(native, W, dev, timed):
+    import torch
+    from paper_2103_01983_amd import offline
+    c3 = W.CONFIGS["c3_ptrom_pipeline"]
+    cl = W.config_cloud("c3_ptrom_pipeline")
+    t0 = time.perf_counter()
+    art, info = offline.train(cl, dt=c3["dt"], nsnap=c3["snapshots"], M=c3["M"], Mr=c3["Mr"], ns=c3["ns"],
+                              depth=c3["depth"], pc=c3["pc"], tol=c3["tol"], max_iter=c3["max_iter"], device=dev)
+    t_off = time.perf_counter() - t0
+    rom = native.Rom(art, tol=c3["tol"], max_iter=c3["max_iter"])
+    steps = c3["steps"]
+    xh = torch.zeros(art["M"], dtype=torch.float64, device=dev)
+    hist = torch.empty(steps * art["M"], dtype=torch.float64, device=dev)
+    it = torch.empty(steps, dtype=torch.int32, device=dev)
+    rom.run(2, xh, None, None)
+    xh.zero_()
+    sec = timed(lambda: rom.run(steps, xh, hist, it))
+    its = it.cpu().numpy()
+    nnz = int(np.asarray(art["ids"]).size)
+    res = {"N": cl.n, "M": art["M"], "Mr": art["Mr"], "ns": int(len(art["off"]) - 1), "Nc": int(np.asarray(art["Gt"]).size),
+           "nnz": nnz, "steps": steps, "offline_seconds": t_off, "online_seconds": sec,
+           "us_per_step": 1e6 * sec / steps, "us_per_gn_iteration": 1e6 * sec / max(int(its.sum()), 1),
+           "mean_gn_iterations": float(its.mean()), "pairs_per_s": float(its.sum()) * nnz / sec}
+    res.update(info.get("report", {}))
+    # accuracy against the trapezoid FOM snapshots (reported, not a gate)
+    Phi, S = info["Phi"], info["S"]
+    x0 = np.asarray(cl.xy, np.float32).astype(np.float64)
+    n = cl.n
+    length = float(np.hypot(x0[n - 1] - x0[0], x0[2 * n - 1] - x0[n]))
+    xr = x0[None, :] + hist.cpu().numpy().reshape(steps, -1) @ Phi.T
+    mae = [offline.mae_distance(xr[t], S[t], n, length) for t in range(min(steps, S.shape[0]))]
+    res["mae_d_time_avg"] = float(np.mean(mae))
+    res["mae_d_final"] = float(mae[-1])
+    res["final_rel_state_err"] = float(np.linalg.norm(xr[-1] - S[-1]) / np.linalg.norm(S[-1] - x0))
+    return res
+
+
+def cpu_baseline(cl, f_gpu, native, x0, g, d):
+    """FP64 oracle on a bounded sample of targets of the same workload: pair
+    interactions/s on the host cores.  Also the GPU result's relative error on
+    that sample."""
+    import oracle
+    n = cl.n
+    xy32 = np.asarray(cl.xy, np.float32).astype(np.float64)
+    g32 = np.asarray(cl.gamma, np.float32).astype(np.float64)
+    d32 = float(np.float32(d))
+    rng = np.random.default_rng(7)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # size the sample for ~10-20 s of oracle work
+    probe = rng.choice(n, 64, replace=False)
+    t = time.perf_counter()
+    oracle.velocity_at(xy32, g32, d32, probe)
+    tp = max(time.perf_counter() - t, 1e-4)
+    ns = int(min(n, max(64, 64 * 12.0 / tp)))
+    idx = rng.choice(n, ns, replace=False)
+    t = time.perf_counter()
+    ref = oracle.velocity_at(xy32, g32, d32, idx)
+    sec = time.perf_counter() - t
+    f = f_gpu.double().cpu().numpy()
+    got = np.concatenate([f[idx], f[n + idx]])
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return {"value": ns * (n - 1) / sec, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle velocity at %d random targets of the N=65536 Gaussian patch (all sources)" % ns,
+            "seconds": sec, "gpu_rel_err_on_sample": err}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,300 @@
+/*
+ * ptrom.h - C ABI of libptrom: the regularized 2D Biot-Savart pair sum, its
+ * Jacobian products and adjoint, explicit and implicit time steppers, a
+ * batched multi-instance stepper, a checkpointed RK4 adjoint, and the online
+ * step of the projection-tree reduced-order model (PTROM) of
+ * Rodriguez et al., "Projection-tree reduced order modeling for fast N-body
+ * computations" (arXiv 2103.01983), on AMD MI355X (gfx950).
+ *
+ * Notation follows the paper:
+ *   N bodies with positions chi_i (x) and psi_i (y) and circulations Gamma_i.
+ *   State vector layout (problem formulation, state-vector definition):
+ *       xy[0..N) = x_0..x_{N-1},  xy[N..2N) = y_0..y_{N-1}     ("SoA")
+ *   Velocity (kernel equation; target-source form f = K gamma):
+ *       f_i = sum_{j != i} Gamma_j / (2 pi) * (-r_y, r_x) / (|r|^2 + delta^2),
+ *       r = x_i - x_j  (target minus source).
+ *   delta is the de-singularisation core; it enters squared (delta is a
+ *   length).  delta = 0 is legal: self pairs are excluded by index, but two
+ *   distinct coincident bodies then give non-finite values (not checked).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers owned by the caller unless the
+ *     comment says "host".  The library never keeps a caller pointer after
+ *     the call returns (ptrom_rom_create copies what it needs).
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *     = the null stream) unless documented as synchronising.
+ *   - A context owns a grow-only device workspace; calls made through one
+ *     context must not run concurrently (use one context per stream/thread).
+ *   - Return value: PTROM_OK (0) on success; PTROM_ENOCONV (1) is a warning
+ *     (an iteration cap was hit, results are still written); negative values
+ *     are errors, with a message from ptrom_last_error().  Arguments are
+ *     validated before anything is launched: N >= 1 and N <= 2^30,
+ *     delta >= 0, dt > 0, nsteps >= 0, non-NULL required pointers, else
+ *     PTROM_EINVAL and nothing is written.
+ */
+#ifndef PTROM_H
+#define PTROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptrom_ctx ptrom_ctx;
+typedef struct ptrom_rom ptrom_rom;
+typedef void *ptrom_stream; /* hipStream_t */
+
+enum {
+  PTROM_OK = 0,
+  PTROM_ENOCONV = 1,
+  PTROM_EINVAL = -1,
+  PTROM_ENOMEM = -2,
+  PTROM_EHIP = -3
+};
+
+/* Implicit one-step schemes of the linear multistep residual (eq. "linKstep"
+ * with k = 1): backward Euler (alpha0 = 1, alpha1 = -1, beta0 = 1,
+ * beta1 = 0) and the trapezoid rule the paper uses (beta0 = beta1 = 1/2). */
+enum { PTROM_BACKWARD_EULER = 0, PTROM_TRAPEZOID = 1 };
+
+/* HyperPair Jacobian: PAPER = the paper's inexact Jacobian (only the 2x2
+ * derivative of each sampled velocity with respect to its own target
+ * position, Section "Problem formulation" and Algorithm "HyperPair");
+ * EXACT = also differentiates the surrogate-source positions. */
+enum { PTROM_JAC_PAPER = 0, PTROM_JAC_EXACT = 1 };
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ptrom_version(void);
+
+/* Create a context bound to HIP device `device`; loads tuned launch
+ * parameters from the file named by the environment variable
+ * PTROM_TUNE_CACHE if it exists.  *out is set only on success. */
+int ptrom_create(ptrom_ctx **out, int device);
+/* Free a context and its workspace (synchronises the device). NULL is a no-op. */
+void ptrom_destroy(ptrom_ctx *ctx);
+/* Message of the last error on this context ("" if none). The pointer stays
+ * valid until the next call on the context. */
+const char *ptrom_last_error(const ptrom_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Pair sums (kernel equation and its derivatives).  FP32 arithmetic with
+ * two-level compensated (Kahan) accumulation over sources.
+ * ---------------------------------------------------------------------- */
+
+/* f[2N] = velocity of every body (SoA). Kernel equation ("BS_kernel"). */
+int ptrom_velocity(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
+                   float *f, ptrom_stream stream);
+
+/* FP64 version of ptrom_velocity (plain double sums, IEEE division). */
+int ptrom_velocity_f64(ptrom_ctx *ctx, int64_t n, const double *xy, const double *gamma,
+                       double delta, double *f, ptrom_stream stream);
+
+/* Jacobian-vector product jv = (df/dx) v, v and jv [2N] SoA:
+ *   (Jv)_i = sum_{j != i} Gamma_j/(2pi) H(r_ij) (v_i - v_j),
+ *   H(r) = d/dr[(-r_y, r_x)/s] = (1/s^2) [[2 r_x r_y, r_y^2 - r_x^2 - delta^2],
+ *                                         [r_y^2 - r_x^2 + delta^2, -2 r_x r_y]],
+ *   s = |r|^2 + delta^2.  Used by implicit (LSPG/Newton) residual Jacobians
+ *   (Section "Least-Squares Petrov-Galerkin projection"). */
+int ptrom_jvp(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
+              const float *v, float *jv, ptrom_stream stream);
+
+/* Per-body 2x2 self blocks B_i = sum_{j != i} Gamma_j/(2pi) H(r_ij), the
+ * paper's inexact "diagonal block" kernel Jacobian (problem formulation).
+ * Output B[4][N]: B00, B01, B10, B11 planes (B11 = -B00). */
+int ptrom_block_jacobian(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma,
+                         float delta, float *B, ptrom_stream stream);
+
+/* Adjoint (vector-Jacobian product) for a cotangent w [2N]:
+ *   gxy[2N]    = (df/dx)^T w,  (J^T w)_k = sum_{j != k} H(r_kj)^T (G_j w_k - G_k w_j)/(2pi)
+ *   ggamma[N]  = d(w.f)/dGamma_k = (1/2pi) sum_{i != k} w_i . (-r_y, r_x)/s, r = x_i - x_k. */
+int ptrom_vjp(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
+              const float *w, float *gxy, float *ggamma, ptrom_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Time steppers.
+ * ---------------------------------------------------------------------- */
+
+/* nsteps classic RK4 steps of dx/dt = f(x) in place on xy[2N]. */
+int ptrom_rk4(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta, float dt,
+              int nsteps, ptrom_stream stream);
+
+/* FP64 RK4 (uses ptrom_velocity_f64). */
+int ptrom_rk4_f64(ptrom_ctx *ctx, int64_t n, double *xy, const double *gamma, double delta,
+                  double dt, int nsteps, ptrom_stream stream);
+
+typedef struct {
+  double newton_tol;  /* stop when |r(xi)| <= newton_tol * |r(x_prev)| (default 1e-6) */
+  int32_t max_newton; /* Newton iterations per step (default 20) */
+  int32_t gmres_restart; /* Krylov basis size (default 20) */
+  int32_t gmres_maxit;   /* matvecs per Newton iteration (default 60) */
+  int32_t pad;
+  double gmres_tol;   /* relative residual of each Newton linear solve (default 1e-3) */
+} ptrom_newton_opts;
+
+typedef struct {
+  int32_t newton_iters; /* total over all steps */
+  int32_t krylov_iters; /* total Jacobian products */
+  int32_t nonconverged_steps;
+  int32_t pad;
+  double max_final_rel_residual; /* max over steps of |r_final| / |r_0| */
+} ptrom_newton_stats;
+
+/* nsteps implicit steps (scheme = PTROM_BACKWARD_EULER or PTROM_TRAPEZOID) of
+ * the k=1 linear multistep residual, each solved by Newton's method whose
+ * linear systems (I - dt beta0 J) d = -r are solved matrix-free by restarted
+ * GMRES over ptrom_jvp.  The unknown is the increment xi - x_prev.
+ * opts may be NULL (defaults).  stats may be NULL.  SYNCHRONISES the stream
+ * (host-side Krylov scalars).  Returns PTROM_ENOCONV if a step hit max_newton. */
+int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
+                   float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
+                   ptrom_newton_stats *stats, ptrom_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Batched parametric instances: nb independent systems in one persistent
+ * launch per velocity evaluation.
+ *   offsets (host) [nb+1]: instance b owns bodies offsets[b]..offsets[b+1]-1;
+ *   xy: instance b's SoA block [x..., y...] occupies xy[2*offsets[b] .. 2*offsets[b+1]);
+ *   gamma[offsets[nb]]; delta (host) [nb] per-instance cores.
+ * ---------------------------------------------------------------------- */
+int ptrom_velocity_batched(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float *xy,
+                           const float *gamma, const float *delta, float *f, ptrom_stream stream);
+
+/* nsteps RK4 steps for every instance, captured once into a HIP graph and
+ * replayed (use_graph = 0 launches the same kernels directly). */
+int ptrom_rk4_batched(ptrom_ctx *ctx, int nb, const int64_t *offsets, float *xy,
+                      const float *gamma, const float *delta, float dt, int nsteps,
+                      int use_graph, ptrom_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Discrete RK4 adjoint with step checkpointing.
+ * ---------------------------------------------------------------------- */
+
+/* Forward: nsteps RK4 steps from xy0; stores the state at steps
+ * 0, every, 2*every, ... into ckpt[ceil(nsteps/every)][2N] and x(T) in xyT. */
+int ptrom_rk4_fwd_ckpt(ptrom_ctx *ctx, int64_t n, const float *xy0, const float *gamma,
+                       float delta, float dt, int nsteps, int every, float *ckpt, float *xyT,
+                       ptrom_stream stream);
+
+/* Backward: given lamT = dQ/dx(T) [2N] and optionally the direct partial
+ * ggamma_direct = dQ/dGamma at fixed x(T) [N] (may be NULL), writes
+ * lam0 = dQ/dx(0) [2N] and ggamma = total dQ/dGamma [N] for the discrete RK4
+ * map, recomputing each segment's stage inputs from its checkpoint. */
+int ptrom_rk4_bwd(ptrom_ctx *ctx, int64_t n, const float *ckpt, const float *gamma, float delta,
+                  float dt, int nsteps, int every, const float *lamT, const float *ggamma_direct,
+                  float *lam0, float *ggamma, ptrom_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Online PTROM (Algorithms "Gauss-Newton" and "HyperPair").
+ * ---------------------------------------------------------------------- */
+
+/* Offline artifacts, all HOST arrays (copied by ptrom_rom_create).
+ * Sampled rows are ordered [chi of the ns sampled bodies, psi of them]. */
+typedef struct {
+  int32_t M;        /* state POD rank */
+  int32_t Mr;       /* residual POD rank (rows of A) */
+  int32_t ns;       /* sampled bodies; nd = 2*ns sampled rows */
+  int32_t jac_mode; /* PTROM_JAC_PAPER or PTROM_JAC_EXACT */
+  int64_t Nc;       /* unique surrogate sources (clusters and single bodies) */
+  int64_t nnz;      /* total entries of the interaction lists */
+  const double *Phibar; /* [nd][M]  rows of Phi at the sampled rows */
+  const double *xbar0;  /* [nd]     x^0 at the sampled rows */
+  const double *xqt0;   /* [Nc][2]  surrogate reference positions */
+  const double *Phit;   /* [Nc][2][M] surrogate POD rows (Phi tilde) */
+  const double *Gt;     /* [Nc]     surrogate circulations (Gamma tilde) */
+  const int64_t *off;   /* [ns+1]   CSR offsets of each sampled target's list */
+  const int64_t *ids;   /* [nnz]    surrogate ids in [0, Nc); a target's own body never appears */
+  const double *A;      /* [Mr][nd] gappy operator [P Phi_r]^+ */
+  double delta, dt;
+  double tol;           /* relative reduced-gradient tolerance */
+  double alpha;         /* Gauss-Newton step length (the paper uses 1) */
+  int32_t max_iter;     /* Gauss-Newton iterations per step (the paper caps at 100) */
+  int32_t pad;
+} ptrom_rom_desc;
+
+/* Copy the artifacts to the device (surrogate and sampled rows as FP32 for
+ * the gather, A as FP64 for the least-squares solve).  Requires
+ * 1 <= M <= 32, M <= Mr <= 64, 1 <= ns <= 2^20, ids in [0, Nc). */
+int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptrom_rom **out);
+void ptrom_rom_destroy(ptrom_rom *rom);
+
+/* One HyperPair evaluation at xhat (device FP64 [M]) with previous-step
+ * terms xbar_prev, fbar_prev (device FP64 [nd]); writes sampled positions
+ * xbar, velocities fbar, trapezoid residual rows rbar ([nd] FP64) and the
+ * residual Jacobian times Phibar, C ([nd][M] FP64).  Any output may be NULL. */
+int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const double *xbar_prev,
+                        const double *fbar_prev, double *xbar, double *fbar, double *rbar,
+                        double *C, ptrom_stream stream);
+
+/* nsteps online time steps in one device-resident launch, starting from
+ * xhat (device FP64 [M], updated in place).  Per step: Gauss-Newton
+ * iterations of HyperPair + FP64 Householder least squares
+ * dxhat = -argmin |A C nu + A rbar|, xhat += alpha dxhat, until the relative
+ * reduced gradient |(AC)^T A rbar| / (its first-iteration value) <= tol or
+ * max_iter iterations.  xhat_hist (device [nsteps][M]) and iters (device
+ * int32 [nsteps]) may be NULL.  Asynchronous; iteration caps are reported in
+ * iters only. */
+int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, int32_t *iters,
+                  ptrom_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Offline training helpers (training hierarchy, Stages 2-3).
+ * ---------------------------------------------------------------------- */
+
+typedef struct ptrom_clusters ptrom_clusters;
+
+/* Host-side (no GPU) quadtree over the weighted POD points and per-target
+ * neighbour-search clustering (Algorithms "ClusterPOD" and "checkPrune").
+ * All arrays are HOST memory:
+ *   wpts [n][2]  each body's point in W_phi = Phi Sigma_hat ((Phi s)_i, (Phi s)_{i+n});
+ *   xy0 [2n]     reference state x^0 (SoA);  phi [2n][M] POD basis, row-major;
+ *   gamma [n];   max_level = depth cap of the tree (root = level 0);
+ *   pc >= 0      neighbourhood factor (Def. 2); INFINITY prunes nothing;
+ *   targets [nt] body ids whose interaction lists are built.
+ * Readings of the open passages: root = tight bounding box; midpoint splits
+ * while a cell holds > 1 body and is above max_level; half-open membership;
+ * width = longer side; |Gamma|-weighted means, strength = sum of Gamma; a
+ * cell holding the target is never pruned; an unpruned leaf expands into its
+ * bodies minus the target.  Unique surrogates: single bodies first (by id),
+ * then cells (by level, row, column); every list is sorted by surrogate id.
+ * The result object owns its arrays; read them with ptrom_cluster_fetch. */
+int ptrom_cluster_build(int64_t n, const double *wpts, const double *xy0, const double *phi, int M,
+                        const double *gamma, int max_level, double pc, int64_t nt,
+                        const int64_t *targets, ptrom_clusters **out);
+int ptrom_cluster_sizes(const ptrom_clusters *c, int64_t *nc, int64_t *nnz);
+/* Copies into caller HOST buffers (any may be NULL): xqt0 [Nc][2], phit
+ * [Nc][2][M], gt [Nc], off [nt+1], ids [nnz], keys [Nc] (body id, or
+ * 2^60 | level<<40 | row<<20 | column for a cell). */
+int ptrom_cluster_fetch(const ptrom_clusters *c, double *xqt0, double *phit, double *gt, int64_t *off,
+                        int64_t *ids, int64_t *keys);
+void ptrom_cluster_destroy(ptrom_clusters *c);
+
+/* FP64 Gram matrix G = X X^T of k device rows X [k][nd] (row-major);
+ * G [k][k] device.  Used for the POD by the method of snapshots. */
+int ptrom_gram_f64(ptrom_ctx *ctx, int64_t nd, int k, const double *X, double *G, ptrom_stream stream);
+
+/* FP64 combination Y = T^T X: Y [M][nd] = sum_a T[a][m] X[a][q] with X [k][nd],
+ * T [k][M] (device).  Forms the basis from snapshots and applies R^{-1} in
+ * the CholeskyQR re-orthogonalisation. */
+int ptrom_combine_f64(ptrom_ctx *ctx, int64_t nd, int k, const double *X, int M, const double *T,
+                      double *Y, ptrom_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Launch-parameter autotuning.
+ * ---------------------------------------------------------------------- */
+
+/* Time the candidate launch configurations of the pair kernels on this
+ * device at a set of sizes, keep the fastest per (operation, size class) in
+ * the context and, if cache_path is not NULL, write them there (text).
+ * SYNCHRONISES; allocates temporary device buffers. */
+int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path);
+
+/* Load tuned parameters written by ptrom_autotune. */
+int ptrom_load_tuning(ptrom_ctx *ctx, const char *cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTROM_H */

@@ -1,0 +1,265 @@
+// Implicit one-step schemes of the linear multistep residual (eq. "linKstep"
+// with k = 1): r(xi) = xi - x_prev - dt (beta0 f(xi) + beta1 f(x_prev)).
+// Newton's method on the increment D = xi - x_prev (keeps the small
+// difference out of FP32 cancellation), each Newton system
+// (I - dt beta0 J(xi)) d = -r solved by restarted GMRES whose matrix-vector
+// products are the Jacobian-product pair kernel.  Krylov vectors live in
+// HBM (FP32); dot products accumulate in FP64 on the device; the small
+// Hessenberg least-squares problem is solved on the host in FP64.
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ptrom;
+
+namespace {
+
+// out = a + b
+__global__ void add_kernel(int64_t m, float *__restrict__ out, const float *__restrict__ a,
+                           const float *__restrict__ b) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) out[q] = a[q] + b[q];
+}
+
+// r = D - dt (b0 f + b1 fp)
+__global__ void residual_kernel(int64_t m, float *__restrict__ r, const float *__restrict__ D,
+                                const float *__restrict__ f, const float *__restrict__ fp, float dtb0,
+                                float dtb1) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) r[q] = D[q] - (dtb0 * f[q] + dtb1 * fp[q]);
+}
+
+// out[v] = sum_q X_v[q] * y[q] for v < nvec; one workgroup per vector, FP64.
+__global__ void __launch_bounds__(1024)
+    multi_dot_kernel(int64_t m, const float *__restrict__ X, int64_t ldx, const float *__restrict__ y,
+                     double *__restrict__ out) {
+  __shared__ double red[1024];
+  const float *x = X + (size_t)blockIdx.x * ldx;
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += blockDim.x) s += (double)x[q] * (double)y[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// y -= sum_v c[v] X_v  (c on the device), or y = scale * y + sum_v c[v] X_v when accumulate.
+__global__ void multi_axpy_kernel(int64_t m, int nvec, const float *__restrict__ X, int64_t ldx,
+                                  const double *__restrict__ c, float sign, float *__restrict__ y) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  double s = 0.0;
+  for (int v = 0; v < nvec; ++v) s += c[v] * (double)X[(size_t)v * ldx + q];
+  y[q] = (float)((double)y[q] + sign * s);
+}
+
+__global__ void scale_kernel(int64_t m, float *__restrict__ out, const float *__restrict__ x, float a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) out[q] = a * x[q];
+}
+
+__global__ void lincomb_kernel(int64_t m, float *__restrict__ out, const float *__restrict__ v,
+                               float c, const float *__restrict__ w) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) out[q] = v[q] - c * w[q];
+}
+
+inline dim3 g1(int64_t m) { return dim3((unsigned)((m + 255) / 256)); }
+
+struct Solver {
+  ptrom_ctx *ctx;
+  hipStream_t st;
+  int64_t n, m;
+  const float *gamma;
+  float delta;
+  PairCfg jcfg;
+  float *pws;
+  size_t pwsf;
+  float *xi, *tmp, *w, *V;
+  double *dev_dots, *host_dots;
+  int restart;
+
+  // w = (I - c J(xi)) v
+  int apply(const float *v, float c, float *out) {
+    hipError_t e = launch_pair(OP_JVP, jcfg, ctx->num_cus, n, xi, gamma, v, delta, tmp, nullptr,
+                               pws, pwsf, st);
+    if (e != hipSuccess) return ctx->hip_fail(e, "jvp");
+    hipLaunchKernelGGL(lincomb_kernel, g1(m), dim3(256), 0, st, m, out, v, c, tmp);
+    return PTROM_OK;
+  }
+
+  int dots(const float *X, int nvec, const float *y, double *host) {
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(nvec), dim3(1024), 0, st, m, X, m, y, dev_dots);
+    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(host, dev_dots, sizeof(double) * nvec, hipMemcpyDeviceToHost, st));
+    PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
+    return PTROM_OK;
+  }
+
+  int norm(const float *y, double *out) {
+    double h;
+    if (int rc = dots(y, 1, y, &h)) return rc;
+    *out = std::sqrt(h);
+    return PTROM_OK;
+  }
+
+  // Solve (I - c J) d = b from d = 0 to relative tolerance rtol; returns matvecs in *used.
+  int gmres(const float *b, float *d, float c, double rtol, int maxit, int *used) {
+    *used = 0;
+    double bn;
+    if (int rc = norm(b, &bn)) return rc;
+    hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, d, b, 0.0f);
+    if (bn == 0.0) return PTROM_OK;
+    std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
+    std::vector<double> h1(restart + 1), h2(restart + 1);
+    bool first = true;
+    while (*used < maxit) {
+      // V0 = residual / |residual|
+      double beta;
+      if (first) {
+        beta = bn;
+        hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V, b, float(1.0 / beta));
+        first = false;
+      } else {
+        if (int rc = apply(d, c, w)) return rc;
+        ++*used;
+        hipLaunchKernelGGL(lincomb_kernel, g1(m), dim3(256), 0, st, m, w, b, 1.0f, w);  // w = b - A d
+        if (int rc = norm(w, &beta)) return rc;
+        if (beta <= rtol * bn) break;
+        hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V, w, float(1.0 / beta));
+      }
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int k = 0;
+      bool done = false;
+      for (; k < restart && *used < maxit; ++k) {
+        float *vk = V + (size_t)k * m;
+        if (int rc = apply(vk, c, w)) return rc;
+        ++*used;
+        // classical Gram-Schmidt, applied twice
+        if (int rc = dots(V, k + 1, w, h1.data())) return rc;
+        PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dev_dots, h1.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, dev_dots, -1.0f, w);
+        if (int rc = dots(V, k + 1, w, h2.data())) return rc;
+        PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dev_dots, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, dev_dots, -1.0f, w);
+        double hn;
+        if (int rc = norm(w, &hn)) return rc;
+        for (int i = 0; i <= k; ++i) H[i * restart + k] = h1[i] + h2[i];
+        H[(k + 1) * restart + k] = hn;
+        if (hn > 0.0)
+          hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V + (size_t)(k + 1) * m, w, float(1.0 / hn));
+        for (int i = 0; i < k; ++i) {
+          const double a = H[i * restart + k], bb = H[(i + 1) * restart + k];
+          H[i * restart + k] = cs[i] * a + sn[i] * bb;
+          H[(i + 1) * restart + k] = -sn[i] * a + cs[i] * bb;
+        }
+        const double a = H[k * restart + k], bb = H[(k + 1) * restart + k];
+        const double rr = std::sqrt(a * a + bb * bb);
+        cs[k] = rr == 0.0 ? 1.0 : a / rr;
+        sn[k] = rr == 0.0 ? 0.0 : bb / rr;
+        H[k * restart + k] = rr;
+        H[(k + 1) * restart + k] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        if (std::fabs(g[k + 1]) <= rtol * bn || hn == 0.0) {
+          ++k;
+          done = true;
+          break;
+        }
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < k; ++j) s -= H[i * restart + j] * y[j];
+        y[i] = s / H[i * restart + i];
+      }
+      PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dev_dots, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k, V, m, dev_dots, 1.0f, d);
+      PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));  // dev_dots is reused next
+      if (done) break;
+    }
+    return PTROM_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
+                              float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
+                              ptrom_newton_stats *stats, ptrom_stream stream) {
+  if (!ctx) return PTROM_EINVAL;
+  ctx->err.clear();
+  if (n < 1 || n > kMaxN) return ctx->fail(PTROM_EINVAL, "n must be in [1, 2^30]");
+  if (!(delta >= 0.0f) || !(dt > 0.0f) || nsteps < 0) return ctx->fail(PTROM_EINVAL, "bad delta/dt/nsteps");
+  if (!xy || !gamma) return ctx->fail(PTROM_EINVAL, "NULL array");
+  if (scheme != PTROM_BACKWARD_EULER && scheme != PTROM_TRAPEZOID) return ctx->fail(PTROM_EINVAL, "bad scheme");
+  ptrom_newton_opts o{1e-6, 20, 20, 60, 0, 1e-3};
+  if (opts) o = *opts;
+  if (o.gmres_restart < 1 || o.gmres_restart > 200 || o.max_newton < 0 || o.gmres_maxit < 1)
+    return ctx->fail(PTROM_EINVAL, "bad Newton/GMRES options");
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
+  ptrom_newton_stats stl{};
+  const int64_t m = 2 * n;
+  const float b0 = scheme == PTROM_BACKWARD_EULER ? 1.0f : 0.5f;
+  const float b1 = scheme == PTROM_BACKWARD_EULER ? 0.0f : 0.5f;
+  const PairCfg vcfg = ctx->tune.get(OP_VEL, n), jcfg = ctx->tune.get(OP_JVP, n);
+  const size_t pwsf = std::max(pair_ws_floats(OP_VEL, vcfg, ctx->num_cus, n),
+                               pair_ws_floats(OP_JVP, jcfg, ctx->num_cus, n));
+  const int R = o.gmres_restart;
+  const size_t vb = align256(m * sizeof(float));
+  const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (R + 2)) + 512;
+  if (int rc = ctx->reserve(need)) return rc;
+  Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
+  float *xprev = cv.take<float>(m), *D = cv.take<float>(m), *xi = cv.take<float>(m);
+  float *f = cv.take<float>(m), *fp = cv.take<float>(m), *r = cv.take<float>(m);
+  float *tmp = cv.take<float>(m), *d = cv.take<float>(m), *w = cv.take<float>(m);
+  float *V = cv.take<float>(m * (R + 1));
+  float *pws = cv.take<float>(pwsf ? pwsf : 1);
+  double *dd = cv.take<double>(R + 2);
+  if (!w || !V || !pws || !dd) return ctx->fail(PTROM_ENOMEM, "workspace carve");
+  std::vector<double> hd(R + 2);
+  hipStream_t st = (hipStream_t)stream;
+  Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hd.data(), R};
+
+  for (int step = 0; step < nsteps; ++step) {
+    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(xprev, xy, m * sizeof(float), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, D, xprev, 0.0f);
+    hipError_t e = launch_pair(OP_VEL, vcfg, ctx->num_cus, n, xprev, gamma, nullptr, delta, fp, nullptr, pws, pwsf, st);
+    if (e != hipSuccess) return ctx->hip_fail(e, "velocity");
+    double r0 = -1.0, rn = 0.0;
+    int it = 0;
+    for (;; ++it) {
+      hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xi, xprev, D);
+      if (it == 0) {
+        hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, f, fp, 1.0f);
+      } else {
+        e = launch_pair(OP_VEL, vcfg, ctx->num_cus, n, xi, gamma, nullptr, delta, f, nullptr, pws, pwsf, st);
+        if (e != hipSuccess) return ctx->hip_fail(e, "velocity");
+      }
+      hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dt * b0, dt * b1);
+      if (int rc = S.norm(r, &rn)) return rc;
+      if (r0 < 0.0) r0 = rn;
+      if (rn <= o.newton_tol * r0 || r0 == 0.0) break;
+      if (it >= o.max_newton) {
+        stl.nonconverged_steps++;
+        break;
+      }
+      hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, r, r, -1.0f);
+      int used = 0;
+      if (int rc = S.gmres(r, d, dt * b0, o.gmres_tol, o.gmres_maxit, &used)) return rc;
+      stl.krylov_iters += used;
+      hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, D, D, d);
+    }
+    stl.newton_iters += it;
+    const double rel = r0 > 0.0 ? rn / r0 : 0.0;
+    if (rel > stl.max_final_rel_residual) stl.max_final_rel_residual = rel;
+    hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xy, xprev, D);
+  }
+  PTROM_CHECK_HIP(ctx, hipGetLastError());
+  PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
+  if (stats) *stats = stl;
+  return stl.nonconverged_steps ? PTROM_ENOCONV : PTROM_OK;
+}

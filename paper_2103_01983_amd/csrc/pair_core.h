@@ -1,0 +1,193 @@
+// Device-side building blocks of the all-pairs Biot-Savart kernels, shared
+// by the single-system grid kernels and the batched persistent kernel.
+#pragma once
+
+#include "internal.h"
+
+namespace ptrom {
+
+constexpr float kInv2Pi = 0.159154943091895335768883763372514362f;
+
+template <int OP> struct Traits;
+template <> struct Traits<OP_VEL> { static constexpr int NSRC = 3, NTGT = 2, NACC = 2; };
+template <> struct Traits<OP_BJAC> { static constexpr int NSRC = 3, NTGT = 2, NACC = 3; };
+template <> struct Traits<OP_JVP> { static constexpr int NSRC = 5, NTGT = 4, NACC = 2; };
+template <> struct Traits<OP_VJP> { static constexpr int NSRC = 5, NTGT = 5, NACC = 3; };
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
+  const float y = x - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// One target-source interaction.  t: target data (x, y, extras), s: source
+// data (x, y, Gamma, extras), d2 = delta^2.  `self` marks the self pair,
+// whose contribution is forced to zero (only used when MASK).
+template <int OP, bool MASK>
+__device__ __forceinline__ void interact(const float *t, const float *s, float d2, float *acc,
+                                         bool self) {
+  const float dx = t[0] - s[0];
+  const float dy = t[1] - s[1];
+  const float q = fmaf(dx, dx, fmaf(dy, dy, d2));
+  float r = __builtin_amdgcn_rcpf(q);
+  if (MASK) r = self ? 0.0f : r;
+  if constexpr (OP == OP_VEL) {
+    const float g = s[2] * r;
+    acc[0] = fmaf(-dy, g, acc[0]);
+    acc[1] = fmaf(dx, g, acc[1]);
+  } else if constexpr (OP == OP_BJAC) {
+    const float g2 = s[2] * r * r;
+    const float a2 = (dx + dx) * dy;
+    const float dd = fmaf(dy, dy, -dx * dx);
+    acc[0] = fmaf(g2, a2, acc[0]);
+    acc[1] = fmaf(g2, dd - d2, acc[1]);
+    acc[2] = fmaf(g2, dd + d2, acc[2]);
+  } else if constexpr (OP == OP_JVP) {
+    // H (v_i - v_j), H = [[a2, dd - d2], [dd + d2, -a2]] / q^2
+    const float g2 = s[2] * r * r;
+    const float a2 = (dx + dx) * dy;
+    const float dd = fmaf(dy, dy, -dx * dx);
+    const float ex = t[2] - s[3];
+    const float ey = t[3] - s[4];
+    acc[0] = fmaf(g2, fmaf(a2, ex, (dd - d2) * ey), acc[0]);
+    acc[1] = fmaf(g2, fmaf(dd + d2, ex, -a2 * ey), acc[1]);
+  } else {
+    // H^T (Gamma_j w_k - Gamma_k w_j) and the circulation partial
+    // -w_j . (-dy, dx)/q with (dx, dy) = x_k - x_j.
+    const float r2 = r * r;
+    const float a2 = (dx + dx) * dy;
+    const float dd = fmaf(dy, dy, -dx * dx);
+    const float qx = fmaf(s[2], t[2], -t[4] * s[3]);
+    const float qy = fmaf(s[2], t[3], -t[4] * s[4]);
+    acc[0] = fmaf(r2, fmaf(a2, qx, (dd + d2) * qy), acc[0]);
+    acc[1] = fmaf(r2, fmaf(dd - d2, qx, -a2 * qy), acc[1]);
+    acc[2] = fmaf(r, fmaf(s[3], dy, -s[4] * dx), acc[2]);
+  }
+}
+
+template <int OP>
+__device__ __forceinline__ void load_source(int n, int j, const float *__restrict__ xy,
+                                            const float *__restrict__ gam,
+                                            const float *__restrict__ aux, float *s) {
+  s[0] = xy[j];
+  s[1] = xy[n + j];
+  s[2] = gam[j];
+  if constexpr (Traits<OP>::NSRC == 5) {
+    s[3] = aux[j];
+    s[4] = aux[n + j];
+  }
+}
+
+// Final layout of the scaled accumulators of one target.
+template <int OP>
+__device__ __forceinline__ void store_final(int n, int i, const float *v, float *__restrict__ out,
+                                            float *__restrict__ out2) {
+  if constexpr (OP == OP_VEL || OP == OP_JVP) {
+    out[i] = v[0] * kInv2Pi;
+    out[n + i] = v[1] * kInv2Pi;
+  } else if constexpr (OP == OP_BJAC) {
+    out[i] = v[0] * kInv2Pi;
+    out[n + i] = v[1] * kInv2Pi;
+    out[2 * n + i] = v[2] * kInv2Pi;
+    out[3 * n + i] = -v[0] * kInv2Pi;
+  } else {
+    out[i] = v[0] * kInv2Pi;
+    out[n + i] = v[1] * kInv2Pi;
+    out2[i] = v[2] * kInv2Pi;
+  }
+}
+
+
+// Compensated sums over sources [sb, se) for the K targets of this lane
+// (targets tgt0 + k*kBlock + threadIdx.x).  Called by all threads of a
+// workgroup with uniform arguments (LDS staging synchronises the block).
+template <int OP, int K, int STAGING>
+__device__ __forceinline__ void pair_block(int n, const float *__restrict__ xy,
+                                           const float *__restrict__ gam,
+                                           const float *__restrict__ aux, float d2, int tgt0,
+                                           int sb, int se, float *lds,
+                                           float (&res)[K][Traits<OP>::NACC]) {
+  using T = Traits<OP>;
+  constexpr int NS = T::NSRC, NT = T::NTGT, NA = T::NACC;
+  const int tid = threadIdx.x;
+  float tg[K][NT];
+  int ti[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tgt0 + k * kBlock + tid;
+    ti[k] = i;
+    const int ic = i < n ? i : n - 1;
+    tg[k][0] = xy[ic];
+    tg[k][1] = xy[n + ic];
+    if constexpr (OP == OP_JVP || OP == OP_VJP) {
+      tg[k][2] = aux[ic];
+      tg[k][3] = aux[n + ic];
+    }
+    if constexpr (OP == OP_VJP) tg[k][4] = gam[ic];
+  }
+  float sum[K][NA], cmp[K][NA];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sum[k][a] = cmp[k][a] = 0.0f;
+  const int tgt_end = tgt0 + kBlock * K;
+
+  for (int ts = sb; ts < se; ts += kTile) {
+    const int cnt = min(kTile, se - ts);
+    if constexpr (STAGING == STAGE_LDS) {
+      __syncthreads();
+      if (tid < cnt) {
+        float s[NS];
+        load_source<OP>(n, ts + tid, xy, gam, aux, s);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) lds[q * kTile + tid] = s[q];
+      }
+      __syncthreads();
+    }
+    float part[K][NA];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) part[k][a] = 0.0f;
+
+    const bool diag = (ts < tgt_end) && (tgt0 < ts + cnt);
+    if (cnt == kTile && !diag) {
+#pragma unroll 4
+      for (int jj = 0; jj < kTile; ++jj) {
+        float s[NS];
+        if constexpr (STAGING == STAGE_LDS) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q) s[q] = lds[q * kTile + jj];
+        } else {
+          load_source<OP>(n, ts + jj, xy, gam, aux, s);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) interact<OP, false>(tg[k], s, d2, part[k], false);
+      }
+    } else {
+      for (int jj = 0; jj < cnt; ++jj) {
+        float s[NS];
+        if constexpr (STAGING == STAGE_LDS) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q) s[q] = lds[q * kTile + jj];
+        } else {
+          load_source<OP>(n, ts + jj, xy, gam, aux, s);
+        }
+        const int j = ts + jj;
+#pragma unroll
+        for (int k = 0; k < K; ++k) interact<OP, true>(tg[k], s, d2, part[k], j == ti[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) kahan_add(sum[k][a], cmp[k][a], part[k][a]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) res[k][a] = sum[k][a] - cmp[k][a];
+}
+
+}  // namespace ptrom

@@ -1,0 +1,129 @@
+// Launch-parameter autotuner for the pair kernels: times every candidate
+// (source staging x targets per lane x occupancy target) on this device at a
+// ladder of sizes and keeps the fastest per (operation, size class).
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ptrom;
+
+static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp"};
+
+extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
+  if (!ctx || !path) return PTROM_EINVAL;
+  std::ifstream in(path);
+  if (!in) return ctx->fail(PTROM_EINVAL, std::string("cannot open ") + path);
+  std::string line;
+  int loaded = 0;
+  while (std::getline(in, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream ss(line);
+    std::string name;
+    int cls, staging, k, waves;
+    if (!(ss >> name >> cls >> staging >> k >> waves)) continue;
+    int op = -1;
+    for (int q = 0; q < OP_COUNT; ++q)
+      if (name == kOpNames[q]) op = q;
+    if (op < 0 || (k != 1 && k != 2 && k != 4) || (staging != STAGE_LDS && staging != STAGE_SCALAR) ||
+        waves < 1 || waves > 64)
+      continue;
+    PairCfg c;
+    c.staging = staging;
+    c.k = k;
+    c.waves_per_simd = waves;
+    ctx->tune.table[{op, cls}] = c;
+    ++loaded;
+  }
+  return loaded ? PTROM_OK : ctx->fail(PTROM_EINVAL, "no tuning entries");
+}
+
+extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
+  if (!ctx) return PTROM_EINVAL;
+  ctx->err.clear();
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
+  const int64_t sizes[] = {2048, 8192, 32768, 65536, 131072};
+  const int64_t nmax = 131072;
+  // synthetic Gaussian-like cloud: deterministic, no RNG state needed
+  std::vector<float> h(5 * nmax);
+  for (int64_t i = 0; i < nmax; ++i) {
+    const double a = 2.399963229728653 * double(i);  // golden-angle spiral
+    const double rr = 0.5 * std::sqrt((i + 0.5) / double(nmax));
+    h[i] = float(rr * std::cos(a));
+    h[nmax + i] = float(rr * std::sin(a));
+    h[2 * nmax + i] = float(1.0 / nmax);
+    h[3 * nmax + i] = float(std::sin(0.37 * i));
+    h[4 * nmax + i] = float(std::cos(0.11 * i));
+  }
+  float *d = nullptr, *o = nullptr, *o2 = nullptr, *wsb = nullptr;
+  PTROM_CHECK_HIP(ctx, hipMalloc(&d, 5 * nmax * sizeof(float)));
+  hipError_t e = hipMalloc(&o, 4 * nmax * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&o2, nmax * sizeof(float));
+  const size_t wsf = size_t(64) * 3 * nmax;  // generous bound on split partials
+  if (e == hipSuccess) e = hipMalloc(&wsb, wsf * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(d, h.data(), 5 * nmax * sizeof(float), hipMemcpyHostToDevice);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  std::ostringstream report;
+  report << "# op size_class staging k waves_per_simd   (ms)\n";
+  for (int op = 0; op < OP_COUNT && e == hipSuccess; ++op) {
+    for (int64_t n : sizes) {
+      // gather the packed copies for this n
+      std::vector<float> hp(5 * n);
+      for (int c = 0; c < 5; ++c)
+        for (int64_t i = 0; i < n; ++i) hp[c * n + i] = h[c * nmax + (i * (nmax / n))];
+      e = hipMemcpy(d, hp.data(), 5 * n * sizeof(float), hipMemcpyHostToDevice);
+      if (e != hipSuccess) break;
+      const float *xy = d, *gam = d + 2 * n, *aux = d + 3 * n;
+      float best = 1e30f;
+      PairCfg bestc;
+      for (int staging : {STAGE_LDS, STAGE_SCALAR})
+        for (int k : {1, 2, 4})
+          for (int waves : {4, 8, 16}) {
+            PairCfg c;
+            c.staging = staging;
+            c.k = k;
+            c.waves_per_simd = waves;
+            if (pair_ws_floats(op, c, ctx->num_cus, n) > wsf) continue;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+              e = launch_pair(op, c, ctx->num_cus, n, xy, gam, aux, 0.01f, o, o2, wsb, wsf, nullptr);
+            const int reps = n <= 8192 ? 20 : 5;
+            if (e == hipSuccess) e = hipEventRecord(a, nullptr);
+            for (int rep = 0; rep < reps && e == hipSuccess; ++rep)
+              e = launch_pair(op, c, ctx->num_cus, n, xy, gam, aux, 0.01f, o, o2, wsb, wsf, nullptr);
+            if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) break;
+            ms /= reps;
+            if (ms < best) {
+              best = ms;
+              bestc = c;
+            }
+          }
+      if (e != hipSuccess) break;
+      const int cls = size_class(n);
+      ctx->tune.table[{op, cls}] = bestc;
+      report << kOpNames[op] << " " << cls << " " << bestc.staging << " " << bestc.k << " "
+             << bestc.waves_per_simd << "   # " << best << " ms at n=" << n << "\n";
+    }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  hipFree(d);
+  hipFree(o);
+  hipFree(o2);
+  hipFree(wsb);
+  if (e != hipSuccess) return ctx->hip_fail(e, "autotune");
+  if (cache_path) {
+    std::ofstream out(cache_path);
+    if (!out) return ctx->fail(PTROM_EINVAL, std::string("cannot write ") + cache_path);
+    out << report.str();
+  }
+  return PTROM_OK;
+}

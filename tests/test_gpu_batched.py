@@ -1,0 +1,104 @@
+"""GPU parity of the batched persistent stepper (many instances with their own
+N_b and delta_b) against the FP64 oracle run instance by instance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_01983_amd import native
+from paper_2103_01983_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def small_batch(sizes, seed):
+    rng = np.random.default_rng(seed)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    xy, g = [], []
+    for b, n in enumerate(sizes):
+        c = W.gaussian_patch(int(n), seed=seed + b)
+        xy.append(c.xy)
+        g.append(c.gamma * rng.uniform(0.5, 2.0))
+    delta = np.array([0.0 if b == 0 else 0.005 + 0.01 * b for b in range(len(sizes))])
+    return off, f32(np.concatenate(xy)), f32(np.concatenate(g)), np.float32(delta)
+
+
+def inst(off, xy, g, b):
+    o0, o1 = off[b], off[b + 1]
+    return xy[2 * o0:2 * o1], g[o0:o1]
+
+
+SIZES = [1, 2, 300, 513, 2049, 257]
+
+
+def test_batched_velocity_parity(dev):
+    off, xy, g, dl = small_batch(SIZES, 11)
+    f = native.velocity_batched(off, torch.tensor(xy, dtype=torch.float32, device=dev),
+                                torch.tensor(g, dtype=torch.float32, device=dev), dl).cpu().numpy()
+    for b in range(len(SIZES)):
+        x, gg = inst(off, xy, g, b)
+        fb = f[2 * off[b]:2 * off[b + 1]]
+        if SIZES[b] == 1:
+            assert np.all(fb == 0)
+            continue
+        assert rel(fb, oracle.velocity(x, gg, float(dl[b]))) <= 1e-5, b
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batched_rk4_parity(dev, use_graph):
+    off, xy, g, dl = small_batch(SIZES, 12)
+    dl[0] = 0.01
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    native.rk4_batched(off, x, torch.tensor(g, dtype=torch.float32, device=dev), dl, 1e-3, 4, use_graph=use_graph)
+    xs = x.cpu().numpy()
+    for b in range(len(SIZES)):
+        x0, gg = inst(off, xy, g, b)
+        o = oracle.rk4(x0, gg, float(dl[b]), float(np.float32(1e-3)), 4)
+        xb = xs[2 * off[b]:2 * off[b + 1]]
+        if SIZES[b] == 1:
+            assert np.array_equal(xb, x0)
+            continue
+        assert rel(xb, o) <= 1e-6 and rel(xb - x0, o - x0) <= 1e-4, b
+
+
+def test_batched_full_config(dev):
+    # 256 instances, N_b log-uniform in [2048, 32768], delta_b in [0.005, 0.05],
+    # circulation scale in [0.5, 2]; sampled velocities of the largest
+    # instances, and 20 RK4 steps of the three smallest against the oracle.
+    bt = W.batched_patches()
+    off = bt.offsets
+    xy, g, dl = f32(bt.xy), f32(bt.gamma), np.float32(bt.delta)
+    xd = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    f = native.velocity_batched(off, xd, gd, dl).cpu().numpy()
+    nb = np.diff(off)
+    rng = np.random.default_rng(0)
+    for b in list(np.argsort(nb)[-3:]) + [0, 100]:
+        x, gg = inst(off, xy, g, b)
+        n = int(nb[b])
+        idx = rng.choice(n, 32, replace=False)
+        fb = f[2 * off[b]:2 * off[b + 1]]
+        assert rel(np.concatenate([fb[idx], fb[n + idx]]), oracle.velocity_at(x, gg, float(dl[b]), idx)) <= 1e-5
+    native.rk4_batched(off, xd, gd, dl, 1e-3, 20)
+    xs = xd.cpu().numpy()
+    for b in np.argsort(nb)[:3]:
+        x0, gg = inst(off, xy, g, b)
+        o = oracle.rk4(x0, gg, float(dl[b]), float(np.float32(1e-3)), 20)
+        xb = xs[2 * off[b]:2 * off[b + 1]]
+        assert rel(xb - x0, o - x0) <= 1e-4
+
+
+def test_batched_rejects_bad_offsets(dev):
+    x = torch.zeros(8, device=dev)
+    g = torch.zeros(4, device=dev)
+    with pytest.raises(native.PtromError):
+        native.velocity_batched([0, 2, 2, 4], x, g, [0.1, 0.1, 0.1])

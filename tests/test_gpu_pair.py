@@ -1,0 +1,125 @@
+"""GPU parity of the pair-sum kernels (velocity, Jacobian products, adjoint,
+self blocks) against the FP64 oracle on identical FP32-rounded inputs.
+Gate: relative L2 <= 1e-5 (velocities, Jacobian products); the adjoint's
+position and circulation parts are gated separately."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_01983_amd import native
+from paper_2103_01983_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def to_dev(a, dev, dt=torch.float32):
+    return torch.tensor(np.asarray(a), dtype=dt, device=dev)
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def cloud(n, seed, kind="gauss", delta=0.01):
+    if kind == "gauss":
+        c = W.gaussian_patch(n, seed=seed, delta=delta)
+    elif kind == "disk":
+        c = W.disk_cloud(n, seed=seed, delta=delta)
+    else:
+        c = W.counter_rotating_patches(n, seed=seed, delta=delta)
+    return f32(c.xy), f32(c.gamma), np.float32(delta)
+
+
+SIZES = [1, 2, 3, 255, 256, 257, 511, 1000, 4099]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("delta", [0.0, 0.01])
+def test_velocity_parity(dev, n, delta):
+    xy, g, d = cloud(n, 100 + n, "disk", delta)
+    f = native.velocity(to_dev(xy, dev), to_dev(g, dev), d).cpu().numpy()
+    o = oracle.velocity(xy, g, float(d))
+    if n == 1:
+        assert np.all(f == 0.0)
+        return
+    assert np.all(np.isfinite(f))
+    assert rel(f, o) <= TOL, rel(f, o)
+
+
+@pytest.mark.parametrize("n", [3, 257, 1000, 4099])
+def test_jvp_parity(dev, n):
+    xy, g, d = cloud(n, 200 + n, "gauss", 0.01)
+    v = f32(W.unit_vectors(n, 1, 7)[0])
+    jv = native.jvp(to_dev(xy, dev), to_dev(g, dev), d, to_dev(v, dev)).cpu().numpy()
+    assert rel(jv, oracle.jvp(xy, g, float(d), v)) <= TOL
+
+
+@pytest.mark.parametrize("n", [3, 257, 4099])
+@pytest.mark.parametrize("delta", [0.0, 0.02])
+def test_vjp_parity(dev, n, delta):
+    xy, g, d = cloud(n, 300 + n, "disk", delta)
+    w = f32(W.random_vectors(n, 1, 9)[0])
+    gx, gg = native.vjp(to_dev(xy, dev), to_dev(g, dev), d, to_dev(w, dev))
+    ox, og = oracle.vjp(xy, g, float(d), w)
+    assert rel(gx.cpu().numpy(), ox) <= TOL
+    assert rel(gg.cpu().numpy(), og) <= TOL
+
+
+@pytest.mark.parametrize("n", [2, 257, 4099])
+def test_block_jacobian_parity(dev, n):
+    xy, g, d = cloud(n, 400 + n, "gauss", 0.01)
+    B = native.block_jacobian(to_dev(xy, dev), to_dev(g, dev), d).cpu().numpy()
+    assert rel(B, oracle.block_jacobian(xy, g, float(d))) <= TOL
+
+
+def test_velocity_f64_parity(dev):
+    xy, g, _ = cloud(777, 5, "disk", 0.02)
+    f = native.velocity_f64(to_dev(xy, dev, torch.float64), to_dev(g, dev, torch.float64), 0.02).cpu().numpy()
+    assert rel(f, oracle.velocity(xy, g, 0.02)) <= 1e-13
+
+
+def test_full_size_gaussian_patch_sampled(dev):
+    # N = 65536 Gaussian patch (sigma 0.25, delta 0.01): velocity and a JVP with a
+    # random unit vector, checked on 256 sampled targets against the oracle.
+    c = W.config_cloud("c2_gaussian_patch")
+    xy, g, d = f32(c.xy), f32(c.gamma), np.float32(c.delta)
+    n = g.size
+    idx = np.random.default_rng(0).choice(n, 256, replace=False)
+    sel = np.concatenate([idx, n + idx])
+    xd, gd = to_dev(xy, dev), to_dev(g, dev)
+    f = native.velocity(xd, gd, d).cpu().numpy()
+    assert rel(f[sel], oracle.velocity_at(xy, g, float(d), idx)) <= TOL
+    v = f32(W.unit_vectors(n, 1, 1002)[0])
+    jv = native.jvp(xd, gd, d, to_dev(v, dev)).cpu().numpy()
+    assert rel(jv[sel], oracle.jvp_at(xy, g, float(d), v, idx)) <= TOL
+    gx, gg = native.vjp(xd, gd, d, to_dev(v, dev))
+    ox, og = oracle.vjp_at(xy, g, float(d), v, idx)
+    assert rel(gx.cpu().numpy()[sel], ox) <= TOL
+    assert rel(gg.cpu().numpy()[idx], og) <= TOL
+    # invariant at full size: sum_i Gamma_i f_i = 0 (FP32 roundoff level)
+    assert abs(np.dot(g, f[:n])) <= 1e-5 * np.abs(g).sum() * np.abs(f).max()
+
+
+def test_deterministic(dev):
+    xy, g, d = cloud(20000, 3, "gauss", 0.01)
+    xd, gd = to_dev(xy, dev), to_dev(g, dev)
+    a = native.velocity(xd, gd, d)
+    b = native.velocity(xd, gd, d)
+    assert torch.equal(a, b)
+
+
+def test_invalid_arguments_raise(dev):
+    xd = torch.zeros(4, device=dev)
+    gd = torch.zeros(2, device=dev)
+    with pytest.raises(native.PtromError):
+        native.velocity(xd, gd, -1.0)
+    with pytest.raises(ValueError):
+        native.velocity(xd, gd.double(), 0.1)

@@ -1,0 +1,98 @@
+"""GPU parity of the time steppers against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_01983_amd import native
+from paper_2103_01983_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def test_rk4_fp32_parity(dev):
+    c = W.gaussian_patch(3000, seed=31, delta=0.01)
+    xy, g = f32(c.xy), f32(c.gamma)
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    native.rk4(x, gd, 0.01, 1e-3, 10)
+    native.rk4(x, gd, 0.01, 1e-3, 10)  # replays the cached graph
+    o = oracle.rk4(xy, g, 0.01, 1e-3, 20)
+    assert rel(x.cpu().numpy(), o) <= 1e-5
+    assert rel(x.cpu().numpy() - xy, o - xy) <= 1e-4
+
+
+def test_rk4_fp64_disk_config(dev):
+    # N=1024 uniform disk, Gamma ~ N(0,1) with zero sum, delta 0.02, 100 RK4
+    # steps at dt 1e-3: the FP64 path reproduces the oracle's discrete map.
+    cfg = W.CONFIGS["c1_disk_fp64"]
+    c = W.config_cloud("c1_disk_fp64")
+    x = torch.tensor(c.xy, dtype=torch.float64, device=dev)
+    gd = torch.tensor(c.gamma, dtype=torch.float64, device=dev)
+    f = native.velocity_f64(x, gd, c.delta).cpu().numpy()
+    assert rel(f, oracle.velocity(c.xy, c.gamma, c.delta)) <= 1e-13
+    # one step from the same state: the step map itself agrees to FP64 roundoff
+    x1 = x.clone()
+    native.rk4_f64(x1, gd, c.delta, cfg["dt"], 1)
+    assert rel(x1.cpu().numpy() - c.xy, oracle.rk4(c.xy, c.gamma, c.delta, cfg["dt"], 1) - c.xy) <= 1e-12
+    native.rk4_f64(x, gd, c.delta, cfg["dt"], cfg["steps"])
+    o = oracle.rk4(c.xy, c.gamma, c.delta, cfg["dt"], cfg["steps"])
+    # The flow is chaotic: the gate is the oracle's own divergence under a
+    # relative perturbation of 1e-16 of the initial state (one FP64 ulp).
+    pert = c.xy * (1 + 1e-16 * np.random.default_rng(0).standard_normal(c.xy.size))
+    cond = rel(oracle.rk4(pert, c.gamma, c.delta, cfg["dt"], cfg["steps"]), o)
+    assert rel(x.cpu().numpy(), o) <= max(cond, 1e-12)
+    # FP32 velocity at the initial state, per evaluation
+    f32v = native.velocity(torch.tensor(f32(c.xy), dtype=torch.float32, device=dev),
+                           torch.tensor(f32(c.gamma), dtype=torch.float32, device=dev), c.delta).cpu().numpy()
+    assert rel(f32v, oracle.velocity(f32(c.xy), f32(c.gamma), float(np.float32(c.delta)))) <= 1e-5
+
+
+@pytest.mark.parametrize("scheme", [native.BACKWARD_EULER, native.TRAPEZOID])
+def test_implicit_parity(dev, scheme):
+    c = W.gaussian_patch(700, seed=41, delta=0.01)
+    xy, g = f32(c.xy), f32(c.gamma) * 50.0
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, 0.01, 5e-4, 5, scheme=scheme, newton_tol=1e-7, gmres_tol=1e-4)
+    assert st.nonconverged_steps == 0
+    o, _ = oracle.implicit(xy, g, float(np.float32(0.01)), float(np.float32(5e-4)), 5, scheme=scheme)
+    xs = x.cpu().numpy()
+    assert rel(xs, o) <= 1e-5
+    assert rel(xs - xy, o - xy) <= 1e-4
+
+
+def test_backward_euler_full_size_residual(dev):
+    # N = 65536 Gaussian patch, backward Euler dt 5e-4: after several steps the
+    # state must satisfy x_n - x_{n-1} - dt f(x_n) = 0 on sampled rows, with f
+    # from the oracle.
+    cfg = W.CONFIGS["c2_gaussian_patch"]
+    c = W.config_cloud("c2_gaussian_patch")
+    n = c.n
+    x = torch.tensor(c.xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(c.gamma, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], 3)
+    assert st.nonconverged_steps == 0
+    xprev = x.cpu().numpy().astype(np.float64)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], 1)
+    assert st.nonconverged_steps == 0
+    xn = x.cpu().numpy().astype(np.float64)
+    idx = np.random.default_rng(1).choice(n, 128, replace=False)
+    sel = np.concatenate([idx, n + idx])
+    fo = oracle.velocity_at(xn, f32(c.gamma), float(np.float32(c.delta)), idx)
+    dtf = float(np.float32(cfg["dt"]))
+    r = xn[sel] - xprev[sel] - dtf * fo
+    # bound: Newton tolerance (1e-6 of the initial residual dt f) plus FP32
+    # velocity error plus rounding of the two stored FP32 states
+    u = 2.0 ** -24
+    rounding = u * np.linalg.norm(np.abs(xn[sel]) + np.abs(xprev[sel]))
+    assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(dtf * fo) + rounding

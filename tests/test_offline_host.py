@@ -1,0 +1,52 @@
+"""Host-side offline pieces of the product (native quadtree clustering,
+greedy sampler) against the oracle's independent implementations: interaction
+lists must agree exactly (index work), surrogate values to FP64 roundoff."""
+import numpy as np
+import pytest
+
+from oracle import offline as oo
+from paper_2103_01983_amd import native
+from paper_2103_01983_amd import offline as po
+from paper_2103_01983_amd import workloads as W
+
+
+def setup(n, seed, M=6):
+    cl = W.counter_rotating_patches(n, seed=seed, delta=0.02)
+    rng = np.random.default_rng(seed)
+    # any orthonormal basis with a position-like leading mode is a valid input
+    Phi = np.linalg.qr(np.column_stack([cl.xy, rng.standard_normal((2 * n, M - 1))]))[0]
+    sigma = np.sort(rng.uniform(0.5, 3.0, M))[::-1] * np.linspace(10, 1, M)
+    return cl, Phi, sigma
+
+
+@pytest.mark.parametrize("n,pc,depth", [(200, 1.0, 6), (513, 0.5, 4), (300, np.inf, 6), (64, 0.0, 6)])
+def test_cluster_lists_match_oracle(n, pc, depth):
+    cl, Phi, sigma = setup(n, 3 + n)
+    P = oo.weighted_points(Phi, sigma)
+    tree = oo.QuadTree(P, depth)
+    targets = np.arange(0, n, 3)
+    ox, oP, oG, ooff, oids, okeys = oo.cluster_artifacts(tree, targets, pc, cl.xy, Phi, cl.gamma)
+    r = native.cluster_build(np.ascontiguousarray(P), cl.xy, Phi, cl.gamma, depth, pc, targets)
+    assert np.array_equal(r["off"], ooff)
+    assert np.array_equal(r["ids"], oids)
+    # keys: bodies (j) then cells (2^60 | level<<40 | row<<20 | col)
+    enc = [k[1] if k[0] == 0 else (1 << 60) | (k[1] << 40) | (k[2] << 20) | k[3] for k in okeys]
+    assert np.array_equal(r["keys"], np.array(enc, dtype=np.int64))
+    np.testing.assert_allclose(r["xqt0"], ox, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["Phit"], oP, rtol=0, atol=1e-13)
+    # sums of up to n terms of size 1/n in different orders
+    np.testing.assert_allclose(r["Gt"], oG, rtol=0, atol=1e-14)
+
+
+def test_greedy_matches_oracle():
+    rng = np.random.default_rng(5)
+    for n, Mr, ns in [(100, 16, 16), (257, 8, 20), (64, 12, 5), (40, 6, 40)]:
+        Phi_r = np.linalg.qr(rng.standard_normal((2 * n, Mr)))[0]
+        assert np.array_equal(po.greedy_sample(Phi_r, ns), oo.greedy_sample(Phi_r, ns)), (n, Mr, ns)
+
+
+def test_cluster_rejects_bad_input():
+    cl, Phi, sigma = setup(50, 1)
+    P = oo.weighted_points(Phi, sigma)
+    with pytest.raises(native.PtromError):
+        native.cluster_build(P, cl.xy, Phi, cl.gamma, 6, 1.0, np.array([0, 50]))
