@@ -30,17 +30,34 @@ __global__ void residual_kernel(int64_t m, float *__restrict__ r, const float *_
   if (q < m) r[q] = D[q] - (dtb0 * f[q] + dtb1 * fp[q]);
 }
 
-// out[v] = sum_q X_v[q] * y[q] for v < nvec; one workgroup per vector, FP64.
-__global__ void __launch_bounds__(1024)
-    multi_dot_kernel(int64_t m, const float *__restrict__ X, int64_t ldx, const float *__restrict__ y,
-                     double *__restrict__ out) {
-  __shared__ double red[1024];
-  const float *x = X + (size_t)blockIdx.x * ldx;
+constexpr int kDotParts = 64;
+
+// part[v][p] = sum over the p-th strided slice of X_v . y (FP64 accumulation);
+// grid (kDotParts, nvec).
+__global__ void __launch_bounds__(256)
+    dot_partial_kernel(int64_t m, const float *__restrict__ X, int64_t ldx, const float *__restrict__ y,
+                       double *__restrict__ part) {
+  __shared__ double red[256];
+  const float *x = X + (size_t)blockIdx.y * ldx;
   double s = 0.0;
-  for (int64_t q = threadIdx.x; q < m; q += blockDim.x) s += (double)x[q] * (double)y[q];
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < m; q += (int64_t)kDotParts * 256)
+    s += (double)x[q] * (double)y[q];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * kDotParts + blockIdx.x] = red[0];
+}
+
+// out[v] = sum_p part[v][p], in a fixed order
+__global__ void __launch_bounds__(64)
+    dot_final_kernel(const double *__restrict__ part, double *__restrict__ out) {
+  __shared__ double red[kDotParts];
+  red[threadIdx.x] = part[blockIdx.x * kDotParts + threadIdx.x];
+  __syncthreads();
+  for (int w = kDotParts / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -80,7 +97,7 @@ struct Solver {
   float *pws;
   size_t pwsf;
   float *xi, *tmp, *w, *V;
-  double *dev_dots, *host_dots;
+  double *dev_dots, *host_dots, *dot_part;
   int restart;
 
   // w = (I - c J(xi)) v
@@ -93,7 +110,8 @@ struct Solver {
   }
 
   int dots(const float *X, int nvec, const float *y, double *host) {
-    hipLaunchKernelGGL(multi_dot_kernel, dim3(nvec), dim3(1024), 0, st, m, X, m, y, dev_dots);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotParts, nvec), dim3(256), 0, st, m, X, m, y, dot_part);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(nvec), dim3(kDotParts), 0, st, dot_part, dev_dots);
     PTROM_CHECK_HIP(ctx, hipMemcpyAsync(host, dev_dots, sizeof(double) * nvec, hipMemcpyDeviceToHost, st));
     PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
     return PTROM_OK;
@@ -210,7 +228,8 @@ extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float 
                                pair_ws_floats(OP_JVP, jcfg, ctx->num_cus, n));
   const int R = o.gmres_restart;
   const size_t vb = align256(m * sizeof(float));
-  const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (R + 2)) + 512;
+  const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (R + 2)) +
+                      align256(sizeof(double) * (R + 2) * kDotParts) + 768;
   if (int rc = ctx->reserve(need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
   float *xprev = cv.take<float>(m), *D = cv.take<float>(m), *xi = cv.take<float>(m);
@@ -219,10 +238,11 @@ extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float 
   float *V = cv.take<float>(m * (R + 1));
   float *pws = cv.take<float>(pwsf ? pwsf : 1);
   double *dd = cv.take<double>(R + 2);
-  if (!w || !V || !pws || !dd) return ctx->fail(PTROM_ENOMEM, "workspace carve");
+  double *dpart = cv.take<double>(size_t(R + 2) * kDotParts);
+  if (!w || !V || !pws || !dd || !dpart) return ctx->fail(PTROM_ENOMEM, "workspace carve");
   std::vector<double> hd(R + 2);
   hipStream_t st = (hipStream_t)stream;
-  Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hd.data(), R};
+  Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hd.data(), dpart, R};
 
   for (int step = 0; step < nsteps; ++step) {
     PTROM_CHECK_HIP(ctx, hipMemcpyAsync(xprev, xy, m * sizeof(float), hipMemcpyDeviceToDevice, st));

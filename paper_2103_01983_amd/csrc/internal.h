@@ -89,7 +89,7 @@ struct ptrom_ctx {
   }
   void keep_graph(const std::string &key, hipGraphExec_t ex) {
     if (graphs.size() >= 16) {
-      hipGraphExecDestroy(graphs.front().exec);
+      (void)hipGraphExecDestroy(graphs.front().exec);
       graphs.erase(graphs.begin());
     }
     graphs.push_back({key, ex});

@@ -44,24 +44,26 @@ __device__ __forceinline__ void interact(const float *t, const float *s, float d
     acc[1] = fmaf(g2, dd - d2, acc[1]);
     acc[2] = fmaf(g2, dd + d2, acc[2]);
   } else if constexpr (OP == OP_JVP) {
-    // H (v_i - v_j), H = [[a2, dd - d2], [dd + d2, -a2]] / q^2
-    const float g2 = s[2] * r * r;
-    const float a2 = (dx + dx) * dy;
-    const float dd = fmaf(dy, dy, -dx * dx);
+    // du/dr = R (I - 2 r r^T / q) / q with R the rotation by +90 degrees, so
+    // H e = R (e - c r) / q,  c = 2 (r . e) / q,  e = v_i - v_j.
     const float ex = t[2] - s[3];
     const float ey = t[3] - s[4];
-    acc[0] = fmaf(g2, fmaf(a2, ex, (dd - d2) * ey), acc[0]);
-    acc[1] = fmaf(g2, fmaf(dd + d2, ex, -a2 * ey), acc[1]);
+    const float c = fmaf(dx, ex, dy * ey) * (r + r);
+    const float wx = fmaf(-c, dx, ex);
+    const float wy = fmaf(-c, dy, ey);
+    const float g = s[2] * r;
+    acc[0] = fmaf(-g, wy, acc[0]);
+    acc[1] = fmaf(g, wx, acc[1]);
   } else {
-    // H^T (Gamma_j w_k - Gamma_k w_j) and the circulation partial
-    // -w_j . (-dy, dx)/q with (dx, dy) = x_k - x_j.
-    const float r2 = r * r;
-    const float a2 = (dx + dx) * dy;
-    const float dd = fmaf(dy, dy, -dx * dx);
+    // H^T q = (I - 2 r r^T / q) R^T q / q with q = Gamma_j w_k - Gamma_k w_j,
+    // R^T q = (q_y, -q_x); and the circulation partial -w_j . R r / q.
     const float qx = fmaf(s[2], t[2], -t[4] * s[3]);
     const float qy = fmaf(s[2], t[3], -t[4] * s[4]);
-    acc[0] = fmaf(r2, fmaf(a2, qx, (dd + d2) * qy), acc[0]);
-    acc[1] = fmaf(r2, fmaf(dd - d2, qx, -a2 * qy), acc[1]);
+    const float c = fmaf(dx, qy, -dy * qx) * (r + r);
+    const float wx = fmaf(-c, dx, qy);
+    const float wy = fmaf(-c, dy, -qx);
+    acc[0] = fmaf(r, wx, acc[0]);
+    acc[1] = fmaf(r, wy, acc[1]);
     acc[2] = fmaf(r, fmaf(s[3], dy, -s[4] * dx), acc[2]);
   }
 }

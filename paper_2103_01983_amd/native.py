@@ -15,6 +15,8 @@ import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libptrom.so")
+# launch parameters chosen by ptrom_autotune on an MI355X (loaded by default)
+TUNING_PATH = os.path.join(PKG, "tuning_gfx950.txt")
 
 PTROM_OK, PTROM_ENOCONV = 0, 1
 BACKWARD_EULER, TRAPEZOID = 0, 1
@@ -123,6 +125,8 @@ def context(device=None) -> int:
         rc = lib().ptrom_create(ctypes.byref(h), idx)
         if rc != PTROM_OK:
             raise PtromError("ptrom_create(device=%d) failed with %d" % (idx, rc))
+        if os.path.exists(TUNING_PATH) and not os.environ.get("PTROM_TUNE_CACHE"):
+            lib().ptrom_load_tuning(h, TUNING_PATH.encode())
         _ctxs[idx] = h
     return _ctxs[idx]
 

@@ -46,12 +46,12 @@ def pod(S, M, center=None):
     sig = np.sqrt(np.maximum(w[order], 0.0))
     if np.any(sig <= 0):
         raise RuntimeError("snapshot matrix has rank < M")
-    T = torch.tensor(V[:, order] / sig[None, :], dtype=torch.float64, device=S.device)
+    T = torch.tensor(np.ascontiguousarray(V[:, order] / sig[None, :]), dtype=torch.float64, device=S.device)
     Phi = native.combine_f64(X, T)
     for _ in range(2):  # CholeskyQR2
         G2 = native.gram_f64(Phi).cpu().numpy()
         R = np.linalg.cholesky(G2).T
-        Rinv = torch.tensor(np.linalg.inv(R), dtype=torch.float64, device=S.device)
+        Rinv = torch.tensor(np.ascontiguousarray(np.linalg.inv(R)), dtype=torch.float64, device=S.device)
         Phi = native.combine_f64(Phi, Rinv)
     return Phi, sig
 

@@ -67,7 +67,10 @@ def test_batched_rk4_parity(dev, use_graph):
         if SIZES[b] == 1:
             assert np.array_equal(xb, x0)
             continue
-        assert rel(xb, o) <= 1e-6 and rel(xb - x0, o - x0) <= 1e-4, b
+        # displacement to 1e-4, plus the FP32 rounding of the stored state per step
+        u = 2.0 ** -24
+        assert rel(xb, o) <= 1e-6, b
+        assert np.linalg.norm(xb - o) <= 1e-4 * np.linalg.norm(o - x0) + 4 * u * np.linalg.norm(o), b
 
 
 def test_batched_full_config(dev):
