@@ -112,6 +112,18 @@ int ptrom_block_jacobian(ptrom_ctx *ctx, int64_t n, const float *xy, const float
 int ptrom_vjp(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
               const float *w, float *gxy, float *ggamma, ptrom_stream stream);
 
+/* Stream function of the regularized flow at every body, induced by the
+ * others: psi_i = -(1/4pi) sum_{j != i} Gamma_j log(|r|^2 + delta^2); psi[N].
+ * The Hamiltonian of the metrics section (in its regularized, conserved form)
+ * is H = 1/2 sum_i Gamma_i psi_i, and f_i = (d psi_i/dy_i, -d psi_i/dx_i). */
+int ptrom_stream_function(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
+                          float *psi, ptrom_stream stream);
+
+/* Velocity induced at nt arbitrary points p [2][nt] (SoA) by all n bodies, no
+ * exclusion (the grid velocity field of the metrics section); f [2][nt]. */
+int ptrom_velocity_points(ptrom_ctx *ctx, int64_t nt, const float *p, int64_t n, const float *xy,
+                          const float *gamma, float delta, float *f, ptrom_stream stream);
+
 /* ------------------------------------------------------------------------
  * Time steppers.
  * ---------------------------------------------------------------------- */
@@ -245,12 +257,17 @@ int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, i
 typedef struct ptrom_clusters ptrom_clusters;
 
 /* Host-side (no GPU) quadtree over the weighted POD points and per-target
- * neighbour-search clustering (Algorithms "ClusterPOD" and "checkPrune").
+ * source clustering (Algorithms "ClusterPOD" and "checkPrune").
  * All arrays are HOST memory:
  *   wpts [n][2]  each body's point in W_phi = Phi Sigma_hat ((Phi s)_i, (Phi s)_{i+n});
  *   xy0 [2n]     reference state x^0 (SoA);  phi [2n][M] POD basis, row-major;
  *   gamma [n];   max_level = depth cap of the tree (root = level 0);
- *   pc >= 0      neighbourhood factor (Def. 2); INFINITY prunes nothing;
+ *   criterion    0 = neighbour search: prune a source cell that does not
+ *                overlap the target leaf grown by pc times its width (Def. 2;
+ *                pc >= 0, INFINITY prunes nothing);
+ *                1 = Barnes-Hut: prune when w / |s - s_i| <= theta, w the cell
+ *                width, s its |Gamma|-weighted mean point, s_i the target's
+ *                point (theta >= 0; 0 prunes nothing but zero-width cells);
  *   targets [nt] body ids whose interaction lists are built.
  * Readings of the open passages: root = tight bounding box; midpoint splits
  * while a cell holds > 1 body and is above max_level; half-open membership;
@@ -260,8 +277,8 @@ typedef struct ptrom_clusters ptrom_clusters;
  * then cells (by level, row, column); every list is sorted by surrogate id.
  * The result object owns its arrays; read them with ptrom_cluster_fetch. */
 int ptrom_cluster_build(int64_t n, const double *wpts, const double *xy0, const double *phi, int M,
-                        const double *gamma, int max_level, double pc, int64_t nt,
-                        const int64_t *targets, ptrom_clusters **out);
+                        const double *gamma, int max_level, int criterion, double pc, double theta,
+                        int64_t nt, const int64_t *targets, ptrom_clusters **out);
 int ptrom_cluster_sizes(const ptrom_clusters *c, int64_t *nc, int64_t *nnz);
 /* Copies into caller HOST buffers (any may be NULL): xqt0 [Nc][2], phit
  * [Nc][2][M], gt [Nc], off [nt+1], ids [nnz], keys [Nc] (body id, or

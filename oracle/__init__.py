@@ -75,6 +75,8 @@ def lib():
         L.or_vjp_at.argtypes = [i64, _dp, _dp, dbl, _dp, i64, _i64p, _dp, _dp]
         L.or_hamiltonian.argtypes = [i64, _dp, _dp, dbl]
         L.or_hamiltonian.restype = dbl
+        L.or_stream_function.argtypes = [i64, _dp, _dp, dbl, _dp]
+        L.or_velocity_points.argtypes = [i64, _dp, i64, _dp, _dp, dbl, _dp]
         L.or_rk4.argtypes = [i64, _dp, _dp, dbl, dbl, i32]
         L.or_implicit.argtypes = [i64, _dp, _dp, dbl, dbl, i32, i32, dbl, i32, dbl, i32, i32,
                                   ctypes.POINTER(NewtonStats)]
@@ -171,6 +173,25 @@ def hamiltonian(xy, gamma, delta):
     n = _n(xy)
     xy, pxy = _d(xy); g, pg = _d(gamma)
     return lib().or_hamiltonian(n, pxy, pg, float(delta))
+
+
+def stream_function(xy, gamma, delta):
+    """psi_i = -(1/4pi) sum_{j!=i} Gamma_j log(|r|^2+delta^2); H = 1/2 sum Gamma_i psi_i."""
+    n = _n(xy)
+    xy, pxy = _d(xy); g, pg = _d(gamma)
+    out = np.empty(n)
+    lib().or_stream_function(n, pxy, pg, float(delta), out.ctypes.data_as(_dp))
+    return out
+
+
+def velocity_points(points, xy, gamma, delta):
+    """Velocity at arbitrary points [2][nt] (SoA) induced by all bodies."""
+    n = _n(xy)
+    p, pp = _d(points); xy, pxy = _d(xy); g, pg = _d(gamma)
+    nt = p.size // 2
+    out = np.empty(2 * nt)
+    lib().or_velocity_points(nt, pp, n, pxy, pg, float(delta), out.ctypes.data_as(_dp))
+    return out
 
 
 # ---------------------------------------------------------------------------

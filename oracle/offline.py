@@ -137,19 +137,38 @@ def node_surrogates(node, xy0, Phi, gamma):
     return x0, ph, float(gamma[idx].sum())
 
 
-def find_clusters(tree, i, pc):
-    """Cluster keys seen by target body i (FindClusters / Traverse with the
-    neighbour-search checkPrune).  Keys: (0, j, 0, 0) for a single body j,
-    node.key for an agglomerated cell."""
+def weighted_point_mean(tree, node, gamma):
+    """|Gamma|-weighted mean of the members' points in the tree's space (the
+    surrogate-source position s of Def. 1 in W_phi); plain mean if all
+    weights vanish."""
+    idx = np.asarray(node.members)
+    w = np.abs(gamma[idx])
+    if w.sum() == 0.0:
+        w = np.ones_like(w)
+    return (w[:, None] * tree.P[idx]).sum(axis=0) / w.sum()
+
+
+def find_clusters(tree, i, pc, criterion="neighbor", theta=0.0, gamma=None):
+    """Cluster keys seen by target body i (FindClusters / Traverse with
+    checkPrune).  criterion "neighbor": prune a cell that does not overlap the
+    target leaf grown by pc times its width; "barnes-hut": prune when
+    w / |s - s_i| <= theta, s the cell's weighted mean point and s_i the
+    target's point.  Keys: (0, j, 0, 0) for a single body j, node.key for an
+    agglomerated cell."""
     leaf = tree.leaf_of[i]
     w = leaf.width
     h_lo = leaf.lo - pc * w
     h_hi = leaf.hi + pc * w
+    si = tree.P[i]
     out = []
 
     def visit(node):
-        ov = (h_hi[0] > node.lo[0] and h_lo[0] < node.hi[0] and
-              h_hi[1] > node.lo[1] and h_lo[1] < node.hi[1])
+        if criterion == "neighbor":
+            ov = (h_hi[0] > node.lo[0] and h_lo[0] < node.hi[0] and
+                  h_hi[1] > node.lo[1] and h_lo[1] < node.hi[1])
+        else:
+            dist = float(np.linalg.norm(weighted_point_mean(tree, node, gamma) - si))
+            ov = not (dist > 0.0 and node.width / dist <= theta)
         if node.level <= leaf.level and (leaf.ix >> (leaf.level - node.level)) == node.ix \
                 and (leaf.iy >> (leaf.level - node.level)) == node.iy:
             ov = True  # the cell holds the target
@@ -169,12 +188,12 @@ def find_clusters(tree, i, pc):
     return out
 
 
-def cluster_artifacts(tree, targets, pc, xy0, Phi, gamma):
+def cluster_artifacts(tree, targets, pc, xy0, Phi, gamma, criterion="neighbor", theta=0.0):
     """UniqueSearch over the cluster lists of ``targets``.  Returns
     (xqt0 [Nc,2], Phit [Nc,2,M], Gt [Nc], off [nt+1], ids [nnz], keys)."""
     n = gamma.size
     M = Phi.shape[1]
-    lists = [find_clusters(tree, int(i), pc) for i in targets]
+    lists = [find_clusters(tree, int(i), pc, criterion, theta, gamma) for i in targets]
     keys = sorted(set(k for L in lists for k in L))
     index = {k: c for c, k in enumerate(keys)}
     by_key = {nd.key: nd for nd in tree.nodes}

@@ -191,6 +191,43 @@ double or_hamiltonian(int64_t n, const double *xy, const double *gam, double del
   return -total / OR_FOUR_PI;
 }
 
+/* Stream function of the regularized flow at every body, induced by the
+ * others: psi_i = -(1/4pi) sum_{j != i} G_j log(|r|^2 + d^2).  The velocity is
+ * its perpendicular gradient in the target position, f_i = (d psi_i/dy_i,
+ * -d psi_i/dx_i), and the Hamiltonian is H = 1/2 sum_i G_i psi_i. */
+void or_stream_function(int64_t n, const double *xy, const double *gam, double delta, double *psi) {
+  const double d2 = delta * delta;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double rx = xy[i] - xy[j], ry = xy[n + i] - xy[n + j];
+      acc += gam[j] * log(rx * rx + ry * ry + d2);
+    }
+    psi[i] = -acc / OR_FOUR_PI;
+  }
+}
+
+/* Velocity induced at nt arbitrary points p [2][nt] by all n bodies (no
+ * exclusion): the grid velocity field of the metrics section. */
+void or_velocity_points(int64_t nt, const double *p, int64_t n, const double *xy, const double *gam,
+                        double delta, double *out) {
+  const double d2 = delta * delta;
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nt; ++t) {
+    double sx = 0.0, sy = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      const double rx = p[t] - xy[j], ry = p[nt + t] - xy[n + j];
+      const double s = rx * rx + ry * ry + d2;
+      sx += gam[j] * (-ry) / s;
+      sy += gam[j] * rx / s;
+    }
+    out[t] = sx / OR_TWO_PI;
+    out[nt + t] = sy / OR_TWO_PI;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Explicit RK4 (classic four-stage scheme).                                 */
 /* ------------------------------------------------------------------------ */

@@ -125,6 +125,23 @@ extern "C" int ptrom_vjp(ptrom_ctx *ctx, int64_t n, const float *xy, const float
   return run_pair(ctx, OP_VJP, n, xy, gamma, w, delta, gxy, ggamma, (hipStream_t)stream);
 }
 
+extern "C" int ptrom_stream_function(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma,
+                                     float delta, float *psi, ptrom_stream stream) {
+  if (int rc = check_common(ctx, n, delta)) return rc;
+  if (!xy || !gamma || !psi) return ctx->fail(PTROM_EINVAL, "NULL array");
+  return run_pair(ctx, OP_PSI, n, xy, gamma, nullptr, delta, psi, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int ptrom_velocity_points(ptrom_ctx *ctx, int64_t nt, const float *p, int64_t n, const float *xy,
+                                     const float *gamma, float delta, float *f, ptrom_stream stream) {
+  if (int rc = check_common(ctx, n, delta)) return rc;
+  if (nt < 1 || nt > kMaxN) return ctx->fail(PTROM_EINVAL, "nt must be in [1, 2^30]");
+  if (!p || !xy || !gamma || !f) return ctx->fail(PTROM_EINVAL, "NULL array");
+  hipError_t e = launch_velocity_points(nt, p, n, xy, gamma, delta, f, (hipStream_t)stream);
+  if (e != hipSuccess) return ctx->hip_fail(e, "points velocity launch");
+  return PTROM_OK;
+}
+
 // ---------------------------------------------------------------- RK4
 
 // Records one RK4 step (4 velocity evaluations + stage updates) on `st`.

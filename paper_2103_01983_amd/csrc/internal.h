@@ -18,7 +18,10 @@ constexpr int kBlock = 256;   // threads per workgroup of the pair kernels (4 wa
 constexpr int kTile = 256;    // sources staged per LDS tile
 constexpr int64_t kMaxN = int64_t(1) << 30;
 
-enum PairOp { OP_VEL = 0, OP_BJAC = 1, OP_JVP = 2, OP_VJP = 3, OP_COUNT = 4 };
+enum PairOp { OP_VEL = 0, OP_BJAC = 1, OP_JVP = 2, OP_VJP = 3, OP_PSI = 4, OP_COUNT = 5 };
+
+// operations with an each-unordered-pair-once variant
+inline bool has_sym(int op) { return op == OP_VEL || op == OP_JVP || op == OP_VJP; }
 
 // Source staging of the pair kernels.
 //  LDS:    the workgroup stages a tile of sources in LDS; every lane reads it
@@ -30,8 +33,9 @@ enum Staging { STAGE_LDS = 0, STAGE_SCALAR = 1 };
 
 struct PairCfg {
   int staging = STAGE_SCALAR;
-  int k = 2;             // targets per lane
+  int k = 2;               // targets per lane
   int waves_per_simd = 8;  // occupancy target used to choose the source split
+  int sym = 0;             // 1: evaluate each unordered pair once (pair_sym.hip)
 };
 
 // One tuned entry per operation and size class (log2 of N, clamped).
@@ -49,6 +53,16 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n, const
                        float *ws, size_t ws_floats, hipStream_t stream);
 size_t pair_ws_floats(int op, const PairCfg &cfg, int num_cus, int64_t n);
 int pair_splits(int op, const PairCfg &cfg, int num_cus, int64_t n);
+
+// Each-unordered-pair-once variant (velocity, JVP, VJP only).
+size_t pair_sym_ws_floats(int op, int k, int64_t n);
+hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64_t n, const float *xy,
+                           const float *gamma, const float *aux, float delta, float *out, float *out2,
+                           float *ws, size_t ws_floats, hipStream_t stream);
+
+// velocity at nt arbitrary points p [2][nt] from all n bodies (no exclusion)
+hipError_t launch_velocity_points(int64_t nt, const float *p, int64_t n, const float *xy,
+                                  const float *gamma, float delta, float *out, hipStream_t stream);
 
 hipError_t launch_velocity_f64(int64_t n, const double *xy, const double *gamma, double delta,
                                double *f, hipStream_t stream);

@@ -102,10 +102,26 @@ inline int64_t node_key(const QNode &q) {
   return kNodeTag | (int64_t(q.level) << 40) | (int64_t(q.iy) << 20) | int64_t(q.ix);
 }
 
-void traverse(const QTree &T, int node, int target, const double hlo[2], const double hhi[2],
-              const QNode &leaf, std::vector<int64_t> &out) {
+struct PruneRule {
+  int criterion;          // 0 neighbour search, 1 Barnes-Hut
+  double theta;
+  double hlo[2], hhi[2];  // neighbourhood of the target leaf
+  double si[2];           // target point
+  const std::vector<double> *mean;  // per node weighted mean point [2]
+};
+
+void traverse(const QTree &T, int node, int target, const PruneRule &pr, const QNode &leaf,
+              std::vector<int64_t> &out) {
   const QNode &q = T.nodes[node];
-  bool ov = hhi[0] > q.lo[0] && hlo[0] < q.hi[0] && hhi[1] > q.lo[1] && hlo[1] < q.hi[1];
+  bool ov;
+  if (pr.criterion == 0) {
+    ov = pr.hhi[0] > q.lo[0] && pr.hlo[0] < q.hi[0] && pr.hhi[1] > q.lo[1] && pr.hlo[1] < q.hi[1];
+  } else {
+    const double dx = (*pr.mean)[2 * node] - pr.si[0], dy = (*pr.mean)[2 * node + 1] - pr.si[1];
+    const double dist = std::sqrt(dx * dx + dy * dy);
+    const double w = std::max(q.hi[0] - q.lo[0], q.hi[1] - q.lo[1]);
+    ov = !(dist > 0.0 && w / dist <= pr.theta);
+  }
   const int sh = leaf.level - q.level;
   if (sh >= 0 && (leaf.ix >> sh) == q.ix && (leaf.iy >> sh) == q.iy) ov = true;  // holds the target
   if (!ov) {
@@ -117,7 +133,7 @@ void traverse(const QTree &T, int node, int target, const double hlo[2], const d
       if (T.perm[t] != target) out.push_back(T.perm[t]);
     return;
   }
-  for (int c = 0; c < q.nchild; ++c) traverse(T, q.child[c], target, hlo, hhi, leaf, out);
+  for (int c = 0; c < q.nchild; ++c) traverse(T, q.child[c], target, pr, leaf, out);
 }
 
 }  // namespace
@@ -130,24 +146,48 @@ struct ptrom_clusters {
 };
 
 extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *xy0, const double *phi,
-                                   int M, const double *gamma, int max_level, double pc, int64_t nt,
-                                   const int64_t *targets, ptrom_clusters **out) {
+                                   int M, const double *gamma, int max_level, int criterion, double pc,
+                                   double theta, int64_t nt, const int64_t *targets, ptrom_clusters **out) {
   if (!out || n < 1 || n > kMaxN || !wpts || !xy0 || !phi || !gamma || M < 1 || max_level < 0 ||
-      max_level > 16 || !(pc >= 0.0) || nt < 1 || !targets)
+      max_level > 16 || !(pc >= 0.0) || !(theta >= 0.0) || (criterion != 0 && criterion != 1) || nt < 1 ||
+      !targets)
     return PTROM_EINVAL;
   for (int64_t t = 0; t < nt; ++t)
     if (targets[t] < 0 || targets[t] >= n) return PTROM_EINVAL;
   QTree T;
   T.build(n, wpts, max_level);
+  // per-node |Gamma|-weighted mean point (Barnes-Hut surrogate position)
+  std::vector<double> mean;
+  if (criterion == 1) {
+    mean.assign(2 * T.nodes.size(), 0.0);
+    for (size_t k = 0; k < T.nodes.size(); ++k) {
+      const QNode &q = T.nodes[k];
+      double ws = 0.0, mx = 0.0, my = 0.0;
+      for (int t = q.first; t < q.first + q.count; ++t) ws += std::fabs(gamma[T.perm[t]]);
+      for (int t = q.first; t < q.first + q.count; ++t) {
+        const int j = T.perm[t];
+        const double wj = ws == 0.0 ? 1.0 / q.count : std::fabs(gamma[j]) / ws;
+        mx += wj * wpts[2 * j];
+        my += wj * wpts[2 * j + 1];
+      }
+      mean[2 * k] = mx;
+      mean[2 * k + 1] = my;
+    }
+  }
   // per-target lists of surrogate keys
   std::vector<std::vector<int64_t>> lists(nt);
   for (int64_t t = 0; t < nt; ++t) {
     const int i = int(targets[t]);
     const QNode &leaf = T.nodes[T.leaf_of[i]];
     const double w = std::max(leaf.hi[0] - leaf.lo[0], leaf.hi[1] - leaf.lo[1]);
-    const double hlo[2] = {leaf.lo[0] - pc * w, leaf.lo[1] - pc * w};
-    const double hhi[2] = {leaf.hi[0] + pc * w, leaf.hi[1] + pc * w};
-    traverse(T, 0, i, hlo, hhi, leaf, lists[t]);
+    PruneRule pr;
+    pr.criterion = criterion;
+    pr.theta = theta;
+    pr.hlo[0] = leaf.lo[0] - pc * w; pr.hlo[1] = leaf.lo[1] - pc * w;
+    pr.hhi[0] = leaf.hi[0] + pc * w; pr.hhi[1] = leaf.hi[1] + pc * w;
+    pr.si[0] = wpts[2 * i]; pr.si[1] = wpts[2 * i + 1];
+    pr.mean = &mean;
+    traverse(T, 0, i, pr, leaf, lists[t]);
   }
   // UniqueSearch
   std::vector<int64_t> keys;

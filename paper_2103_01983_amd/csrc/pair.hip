@@ -67,7 +67,48 @@ int nacc(int op) {
     case OP_VEL: return Traits<OP_VEL>::NACC;
     case OP_BJAC: return Traits<OP_BJAC>::NACC;
     case OP_JVP: return Traits<OP_JVP>::NACC;
+    case OP_PSI: return Traits<OP_PSI>::NACC;
     default: return Traits<OP_VJP>::NACC;
+  }
+}
+
+// Velocity at arbitrary points: K = 2 points per lane, sources read at
+// wave-uniform addresses, 256-source tiles added with Kahan compensation.
+__global__ void __launch_bounds__(kBlock)
+    points_velocity_kernel(int nt, const float *__restrict__ p, int n, const float *__restrict__ xy,
+                           const float *__restrict__ gam, float d2, float *__restrict__ out) {
+  constexpr int K = 2;
+  float tg[K][2];
+  const int t0 = blockIdx.x * (kBlock * K);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int t = t0 + k * kBlock + threadIdx.x;
+    const int tc = t < nt ? t : nt - 1;
+    tg[k][0] = p[tc];
+    tg[k][1] = p[nt + tc];
+  }
+  float sum[K][2] = {}, cmp[K][2] = {};
+  for (int ts = 0; ts < n; ts += kTile) {
+    const int cnt = min(kTile, n - ts);
+    float part[K][2] = {};
+    for (int jj = 0; jj < cnt; ++jj) {
+      const float s[3] = {xy[ts + jj], xy[n + ts + jj], gam[ts + jj]};
+#pragma unroll
+      for (int k = 0; k < K; ++k) interact<OP_VEL, false>(tg[k], s, d2, part[k], false);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      kahan_add(sum[k][0], cmp[k][0], part[k][0]);
+      kahan_add(sum[k][1], cmp[k][1], part[k][1]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int t = t0 + k * kBlock + threadIdx.x;
+    if (t < nt) {
+      out[t] = (sum[k][0] - cmp[k][0]) * kInv2Pi;
+      out[nt + t] = (sum[k][1] - cmp[k][1]) * kInv2Pi;
+    }
   }
 }
 
@@ -180,6 +221,7 @@ int pair_splits(int op, const PairCfg &cfg, int num_cus, int64_t n) {
 }
 
 size_t pair_ws_floats(int op, const PairCfg &cfg, int num_cus, int64_t n) {
+  if (cfg.sym && has_sym(op)) return pair_sym_ws_floats(op, cfg.k, n);
   const int s = pair_splits(op, cfg, num_cus, n);
   return s > 1 ? size_t(s) * nacc(op) * size_t(n) : 0;
 }
@@ -187,6 +229,9 @@ size_t pair_ws_floats(int op, const PairCfg &cfg, int num_cus, int64_t n) {
 hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, const float *xy,
                        const float *gamma, const float *aux, float delta, float *out, float *out2,
                        float *ws, size_t ws_floats, hipStream_t stream) {
+  if (cfg.sym && has_sym(op))
+    return launch_pair_sym(op, cfg.k, cfg.waves_per_simd, num_cus, n64, xy, gamma, aux, delta, out, out2, ws,
+                           ws_floats, stream);
   const int n = int(n64);
   int s = pair_splits(op, cfg, num_cus, n64);
   int64_t chunk = ((n64 + s - 1) / s + kTile - 1) / kTile * kTile;
@@ -201,6 +246,7 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, con
     case OP_VEL: e = dispatch<OP_VEL>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
     case OP_BJAC: e = dispatch<OP_BJAC>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
     case OP_JVP: e = dispatch<OP_JVP>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
+    case OP_PSI: e = dispatch<OP_PSI>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
     default: e = dispatch<OP_VJP>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
   }
   if (e != hipSuccess || !partial) return e;
@@ -209,8 +255,16 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, con
     case OP_VEL: hipLaunchKernelGGL(reduce_kernel<OP_VEL>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
     case OP_BJAC: hipLaunchKernelGGL(reduce_kernel<OP_BJAC>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
     case OP_JVP: hipLaunchKernelGGL(reduce_kernel<OP_JVP>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
+    case OP_PSI: hipLaunchKernelGGL(reduce_kernel<OP_PSI>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
     default: hipLaunchKernelGGL(reduce_kernel<OP_VJP>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity_points(int64_t nt, const float *p, int64_t n, const float *xy,
+                                  const float *gamma, float delta, float *out, hipStream_t stream) {
+  hipLaunchKernelGGL(points_velocity_kernel, dim3((unsigned)((nt + 2 * kBlock - 1) / (2 * kBlock))), dim3(kBlock),
+                     0, stream, int(nt), p, int(n), xy, gamma, delta * delta, out);
   return hipGetLastError();
 }
 

@@ -13,6 +13,10 @@ template <> struct Traits<OP_VEL> { static constexpr int NSRC = 3, NTGT = 2, NAC
 template <> struct Traits<OP_BJAC> { static constexpr int NSRC = 3, NTGT = 2, NACC = 3; };
 template <> struct Traits<OP_JVP> { static constexpr int NSRC = 5, NTGT = 4, NACC = 2; };
 template <> struct Traits<OP_VJP> { static constexpr int NSRC = 5, NTGT = 5, NACC = 3; };
+template <> struct Traits<OP_PSI> { static constexpr int NSRC = 3, NTGT = 2, NACC = 1; };
+
+// -ln(2)/(4 pi): the stream-function sum is accumulated with log2
+constexpr float kPsiScale = -0.0551589363396979447f;
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
   const float y = x - c;
@@ -30,6 +34,13 @@ __device__ __forceinline__ void interact(const float *t, const float *s, float d
   const float dx = t[0] - s[0];
   const float dy = t[1] - s[1];
   const float q = fmaf(dx, dx, fmaf(dy, dy, d2));
+  if constexpr (OP == OP_PSI) {
+    // Gamma_j log2(|r|^2 + delta^2) (stream function of the regularized flow)
+    float L = __builtin_amdgcn_logf(q);
+    if (MASK) L = self ? 0.0f : L;
+    acc[0] = fmaf(s[2], L, acc[0]);
+    return;
+  }
   float r = __builtin_amdgcn_rcpf(q);
   if (MASK) r = self ? 0.0f : r;
   if constexpr (OP == OP_VEL) {
@@ -93,6 +104,8 @@ __device__ __forceinline__ void store_final(int n, int i, const float *v, float 
     out[n + i] = v[1] * kInv2Pi;
     out[2 * n + i] = v[2] * kInv2Pi;
     out[3 * n + i] = -v[0] * kInv2Pi;
+  } else if constexpr (OP == OP_PSI) {
+    out[i] = v[0] * kPsiScale;
   } else {
     out[i] = v[0] * kInv2Pi;
     out[n + i] = v[1] * kInv2Pi;

@@ -1,0 +1,256 @@
+// All-pairs kernels that evaluate every unordered pair once.
+//
+// The Biot-Savart pair terms are antisymmetric: with r = x_i - x_j the term
+// body j receives from body i is the term body i receives from j with
+// Gamma_j replaced by Gamma_i and the sign flipped (velocity: u(-r) = -u(r);
+// Jacobian product: H(-r) = H(r) and v_j - v_i = -(v_i - v_j); adjoint:
+// q_ji = -q_ij).  The body index range is cut into blocks of 256*K; block
+// pairs (I, J) with J > I are evaluated once, each interaction adding the
+// forward term to the target (registers) and the reaction term to the
+// source; diagonal blocks (I, I) use the ordinary one-sided tile.
+//
+// Inside an off-diagonal item a workgroup stages 64 sources of block J in
+// LDS and each wave sweeps them in 64 steps, lane l taking source
+// (l + t) mod 64 at step t: the 64 lanes then always touch 64 different
+// sources, so their reaction terms (summed over the lane's K targets) go
+// into a per-wave LDS row with conflict-free ds_add_f32.  Workgroups pop
+// items from a device counter (persistent launch).  Forward sums land in
+// F[J][.][N], reactions in R[I][.][N]; a final kernel adds, per body, its
+// forward slots J >= block(b) and reaction slots I < block(b) in a fixed
+// order with Kahan compensation, so results are bitwise reproducible.
+#include "pair_core.h"
+
+namespace ptrom {
+namespace {
+
+constexpr float kFar = 1.0e15f;  // position of padding bodies (never coincides with a real one)
+
+// Forward and reaction terms of one pair; t: target data, s: source data.
+template <int OP>
+__device__ __forceinline__ void interact_sym(const float *t, const float *s, float d2, float *acc,
+                                             float *react) {
+  const float dx = t[0] - s[0];
+  const float dy = t[1] - s[1];
+  const float q = fmaf(dx, dx, fmaf(dy, dy, d2));
+  const float r = __builtin_amdgcn_rcpf(q);
+  if constexpr (OP == OP_VEL) {
+    const float gj = s[2] * r, gi = t[4] * r;
+    acc[0] = fmaf(-dy, gj, acc[0]);
+    acc[1] = fmaf(dx, gj, acc[1]);
+    react[0] = fmaf(dy, gi, react[0]);
+    react[1] = fmaf(-dx, gi, react[1]);
+  } else if constexpr (OP == OP_JVP) {
+    const float ex = t[2] - s[3];
+    const float ey = t[3] - s[4];
+    const float c = fmaf(dx, ex, dy * ey) * (r + r);
+    const float wx = fmaf(-c, dx, ex);
+    const float wy = fmaf(-c, dy, ey);
+    const float gj = s[2] * r, gi = t[4] * r;
+    acc[0] = fmaf(-gj, wy, acc[0]);
+    acc[1] = fmaf(gj, wx, acc[1]);
+    react[0] = fmaf(gi, wy, react[0]);
+    react[1] = fmaf(-gi, wx, react[1]);
+  } else {
+    const float qx = fmaf(s[2], t[2], -t[4] * s[3]);
+    const float qy = fmaf(s[2], t[3], -t[4] * s[4]);
+    const float c = fmaf(dx, qy, -dy * qx) * (r + r);
+    const float tx = r * fmaf(-c, dx, qy);
+    const float ty = r * fmaf(-c, dy, -qx);
+    acc[0] += tx;
+    acc[1] += ty;
+    react[0] -= tx;
+    react[1] -= ty;
+    acc[2] = fmaf(r, fmaf(s[3], dy, -s[4] * dx), acc[2]);
+    react[2] = fmaf(r, fmaf(t[3], dx, -t[2] * dy), react[2]);
+  }
+}
+
+__global__ void sym_reset_kernel(int *__restrict__ counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
+}
+
+template <int OP, int K>
+__global__ void __launch_bounds__(kBlock)
+    pair_sym_kernel(int n, const float *__restrict__ xy, const float *__restrict__ gam,
+                    const float *__restrict__ aux, float d2, int nb, int *__restrict__ counter,
+                    float *__restrict__ F, float *__restrict__ R) {
+  using T = Traits<OP>;
+  constexpr int NA = T::NACC, NS = T::NSRC;
+  constexpr int TB = kBlock * K;
+  __shared__ float4 s_a[64];
+  __shared__ float s_b[64];
+  __shared__ float racc[kBlock / 64][NA][64];
+  __shared__ float lds_diag[NS * kTile];
+  __shared__ int item_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (;;) {
+    if (tid == 0) item_s = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(item_s);
+    __syncthreads();
+    if (it >= nb * nb) break;
+    const int I = it / nb, J = it % nb;
+    if (J < I) continue;
+    const int tgt0 = I * TB;
+    if (J == I) {
+      float res[K][NA];
+      pair_block<OP, K, STAGE_LDS>(n, xy, gam, aux, d2, tgt0, tgt0, min(n, tgt0 + TB), lds_diag, res);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = tgt0 + k * kBlock + tid;
+        if (i < n)
+#pragma unroll
+          for (int a = 0; a < NA; ++a) F[(size_t)(J * NA + a) * n + i] = res[k][a];
+      }
+      continue;
+    }
+    // targets of block I: x, y, aux0, aux1, Gamma (padding: far away, no strength)
+    float tg[K][5];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tgt0 + k * kBlock + tid;
+      const bool ok = i < n;
+      tg[k][0] = ok ? xy[i] : 2.0f * kFar;
+      tg[k][1] = ok ? xy[n + i] : 2.0f * kFar;
+      if constexpr (NS == 5) {
+        tg[k][2] = ok ? aux[i] : 0.0f;
+        tg[k][3] = ok ? aux[n + i] : 0.0f;
+      } else {
+        tg[k][2] = tg[k][3] = 0.0f;
+      }
+      tg[k][4] = ok ? gam[i] : 0.0f;
+    }
+    float sum[K][NA], cmp[K][NA];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sum[k][a] = cmp[k][a] = 0.0f;
+
+    const int src0 = J * TB;
+    for (int u = 0; u < TB; u += 64) {
+      const int j0 = src0 + u;
+      if (j0 >= n) break;
+      __syncthreads();
+      if (tid < 64) {
+        const int j = j0 + tid;
+        const bool ok = j < n;
+        s_a[tid] = make_float4(ok ? xy[j] : kFar, ok ? xy[n + j] : kFar, ok ? gam[j] : 0.0f,
+                               (NS == 5 && ok) ? aux[j] : 0.0f);
+        s_b[tid] = (NS == 5 && ok) ? aux[n + j] : 0.0f;
+      }
+#pragma unroll
+      for (int a = 0; a < NA; ++a) racc[wave][a][lane] = 0.0f;
+      __syncthreads();
+      float part[K][NA];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) part[k][a] = 0.0f;
+#pragma unroll 2
+      for (int t = 0; t < 64; ++t) {
+        const int sidx = (lane + t) & 63;
+        const float4 A = s_a[sidx];
+        float s[5] = {A.x, A.y, A.z, A.w, s_b[sidx]};
+        float react[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) react[a] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) interact_sym<OP>(tg[k], s, d2, part[k], react);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) atomicAdd(&racc[wave][a][sidx], react[a]);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) kahan_add(sum[k][a], cmp[k][a], part[k][a]);
+      __syncthreads();
+      if (tid < 64 && j0 + tid < n) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          float s = 0.0f, c = 0.0f;
+#pragma unroll
+          for (int w = 0; w < kBlock / 64; ++w) kahan_add(s, c, racc[w][a][tid]);
+          R[(size_t)(I * NA + a) * n + j0 + tid] = s - c;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tgt0 + k * kBlock + tid;
+      if (i < n)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) F[(size_t)(J * NA + a) * n + i] = sum[k][a] - cmp[k][a];
+    }
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(256)
+    sym_reduce_kernel(int n, int tb, int nb, const float *__restrict__ F, const float *__restrict__ R,
+                      float *__restrict__ out, float *__restrict__ out2) {
+  constexpr int NA = Traits<OP>::NACC;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const int B = b / tb;
+  float v[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    float s = 0.0f, c = 0.0f;
+    for (int J = B; J < nb; ++J) kahan_add(s, c, F[(size_t)(J * NA + a) * n + b]);
+    for (int I = 0; I < B; ++I) kahan_add(s, c, R[(size_t)(I * NA + a) * n + b]);
+    v[a] = s - c;
+  }
+  store_final<OP>(n, b, v, out, out2);
+}
+
+template <int OP, int K>
+hipError_t launch_sym_t(int n, const float *xy, const float *gam, const float *aux, float d2,
+                        int grid, float *ws, float *out, float *out2, hipStream_t st) {
+  constexpr int NA = Traits<OP>::NACC;
+  const int tb = kBlock * K;
+  const int nb = (n + tb - 1) / tb;
+  float *F = ws;
+  float *R = ws + (size_t)nb * NA * n;
+  int *counter = reinterpret_cast<int *>(R + (size_t)nb * NA * n);
+  hipLaunchKernelGGL(sym_reset_kernel, dim3(1), dim3(64), 0, st, counter);
+  hipLaunchKernelGGL((pair_sym_kernel<OP, K>), dim3(grid), dim3(kBlock), 0, st, n, xy, gam, aux, d2, nb,
+                     counter, F, R);
+  hipLaunchKernelGGL(sym_reduce_kernel<OP>, dim3((n + 255) / 256), dim3(256), 0, st, n, tb, nb, F, R, out,
+                     out2);
+  return hipGetLastError();
+}
+
+template <int OP>
+hipError_t launch_sym_op(int k, int n, const float *xy, const float *gam, const float *aux, float d2,
+                         int grid, float *ws, float *out, float *out2, hipStream_t st) {
+  if (k == 2) return launch_sym_t<OP, 2>(n, xy, gam, aux, d2, grid, ws, out, out2, st);
+  if (k == 4) return launch_sym_t<OP, 4>(n, xy, gam, aux, d2, grid, ws, out, out2, st);
+  return launch_sym_t<OP, 1>(n, xy, gam, aux, d2, grid, ws, out, out2, st);
+}
+
+}  // namespace
+
+size_t pair_sym_ws_floats(int op, int k, int64_t n) {
+  const int64_t tb = kBlock * int64_t(k);
+  const int64_t nb = (n + tb - 1) / tb;
+  const int na = op == OP_VJP ? 3 : 2;
+  return size_t(2 * nb * na * n + 64);
+}
+
+hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64_t n64, const float *xy,
+                           const float *gamma, const float *aux, float delta, float *out, float *out2,
+                           float *ws, size_t ws_floats, hipStream_t stream) {
+  if (ws_floats < pair_sym_ws_floats(op, k, n64)) return hipErrorInvalidValue;
+  const int n = int(n64);
+  const float d2 = delta * delta;
+  const int grid = num_cus * (waves_per_simd < 1 ? 1 : waves_per_simd);
+  switch (op) {
+    case OP_VEL: return launch_sym_op<OP_VEL>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
+    case OP_JVP: return launch_sym_op<OP_JVP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
+    case OP_VJP: return launch_sym_op<OP_VJP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ptrom

@@ -1,7 +1,9 @@
 // Launch-parameter autotuner for the pair kernels: times every candidate
 // (source staging x targets per lane x occupancy target) on this device at a
 // ladder of sizes and keeps the fastest per (operation, size class).
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -11,7 +13,7 @@
 
 using namespace ptrom;
 
-static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp"};
+static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp", "stream_function"};
 
 extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
   if (!ctx || !path) return PTROM_EINVAL;
@@ -23,18 +25,22 @@ extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
     if (line.empty() || line[0] == '#') continue;
     std::istringstream ss(line);
     std::string name;
-    int cls, staging, k, waves;
+    int cls, staging, k, waves, sym = 0;
     if (!(ss >> name >> cls >> staging >> k >> waves)) continue;
+    std::string tok;
+    if (ss >> tok && tok[0] != '#') sym = std::atoi(tok.c_str());
     int op = -1;
     for (int q = 0; q < OP_COUNT; ++q)
       if (name == kOpNames[q]) op = q;
     if (op < 0 || (k != 1 && k != 2 && k != 4) || (staging != STAGE_LDS && staging != STAGE_SCALAR) ||
         waves < 1 || waves > 64)
       continue;
+    if (sym != 0 && sym != 1) continue;
     PairCfg c;
     c.staging = staging;
     c.k = k;
     c.waves_per_simd = waves;
+    c.sym = has_sym(op) ? sym : 0;
     ctx->tune.table[{op, cls}] = c;
     ++loaded;
   }
@@ -62,14 +68,14 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
   PTROM_CHECK_HIP(ctx, hipMalloc(&d, 5 * nmax * sizeof(float)));
   hipError_t e = hipMalloc(&o, 4 * nmax * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&o2, nmax * sizeof(float));
-  const size_t wsf = size_t(64) * 3 * nmax;  // generous bound on split partials
+  const size_t wsf = std::max(size_t(64) * 3 * nmax, pair_sym_ws_floats(OP_VJP, 2, nmax));  // split / pair-block partials
   if (e == hipSuccess) e = hipMalloc(&wsb, wsf * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(d, h.data(), 5 * nmax * sizeof(float), hipMemcpyHostToDevice);
   hipEvent_t a = nullptr, b = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   std::ostringstream report;
-  report << "# op size_class staging k waves_per_simd   (ms)\n";
+  report << "# op size_class staging k waves_per_simd sym   (ms)\n";
   for (int op = 0; op < OP_COUNT && e == hipSuccess; ++op) {
     for (int64_t n : sizes) {
       // gather the packed copies for this n
@@ -81,6 +87,7 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
       const float *xy = d, *gam = d + 2 * n, *aux = d + 3 * n;
       float best = 1e30f;
       PairCfg bestc;
+      std::vector<PairCfg> cands;
       for (int staging : {STAGE_LDS, STAGE_SCALAR})
         for (int k : {1, 2, 4})
           for (int waves : {4, 8, 16}) {
@@ -88,6 +95,19 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
             c.staging = staging;
             c.k = k;
             c.waves_per_simd = waves;
+            cands.push_back(c);
+          }
+      if (has_sym(op))
+        for (int k : {2, 4})
+          for (int waves : {2, 4, 8}) {
+            PairCfg c;
+            c.staging = STAGE_LDS;
+            c.k = k;
+            c.waves_per_simd = waves;
+            c.sym = 1;
+            cands.push_back(c);
+          }
+      for (const PairCfg &c : cands) {
             if (pair_ws_floats(op, c, ctx->num_cus, n) > wsf) continue;
             for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
               e = launch_pair(op, c, ctx->num_cus, n, xy, gam, aux, 0.01f, o, o2, wsb, wsf, nullptr);
@@ -110,7 +130,7 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
       const int cls = size_class(n);
       ctx->tune.table[{op, cls}] = bestc;
       report << kOpNames[op] << " " << cls << " " << bestc.staging << " " << bestc.k << " "
-             << bestc.waves_per_simd << "   # " << best << " ms at n=" << n << "\n";
+             << bestc.waves_per_simd << " " << bestc.sym << "   # " << best << " ms at n=" << n << "\n";
     }
   }
   if (a) hipEventDestroy(a);

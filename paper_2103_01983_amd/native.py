@@ -59,6 +59,8 @@ SIGNATURES = {
     "ptrom_jvp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp]),
     "ptrom_block_jacobian": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
     "ptrom_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp, _vp]),
+    "ptrom_stream_function": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
+    "ptrom_velocity_points": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _f32, _vp, _vp]),
     "ptrom_rk4": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _f32, ctypes.c_int, _vp]),
     "ptrom_rk4_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f64, _f64, ctypes.c_int, _vp]),
     "ptrom_implicit": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _f32, ctypes.c_int, ctypes.c_int,
@@ -74,8 +76,8 @@ SIGNATURES = {
     "ptrom_rom_destroy": (None, [_vp]),
     "ptrom_rom_hyperpair": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptrom_rom_run": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
-    "ptrom_cluster_build": (ctypes.c_int, [_i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _f64, _i64,
-                                           _vp, ctypes.POINTER(_vp)]),
+    "ptrom_cluster_build": (ctypes.c_int, [_i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
+                                           _f64, _f64, _i64, _vp, ctypes.POINTER(_vp)]),
     "ptrom_cluster_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "ptrom_cluster_fetch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptrom_cluster_destroy": (None, [_vp]),
@@ -131,6 +133,22 @@ def context(device=None) -> int:
     return _ctxs[idx]
 
 
+def make_context(device=0, tuning_path=None):
+    """A private library context (not the shared per-device one), optionally
+    with its own launch table; release with destroy_context."""
+    h = _vp()
+    rc = lib().ptrom_create(ctypes.byref(h), int(device))
+    if rc != PTROM_OK:
+        raise PtromError("ptrom_create(device=%d) failed with %d" % (device, rc))
+    if tuning_path:
+        _check(h, lib().ptrom_load_tuning(h, tuning_path.encode()), "ptrom_load_tuning")
+    return h
+
+
+def destroy_context(h):
+    lib().ptrom_destroy(h)
+
+
 def _check(ctx, rc, what, warn_ok=False):
     if rc == PTROM_OK or (warn_ok and rc == PTROM_ENOCONV):
         return rc
@@ -164,10 +182,10 @@ def _n(xy):
 
 # --------------------------------------------------------------- pair sums
 
-def velocity(xy, gamma, delta, out=None):
+def velocity(xy, gamma, delta, out=None, ctx=None):
     n = _n(xy)
     out = torch.empty_like(xy) if out is None else out
-    c = context(xy.device)
+    c = context(xy.device) if ctx is None else ctx
     _check(c, lib().ptrom_velocity(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
                                    _ptr(gamma, torch.float32, n, "gamma"), float(delta),
                                    _ptr(out, torch.float32, 2 * n, "out"), _stream(xy)), "ptrom_velocity")
@@ -185,20 +203,20 @@ def velocity_f64(xy, gamma, delta, out=None):
     return out
 
 
-def jvp(xy, gamma, delta, v, out=None):
+def jvp(xy, gamma, delta, v, out=None, ctx=None):
     n = _n(xy)
     out = torch.empty_like(xy) if out is None else out
-    c = context(xy.device)
+    c = context(xy.device) if ctx is None else ctx
     _check(c, lib().ptrom_jvp(c, n, _ptr(xy, torch.float32, 2 * n, "xy"), _ptr(gamma, torch.float32, n, "gamma"),
                               float(delta), _ptr(v, torch.float32, 2 * n, "v"),
                               _ptr(out, torch.float32, 2 * n, "out"), _stream(xy)), "ptrom_jvp")
     return out
 
 
-def block_jacobian(xy, gamma, delta, out=None):
+def block_jacobian(xy, gamma, delta, out=None, ctx=None):
     n = _n(xy)
     out = torch.empty(4 * n, dtype=torch.float32, device=xy.device) if out is None else out
-    c = context(xy.device)
+    c = context(xy.device) if ctx is None else ctx
     _check(c, lib().ptrom_block_jacobian(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
                                          _ptr(gamma, torch.float32, n, "gamma"), float(delta),
                                          _ptr(out, torch.float32, 4 * n, "out"), _stream(xy)),
@@ -206,16 +224,46 @@ def block_jacobian(xy, gamma, delta, out=None):
     return out
 
 
-def vjp(xy, gamma, delta, w, gxy=None, ggamma=None):
+def vjp(xy, gamma, delta, w, gxy=None, ggamma=None, ctx=None):
     n = _n(xy)
     gxy = torch.empty_like(xy) if gxy is None else gxy
     ggamma = torch.empty_like(gamma) if ggamma is None else ggamma
-    c = context(xy.device)
+    c = context(xy.device) if ctx is None else ctx
     _check(c, lib().ptrom_vjp(c, n, _ptr(xy, torch.float32, 2 * n, "xy"), _ptr(gamma, torch.float32, n, "gamma"),
                               float(delta), _ptr(w, torch.float32, 2 * n, "w"),
                               _ptr(gxy, torch.float32, 2 * n, "gxy"), _ptr(ggamma, torch.float32, n, "ggamma"),
                               _stream(xy)), "ptrom_vjp")
     return gxy, ggamma
+
+
+def stream_function(xy, gamma, delta, out=None, ctx=None):
+    """psi_i = -(1/4pi) sum_{j!=i} Gamma_j log(|r|^2+delta^2); H = 1/2 sum Gamma_i psi_i."""
+    n = _n(xy)
+    out = torch.empty_like(gamma) if out is None else out
+    c = context(xy.device) if ctx is None else ctx
+    _check(c, lib().ptrom_stream_function(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
+                                          _ptr(gamma, torch.float32, n, "gamma"), float(delta),
+                                          _ptr(out, torch.float32, n, "psi"), _stream(xy)), "ptrom_stream_function")
+    return out
+
+
+def hamiltonian(xy, gamma, delta):
+    """Regularized Hamiltonian 1/2 sum_i Gamma_i psi_i (the final sum in FP64 on the device)."""
+    psi = stream_function(xy, gamma, delta)
+    return 0.5 * torch.dot(gamma.double(), psi.double())
+
+
+def velocity_points(points, xy, gamma, delta, out=None):
+    """Velocity at arbitrary points [2][nt] (SoA) induced by all bodies."""
+    n = _n(xy)
+    nt = _n(points)
+    out = torch.empty_like(points) if out is None else out
+    c = context(xy.device)
+    _check(c, lib().ptrom_velocity_points(c, nt, _ptr(points, torch.float32, 2 * nt, "points"), n,
+                                          _ptr(xy, torch.float32, 2 * n, "xy"), _ptr(gamma, torch.float32, n, "gamma"),
+                                          float(delta), _ptr(out, torch.float32, 2 * nt, "out"), _stream(xy)),
+           "ptrom_velocity_points")
+    return out
 
 
 # --------------------------------------------------------------- steppers
@@ -396,8 +444,11 @@ class Rom:
 
 # --------------------------------------------------------------- offline helpers
 
-def cluster_build(wpts, xy0, phi, gamma, max_level, pc, targets):
-    """Host quadtree + neighbour-search clustering (native).  Returns dict with
+NEIGHBOR, BARNES_HUT = 0, 1
+
+
+def cluster_build(wpts, xy0, phi, gamma, max_level, pc, targets, criterion=NEIGHBOR, theta=0.0):
+    """Host quadtree + source clustering (native).  Returns dict with
     xqt0 [Nc,2], Phit [Nc,2,M], Gt [Nc], off [nt+1], ids [nnz], keys [Nc]."""
     wpts = np.ascontiguousarray(wpts, dtype=np.float64)
     xy0 = np.ascontiguousarray(xy0, dtype=np.float64)
@@ -411,8 +462,8 @@ def cluster_build(wpts, xy0, phi, gamma, max_level, pc, targets):
     h = _vp()
     L = lib()
     rc = L.ptrom_cluster_build(n, wpts.ctypes.data_as(_vp), xy0.ctypes.data_as(_vp), phi.ctypes.data_as(_vp), M,
-                               gamma.ctypes.data_as(_vp), int(max_level), float(pc), targets.size,
-                               targets.ctypes.data_as(_vp), ctypes.byref(h))
+                               gamma.ctypes.data_as(_vp), int(max_level), int(criterion), float(pc), float(theta),
+                               targets.size, targets.ctypes.data_as(_vp), ctypes.byref(h))
     if rc != PTROM_OK:
         raise PtromError("ptrom_cluster_build failed (%d)" % rc)
     try:

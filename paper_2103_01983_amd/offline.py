@@ -68,9 +68,9 @@ def sample_rows(sample, n):
     return np.concatenate([s, n + s])
 
 
-def artifacts(sample, wpts, xy0, Phi_h, gamma, depth, pc, delta, dt, A):
+def artifacts(sample, wpts, xy0, Phi_h, gamma, depth, pc, delta, dt, A, criterion=native.NEIGHBOR, theta=0.0):
     n = gamma.size
-    cl = native.cluster_build(wpts, xy0, Phi_h, gamma, depth, pc, sample)
+    cl = native.cluster_build(wpts, xy0, Phi_h, gamma, depth, pc, sample, criterion, theta)
     rows = sample_rows(sample, n)
     return dict(M=Phi_h.shape[1], Mr=A.shape[0], sample=np.asarray(sample), Phibar=Phi_h[rows].copy(),
                 xbar0=np.asarray(xy0)[rows].copy(), xqt0=cl["xqt0"], Phit=cl["Phit"], Gt=cl["Gt"],
@@ -163,7 +163,7 @@ def greedy_sample(Phi_r, ns):
 
 
 def train(cloud, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, jac_mode=native.JAC_PAPER,
-          center=False, device=None):
+          center=False, device=None, criterion=native.NEIGHBOR, theta=0.0):
     """Stages 1-4 on one GPU.  Returns (artifacts, info)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
     t = {}
@@ -187,7 +187,7 @@ def train(cloud, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, 
 
     t0 = time.perf_counter()
     dummy_A = np.zeros((M, 2 * n))
-    art2 = artifacts(np.arange(n), wpts, xy0_h, Phi_h, g_h, depth, pc, d, dt, dummy_A)
+    art2 = artifacts(np.arange(n), wpts, xy0_h, Phi_h, g_h, depth, pc, d, dt, dummy_A, criterion, theta)
     t["stage2_cluster_s"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     R, hist2, it2 = tier2(art2, nsnap, tol, max_iter, jac_mode=jac_mode, device=dev)
@@ -200,7 +200,7 @@ def train(cloud, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, 
     t0 = time.perf_counter()
     sample = greedy_sample(Phi_r, ns)
     A = np.linalg.pinv(Phi_r[sample_rows(sample, n)])
-    art = artifacts(sample, wpts, xy0_h, Phi_h, g_h, depth, pc, d, dt, A)
+    art = artifacts(sample, wpts, xy0_h, Phi_h, g_h, depth, pc, d, dt, A, criterion, theta)
     t["stage4_s"] = time.perf_counter() - t0
 
     # reproduction quality of the Tier-II model (reported, not a gate)

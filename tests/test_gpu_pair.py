@@ -123,3 +123,22 @@ def test_invalid_arguments_raise(dev):
         native.velocity(xd, gd, -1.0)
     with pytest.raises(ValueError):
         native.velocity(xd, gd.double(), 0.1)
+
+
+@pytest.mark.parametrize("n,delta", [(2, 0.0), (257, 0.0), (4099, 0.01)])
+def test_stream_function_parity(dev, n, delta):
+    xy, g, d = cloud(n, 500 + n, "gauss", delta)
+    xd, gd = to_dev(xy, dev), to_dev(g, dev)
+    psi = native.stream_function(xd, gd, d).cpu().numpy()
+    assert rel(psi, oracle.stream_function(xy, g, float(d))) <= 1e-5
+    H = native.hamiltonian(xd, gd, d).item()
+    Ho = oracle.hamiltonian(xy, g, float(d))
+    assert abs(H - Ho) <= 1e-5 * abs(Ho)
+
+
+def test_velocity_points_parity(dev):
+    xy, g, d = cloud(3000, 77, "disk", 0.01)
+    rng = np.random.default_rng(5)
+    pts = f32(np.concatenate([rng.uniform(-1.2, 1.2, 1000), rng.uniform(-1.2, 1.2, 1000)]))
+    f = native.velocity_points(to_dev(pts, dev), to_dev(xy, dev), to_dev(g, dev), d).cpu().numpy()
+    assert rel(f, oracle.velocity_points(pts, xy, g, float(d))) <= 1e-5

@@ -50,3 +50,32 @@ def test_cluster_rejects_bad_input():
     P = oo.weighted_points(Phi, sigma)
     with pytest.raises(native.PtromError):
         native.cluster_build(P, cl.xy, Phi, cl.gamma, 6, 1.0, np.array([0, 50]))
+
+
+@pytest.mark.parametrize("n,theta,depth", [(200, 0.5, 6), (300, 1.0, 5), (128, 2.0, 6)])
+def test_barnes_hut_lists_match_oracle(n, theta, depth):
+    cl, Phi, sigma = setup(n, 50 + n)
+    P = oo.weighted_points(Phi, sigma)
+    tree = oo.QuadTree(P, depth)
+    targets = np.arange(1, n, 4)
+    ox, oP, oG, ooff, oids, okeys = oo.cluster_artifacts(tree, targets, 0.0, cl.xy, Phi, cl.gamma,
+                                                          criterion="barnes-hut", theta=theta)
+    r = native.cluster_build(np.ascontiguousarray(P), cl.xy, Phi, cl.gamma, depth, 0.0, targets,
+                             native.BARNES_HUT, theta)
+    assert np.array_equal(r["off"], ooff)
+    assert np.array_equal(r["ids"], oids)
+    np.testing.assert_allclose(r["Phit"], oP, rtol=0, atol=1e-13)
+
+
+def test_barnes_hut_theta_zero_is_exact_and_lists_cover_all():
+    cl, Phi, sigma = setup(150, 9)
+    P = oo.weighted_points(Phi, sigma)
+    tree = oo.QuadTree(P, 6)
+    keys_nodes = {nd.key: nd for nd in tree.nodes}
+    for i in [0, 70, 149]:
+        assert sorted(k[1] for k in oo.find_clusters(tree, i, 0.0, "barnes-hut", 0.0, cl.gamma)) == \
+            [j for j in range(150) if j != i]
+        members = []
+        for k in oo.find_clusters(tree, i, 0.0, "barnes-hut", 1.5, cl.gamma):
+            members.extend([k[1]] if k[0] == 0 else keys_nodes[k].members)
+        assert sorted(members) == [j for j in range(150) if j != i]

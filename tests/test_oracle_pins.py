@@ -345,3 +345,50 @@ def test_lstsq_matches_numpy():
         G = rng.standard_normal((m, n)); b = rng.standard_normal(m)
         x = oracle.lstsq(G, b)
         np.testing.assert_allclose(x, np.linalg.lstsq(G, b, rcond=None)[0], rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------- stream function, field points
+
+def test_stream_function_gradient_is_velocity():
+    # f_i = (d psi_i / d y_i, -d psi_i / d x_i) with the sources held fixed
+    cl = W.gaussian_patch(90, seed=13, delta=0.03)
+    xy, g, d = cl.xy, cl.gamma * 90, cl.delta
+    n = g.size
+    f = oracle.velocity(xy, g, d)
+    h = 1e-6
+    for i in [0, 41, 89]:
+        e = np.zeros(2 * n)
+        e[n + i] = h
+        dpsi_dy = (oracle.stream_function(xy + e, g, d)[i] - oracle.stream_function(xy - e, g, d)[i]) / (2 * h)
+        e[:] = 0.0
+        e[i] = h
+        dpsi_dx = (oracle.stream_function(xy + e, g, d)[i] - oracle.stream_function(xy - e, g, d)[i]) / (2 * h)
+        assert dpsi_dy == pytest.approx(f[i], rel=1e-7, abs=1e-9)
+        assert -dpsi_dx == pytest.approx(f[n + i], rel=1e-7, abs=1e-9)
+
+
+def test_stream_function_two_bodies_and_hamiltonian():
+    xy = np.array([0.0, 0.6, 0.0, 0.8])          # d = 1
+    g = np.array([1.5, -0.7])
+    psi = oracle.stream_function(xy, g, 0.5)
+    np.testing.assert_allclose(psi, [0.7 / (4 * math.pi) * math.log(1.25), -1.5 / (4 * math.pi) * math.log(1.25)],
+                               rtol=1e-15)
+    cl = W.disk_cloud(150, seed=6)
+    H = 0.5 * np.dot(cl.gamma, oracle.stream_function(cl.xy, cl.gamma, 0.02))
+    assert H == pytest.approx(oracle.hamiltonian(cl.xy, cl.gamma, 0.02), rel=1e-12)
+
+
+def test_velocity_at_points_matches_bodies_and_far_field():
+    cl = W.gaussian_patch(120, seed=17, delta=0.02)
+    n = cl.n
+    # a point placed on a zero-strength body reproduces that body's velocity
+    g = cl.gamma.copy()
+    g[5] = 0.0
+    p = np.array([cl.xy[5], cl.xy[n + 5]])
+    fp = oracle.velocity_points(p, cl.xy, g, cl.delta)
+    f = oracle.velocity(cl.xy, g, cl.delta)
+    np.testing.assert_allclose(fp, [f[5], f[n + 5]], rtol=1e-13)
+    # far away the field is that of a point vortex of the total circulation at the centroid
+    R = 1e4
+    fp = oracle.velocity_points(np.array([R, 0.0]), cl.xy, cl.gamma, cl.delta)
+    assert fp[1] == pytest.approx(cl.gamma.sum() / (2 * math.pi * R), rel=1e-3)
