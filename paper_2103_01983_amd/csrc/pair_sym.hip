@@ -11,13 +11,15 @@
 //
 // Inside an off-diagonal item a workgroup stages 64 sources of block J in
 // LDS and each wave sweeps them in 64 steps, lane l taking source
-// (l + t) mod 64 at step t: the 64 lanes then always touch 64 different
-// sources, so their reaction terms (summed over the lane's K targets) go
-// into a per-wave LDS row with conflict-free ds_add_f32.  Workgroups pop
-// items from a device counter (persistent launch).  Forward sums land in
-// F[J][.][N], reactions in R[I][.][N]; a final kernel adds, per body, its
-// forward slots J >= block(b) and reaction slots I < block(b) in a fixed
-// order with Kahan compensation, so results are bitwise reproducible.
+// (l + t) mod 64 at step t.  The reaction accumulators travel with their
+// sources: every step rotates them one lane to the left inside the add
+// (v_add_f32 with the DPP wave_rol:1 modifier), so after the sweep lane l
+// holds the complete reaction on source (l - 1) mod 64 and no per-step
+// shared-memory traffic is needed.  Workgroups pop items from a device
+// counter (persistent launch).  Forward sums land in F[J][.][N], reactions
+// in R[I][.][N]; a final kernel adds, per body, its forward slots
+// J >= block(b) and reaction slots I < block(b) in a fixed order with Kahan
+// compensation, so results are bitwise reproducible.
 #include "pair_core.h"
 
 namespace ptrom {
@@ -65,6 +67,12 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
   }
 }
 
+// lane l receives lane (l + 1) mod 64's value, added to `add`
+__device__ __forceinline__ float rotate_add(float v, float add) {
+  const int r = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134 /* wave_rol:1 */, 0xF, 0xF, false);
+  return __builtin_bit_cast(float, r) + add;
+}
+
 __global__ void sym_reset_kernel(int *__restrict__ counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
@@ -79,7 +87,7 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int TB = kBlock * K;
   __shared__ float4 s_a[64];
   __shared__ float s_b[64];
-  __shared__ float racc[kBlock / 64][NA][64];
+  __shared__ float racc_lds[kBlock / 64][NA][64];
   __shared__ float lds_diag[NS * kTile];
   __shared__ int item_s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -139,14 +147,14 @@ __global__ void __launch_bounds__(kBlock)
                                (NS == 5 && ok) ? aux[j] : 0.0f);
         s_b[tid] = (NS == 5 && ok) ? aux[n + j] : 0.0f;
       }
-#pragma unroll
-      for (int a = 0; a < NA; ++a) racc[wave][a][lane] = 0.0f;
       __syncthreads();
-      float part[K][NA];
+      float part[K][NA], racc[NA];
 #pragma unroll
       for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int a = 0; a < NA; ++a) part[k][a] = 0.0f;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) racc[a] = 0.0f;
 #pragma unroll 2
       for (int t = 0; t < 64; ++t) {
         const int sidx = (lane + t) & 63;
@@ -158,8 +166,11 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
         for (int k = 0; k < K; ++k) interact_sym<OP>(tg[k], s, d2, part[k], react);
 #pragma unroll
-        for (int a = 0; a < NA; ++a) atomicAdd(&racc[wave][a][sidx], react[a]);
+        for (int a = 0; a < NA; ++a) racc[a] = rotate_add(racc[a], react[a]);
       }
+      // lane l now holds the reaction on source (l - 1) mod 64
+#pragma unroll
+      for (int a = 0; a < NA; ++a) racc_lds[wave][a][(lane + 63) & 63] = racc[a];
 #pragma unroll
       for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -170,7 +181,7 @@ __global__ void __launch_bounds__(kBlock)
         for (int a = 0; a < NA; ++a) {
           float s = 0.0f, c = 0.0f;
 #pragma unroll
-          for (int w = 0; w < kBlock / 64; ++w) kahan_add(s, c, racc[w][a][tid]);
+          for (int w = 0; w < kBlock / 64; ++w) kahan_add(s, c, racc_lds[w][a][tid]);
           R[(size_t)(I * NA + a) * n + j0 + tid] = s - c;
         }
       }
