@@ -32,9 +32,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3
-# algorithmic FP32 work per pair interaction (FMA = 2, reciprocal = 1), counted
-# from the formulas the kernels evaluate
+# algorithmic FP32 work per ordered pair interaction (FMA = 2, reciprocal = 1),
+# counted from the one-sided formulas the kernels evaluate
 FLOP_PER_PAIR = {"velocity": 12, "jvp": 23, "vjp": 31, "block_jacobian": 22}
+# FP32 work the each-unordered-pair-once kernels execute per UNORDERED pair:
+# the shared distance/reciprocal terms once, the forward and reaction
+# accumulations, and the per-step lane rotation of the reaction accumulators
+SYM_FLOP_PER_UNORDERED_PAIR = {"velocity": 19, "jvp": 30, "vjp": 41}
+PAIR_SOURCES = ("pair_core.h", "pair.hip", "pair_sym.hip")
+OP_ID = {"velocity": 0, "block_jacobian": 1, "jvp": 2, "vjp": 3, "stream_function": 4}
 
 
 def log(*a):
@@ -123,25 +129,9 @@ def main():
 
     jvp_ms = float(np.mean(timings["jvp"]))
     vel_ms = float(np.mean(timings["velocity"]))
-    roof = {
-        "bound": "alu",
-        "kernel": "pair_kernel<jvp> (Jacobian-vector product, N=65536)",
-        "achieved": FLOP_PER_PAIR["jvp"] * pairs / (jvp_ms * 1e-3) / 1e12,
-        "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s",
-        "avg_launch_ms": jvp_ms,
-        "flop_per_pair": FLOP_PER_PAIR["jvp"],
-        "traffic": None,
-    }
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_for("jvp")
-    roof_vel = {
-        "kernel": "pair_kernel<velocity> (N=65536)",
-        "achieved": FLOP_PER_PAIR["velocity"] * pairs / (vel_ms * 1e-3) / 1e12,
-        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "avg_launch_ms": vel_ms,
-        "pairs_per_s": pairs / (vel_ms * 1e-3), "flop_per_pair": FLOP_PER_PAIR["velocity"],
-    }
-    roof_vel["frac"] = roof_vel["achieved"] / roof_vel["peak"]
+    roof = roofline_entry(native, "jvp", n, pairs, jvp_ms)
+    roof_vel = roofline_entry(native, "velocity", n, pairs, vel_ms)
+    roof_vel["pairs_per_s"] = pairs / (vel_ms * 1e-3)
 
     out = {
         "metric": "Biot-Savart pair-interactions/s at <=1e-5 rel err; batched & adjoint vs plain",
@@ -189,21 +179,63 @@ def copy_calibration():
     return 0
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+def kernel_names(op, cfg):
+    """Kernels one launch of pair operation ``op`` runs under launch ``cfg``."""
+    o = OP_ID[op]
+    if cfg["sym"]:
+        return ["sym_reset_kernel", f"pair_sym_kernel<{o}, {cfg['k']}>", f"sym_reduce_kernel<{o}>"]
+    names = [f"pair_kernel<{o}, {cfg['k']}, {cfg['staging']}>"]
+    if cfg["splits"] > 1:
+        names.append(f"reduce_kernel<{o}>")
+    return names
+
+
+def roofline_entry(native, op, n, pairs, launch_ms):
+    """Roofline record of one pair-operation launch timed with HIP events on
+    its stream (all kernels of the launch)."""
+    cfg = native.pair_config(op, n)
+    ach = FLOP_PER_PAIR[op] * pairs / (launch_ms * 1e-3) / 1e12
+    r = {
+        "bound": "alu",
+        "kernel": " + ".join(kernel_names(op, cfg)) + f" ({op}, N={n})",
+        "launch": cfg,
+        "achieved": ach,
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": ach / PEAK_FP32_TFLOPS,
+        "avg_launch_ms": launch_ms,
+        "flop_per_pair": FLOP_PER_PAIR[op],
+        "traffic": traffic_for(op, cfg),
+    }
+    if cfg["sym"]:
+        ex = SYM_FLOP_PER_UNORDERED_PAIR[op] * pairs / 2 / (launch_ms * 1e-3) / 1e12
+        r["executed_flop_per_unordered_pair"] = SYM_FLOP_PER_UNORDERED_PAIR[op]
+        r["executed_tflops"] = ex
+        r["executed_frac"] = ex / PEAK_FP32_TFLOPS
+    return r
+
+
+def pair_source_sha():
+    from hashlib import sha256
+    h = sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_01983_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(op, cfg):
+    """HBM bytes per launch (all kernels of the launch) from committed
+    rocprofv3 counter runs, if they were taken on the current pair-kernel
+    sources and the same launch configuration."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    from hashlib import sha256
-    src = os.path.join(ROOT, "paper_2103_01983_amd", "csrc", "pair_core.h")
-    with open(src, "rb") as fh:
-        h = sha256(fh.read()).hexdigest()[:16]
-    ent = t.get(kernel)
-    if not ent or ent.get("source_sha") != h:
+    ent = t.get(op)
+    if not ent or ent.get("source_sha") != pair_source_sha() or ent.get("launch") != cfg:
         return None
     return ent.get("bytes_per_launch")
 
@@ -315,7 +347,38 @@ def rom_form(native, W, dev, timed):
     res["mae_d_time_avg"] = float(np.mean(mae))
     res["mae_d_final"] = float(mae[-1])
     res["final_rel_state_err"] = float(np.linalg.norm(xr[-1] - S[-1]) / np.linalg.norm(S[-1] - x0))
+    res["gather_sweep"] = gather_sweep(native, offline, info, cl, art, dev, timed)
     return res
+
+
+def gather_sweep(native, offline, info, cl, art, dev, timed):
+    """HyperPair gather over growing sample sets (random bodies; same tree,
+    basis and clustering): HBM bytes streamed per evaluation / time."""
+    import torch
+    n = cl.n
+    rng = np.random.default_rng(11)
+    xy0 = np.asarray(cl.xy, np.float32).astype(np.float64)
+    g = np.asarray(cl.gamma, np.float32).astype(np.float64)
+    out = []
+    for ns in (16, 256, 2048, 16384):
+        sample = np.arange(n) if ns >= n else np.sort(rng.choice(n, ns, replace=False))
+        A = np.zeros((art["M"], 2 * sample.size))
+        a = offline.artifacts(sample, info["wpts"], xy0, info["Phi"], g, 6, 1.0, cl.delta, art["dt"], A)
+        rom = native.Rom(a)
+        M, nd = a["M"], 2 * sample.size
+        xh = torch.zeros(M, dtype=torch.float64, device=dev)
+        prev = torch.zeros(nd, dtype=torch.float64, device=dev)
+        rom.hyperpair(xh, prev, prev)
+        reps = 20
+        sec = timed(lambda: rom.hyperpair(xh, prev, prev), reps=reps)
+        nnz = int(a["ids"].size)
+        ew = 4 + (2 * M + 3) // 4 * 4
+        # entry rows, offsets, sampled rows and previous-step rows read; xbar, fbar, rbar, C written
+        byts = nnz * ew * 4 + (sample.size + 1) * 4 + nd * (M + 1) * 4 + 5 * nd * 8 + nd * M * 8
+        out.append({"ns": int(sample.size), "nnz": nnz, "us": sec * 1e6, "bytes": byts,
+                    "GB_per_s": byts / sec / 1e9, "pairs_per_s": nnz / sec})
+        rom.close()
+    return out
 
 
 def cpu_baseline(cl, f_gpu, native, x0, g, d):

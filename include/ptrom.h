@@ -310,6 +310,23 @@ int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path);
 /* Load tuned parameters written by ptrom_autotune. */
 int ptrom_load_tuning(ptrom_ctx *ctx, const char *cache_path);
 
+/* Pair-kernel operations, as named in the tuning file. */
+enum {
+  PTROM_OP_VELOCITY = 0,
+  PTROM_OP_BLOCK_JACOBIAN = 1,
+  PTROM_OP_JVP = 2,
+  PTROM_OP_VJP = 3,
+  PTROM_OP_STREAM_FUNCTION = 4
+};
+
+/* The launch the context would use for operation op at n bodies, written to
+ * the caller's HOST array out[5]: source staging (0 LDS tiles, 1 scalar
+ * cache), targets per lane, waves per SIMD, each-unordered-pair-once form
+ * (0/1), and the number of source chunks of the one-sided form (0 for the
+ * each-pair-once form).  Host only; EINVAL for an unknown op or n outside
+ * [1, 2^30]. */
+int ptrom_pair_config(ptrom_ctx *ctx, int op, int64_t n, int32_t *out);
+
 #ifdef __cplusplus
 }
 #endif

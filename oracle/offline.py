@@ -27,8 +27,11 @@ notes):
   - weighted means use |Gamma| as weights (so mixed-sign cells stay
     defined); the surrogate strength is the plain sum of Gamma;
   - neighbour test as in the checkPrune listing (source cell bounds, strict
-    inequalities); a cell that holds the target is never pruned; an unpruned
-    leaf is expanded into its bodies, the target itself excluded;
+    inequalities); a cell that holds the target is never pruned; nor is a
+    cell whose surrogate sits on the target at x^0 (rounding allowance
+    1e-9 (1 + |x_i|)); an unpruned leaf is expanded into its bodies, the
+    target itself excluded;
+  - a POD mode's sign makes its largest-magnitude entry positive;
   - the greedy loop processes the residual basis in n_it groups and, after
     the first group, uses the gappy-POD reconstruction error of each group
     from the already-processed vectors on the current sample; ties go to the
@@ -58,10 +61,15 @@ def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap):
 
 def pod(S, M, x0=None):
     """Phi = first M left singular vectors of S (or of S - x0 1^T); returns
-    (Phi [Nd, M], sigma [M])."""
+    (Phi [Nd, M], sigma [M]).  Each mode's sign makes its entry of largest
+    magnitude positive (the lowest row on ties), so W_phi is reproducible."""
     A = S if x0 is None else S - np.asarray(x0)[:, None]
     U, s, _ = np.linalg.svd(A, full_matrices=False)
-    return U[:, :M].copy(), s[:M].copy()
+    Phi = U[:, :M].copy()
+    for m in range(M):
+        if Phi[np.argmax(np.abs(Phi[:, m])), m] < 0.0:
+            Phi[:, m] = -Phi[:, m]
+    return Phi, s[:M].copy()
 
 
 def weighted_points(Phi, sigma):
@@ -148,13 +156,29 @@ def weighted_point_mean(tree, node, gamma):
     return (w[:, None] * tree.P[idx]).sum(axis=0) / w.sum()
 
 
-def find_clusters(tree, i, pc, criterion="neighbor", theta=0.0, gamma=None):
+def coincides(node, i, xy0, gamma):
+    """True when the cell's surrogate (|Gamma|-weighted mean of its members'
+    initial positions) lies on body i's initial position, to within 1e-9 of
+    (1 + |x_i|).  At delta = 0 such a pair has no defined velocity."""
+    n = gamma.size
+    idx = np.asarray(node.members)
+    w = np.abs(gamma[idx])
+    if w.sum() == 0.0:
+        w = np.ones_like(w)
+    w = w / w.sum()
+    sx, sy = float(np.dot(w, xy0[idx])), float(np.dot(w, xy0[n + idx]))
+    xi, yi = float(xy0[i]), float(xy0[n + i])
+    return np.hypot(sx - xi, sy - yi) <= 1e-9 * (1.0 + np.hypot(xi, yi))
+
+
+def find_clusters(tree, i, pc, criterion="neighbor", theta=0.0, gamma=None, xy0=None):
     """Cluster keys seen by target body i (FindClusters / Traverse with
     checkPrune).  criterion "neighbor": prune a cell that does not overlap the
     target leaf grown by pc times its width; "barnes-hut": prune when
     w / |s - s_i| <= theta, s the cell's weighted mean point and s_i the
-    target's point.  Keys: (0, j, 0, 0) for a single body j, node.key for an
-    agglomerated cell."""
+    target's point.  With ``xy0`` (initial positions) a cell whose surrogate
+    coincides with the target there is opened instead of pruned.  Keys:
+    (0, j, 0, 0) for a single body j, node.key for an agglomerated cell."""
     leaf = tree.leaf_of[i]
     w = leaf.width
     h_lo = leaf.lo - pc * w
@@ -172,6 +196,8 @@ def find_clusters(tree, i, pc, criterion="neighbor", theta=0.0, gamma=None):
         if node.level <= leaf.level and (leaf.ix >> (leaf.level - node.level)) == node.ix \
                 and (leaf.iy >> (leaf.level - node.level)) == node.iy:
             ov = True  # the cell holds the target
+        if not ov and xy0 is not None and len(node.members) > 1 and coincides(node, i, xy0, gamma):
+            ov = True
         if not ov:
             if len(node.members) == 1:
                 out.append((0, node.members[0], 0, 0))
@@ -193,7 +219,7 @@ def cluster_artifacts(tree, targets, pc, xy0, Phi, gamma, criterion="neighbor", 
     (xqt0 [Nc,2], Phit [Nc,2,M], Gt [Nc], off [nt+1], ids [nnz], keys)."""
     n = gamma.size
     M = Phi.shape[1]
-    lists = [find_clusters(tree, int(i), pc, criterion, theta, gamma) for i in targets]
+    lists = [find_clusters(tree, int(i), pc, criterion, theta, gamma, np.asarray(xy0, float)) for i in targets]
     keys = sorted(set(k for L in lists for k in L))
     index = {k: c for c, k in enumerate(keys)}
     by_key = {nd.key: nd for nd in tree.nodes}

@@ -495,7 +495,8 @@ typedef struct {
   double delta, dt;
 } or_rom;
 
-/* One HyperPair evaluation at generalized coordinates xhat.
+/* One HyperPair evaluation at generalized coordinates xhat (source clustering
+ * with the Biot-Savart kernel of the governing equations).
  * Outputs: xbar[nd] (sampled positions), fbar[nd] (sampled velocities),
  * rbar[nd] (trapezoid residual rows), C[nd][M] (residual Jacobian times Phi). */
 static void rom_hyperpair(const or_rom *R, const double *xhat, const double *xbar_prev,
@@ -526,6 +527,11 @@ static void rom_hyperpair(const or_rom *R, const double *xhat, const double *xba
       const int64_t c = R->ids[e];
       const double rx = tx - p[2 * c], ry = ty - p[2 * c + 1];
       const double s = rx * rx + ry * ry + d2;
+      /* A surrogate can sit exactly on its target when delta = 0 (its
+       * Gamma-weighted mean is taken in physical space, its cell was chosen
+       * in the weighted POD space): such a pair, like the self pair, adds
+       * neither velocity nor Jacobian. */
+      if (s == 0.0) continue;
       const double g = R->Gt[c] / OR_TWO_PI;
       fx += g * (-ry) / s;
       fy += g * rx / s;

@@ -14,9 +14,11 @@
 // weighted means use |Gamma| (plain mean when all weights vanish) and the
 // surrogate strength is the sum of Gamma; a source cell is pruned when it
 // does not overlap the target leaf grown by pc times its width on every side
-// (strict inequalities) and does not hold the target; an unpruned leaf is
-// expanded into its bodies without the target; a pruned cell holding one
-// body is that body.  Unique surrogates are ordered bodies first (by index)
+// (strict inequalities) and does not hold the target; a cell whose weighted
+// mean initial position coincides with the target's (within 1e-9 of the
+// target's distance from the origin, plus 1e-9) is never pruned either; an
+// unpruned leaf is expanded into its bodies without the target; a pruned
+// cell holding one body is that body.  Unique surrogates are ordered bodies first (by index)
 // then cells (by level, row, column); each list is sorted by surrogate id.
 #include <algorithm>
 #include <cmath>
@@ -107,8 +109,14 @@ struct PruneRule {
   double theta;
   double hlo[2], hhi[2];  // neighbourhood of the target leaf
   double si[2];           // target point
+  double xi[2], tol;      // target's initial physical position, coincidence radius
   const std::vector<double> *mean;  // per node weighted mean point [2]
+  const std::vector<double> *phys;  // per node weighted mean initial position [2]
 };
+
+// A surrogate whose position at x^0 is the target's own (to rounding) would
+// make the pair singular at delta = 0; such a cell is opened instead.
+constexpr double kCoincide = 1e-9;
 
 void traverse(const QTree &T, int node, int target, const PruneRule &pr, const QNode &leaf,
               std::vector<int64_t> &out) {
@@ -124,6 +132,10 @@ void traverse(const QTree &T, int node, int target, const PruneRule &pr, const Q
   }
   const int sh = leaf.level - q.level;
   if (sh >= 0 && (leaf.ix >> sh) == q.ix && (leaf.iy >> sh) == q.iy) ov = true;  // holds the target
+  if (!ov && q.count > 1) {
+    const double dx = (*pr.phys)[2 * node] - pr.xi[0], dy = (*pr.phys)[2 * node + 1] - pr.xi[1];
+    if (std::sqrt(dx * dx + dy * dy) <= pr.tol) ov = true;
+  }
   if (!ov) {
     out.push_back(q.count == 1 ? int64_t(T.perm[q.first]) : node_key(q));
     return;
@@ -156,23 +168,25 @@ extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *
     if (targets[t] < 0 || targets[t] >= n) return PTROM_EINVAL;
   QTree T;
   T.build(n, wpts, max_level);
-  // per-node |Gamma|-weighted mean point (Barnes-Hut surrogate position)
-  std::vector<double> mean;
-  if (criterion == 1) {
-    mean.assign(2 * T.nodes.size(), 0.0);
-    for (size_t k = 0; k < T.nodes.size(); ++k) {
-      const QNode &q = T.nodes[k];
-      double ws = 0.0, mx = 0.0, my = 0.0;
-      for (int t = q.first; t < q.first + q.count; ++t) ws += std::fabs(gamma[T.perm[t]]);
-      for (int t = q.first; t < q.first + q.count; ++t) {
-        const int j = T.perm[t];
-        const double wj = ws == 0.0 ? 1.0 / q.count : std::fabs(gamma[j]) / ws;
-        mx += wj * wpts[2 * j];
-        my += wj * wpts[2 * j + 1];
-      }
-      mean[2 * k] = mx;
-      mean[2 * k + 1] = my;
+  // per-node |Gamma|-weighted means: the point in W_phi (Barnes-Hut
+  // surrogate position) and the initial physical position
+  std::vector<double> mean(2 * T.nodes.size(), 0.0), phys(2 * T.nodes.size(), 0.0);
+  for (size_t k = 0; k < T.nodes.size(); ++k) {
+    const QNode &q = T.nodes[k];
+    double ws = 0.0, mx = 0.0, my = 0.0, px = 0.0, py = 0.0;
+    for (int t = q.first; t < q.first + q.count; ++t) ws += std::fabs(gamma[T.perm[t]]);
+    for (int t = q.first; t < q.first + q.count; ++t) {
+      const int j = T.perm[t];
+      const double wj = ws == 0.0 ? 1.0 / q.count : std::fabs(gamma[j]) / ws;
+      mx += wj * wpts[2 * j];
+      my += wj * wpts[2 * j + 1];
+      px += wj * xy0[j];
+      py += wj * xy0[n + j];
     }
+    mean[2 * k] = mx;
+    mean[2 * k + 1] = my;
+    phys[2 * k] = px;
+    phys[2 * k + 1] = py;
   }
   // per-target lists of surrogate keys
   std::vector<std::vector<int64_t>> lists(nt);
@@ -186,7 +200,10 @@ extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *
     pr.hlo[0] = leaf.lo[0] - pc * w; pr.hlo[1] = leaf.lo[1] - pc * w;
     pr.hhi[0] = leaf.hi[0] + pc * w; pr.hhi[1] = leaf.hi[1] + pc * w;
     pr.si[0] = wpts[2 * i]; pr.si[1] = wpts[2 * i + 1];
+    pr.xi[0] = xy0[i]; pr.xi[1] = xy0[n + i];
+    pr.tol = kCoincide * (1.0 + std::sqrt(xy0[i] * xy0[i] + xy0[n + i] * xy0[n + i]));
     pr.mean = &mean;
+    pr.phys = &phys;
     traverse(T, 0, i, pr, leaf, lists[t]);
   }
   // UniqueSearch

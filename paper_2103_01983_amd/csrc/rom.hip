@@ -99,7 +99,8 @@ __device__ void gather_target(const RomDev &d, int i, int lane, const double *xh
       ry = fmaf(Dy[m], xf[m], ry);
     }
     const float q = fmaf(rx, rx, fmaf(ry, ry, d.d2));
-    const float r = 1.0f / q;
+    // a surrogate exactly on its target (possible at delta = 0) adds nothing
+    const float r = q > 0.f ? 1.0f / q : 0.f;
     const float g = head.z * r;
     fx = fmaf(-ry, g, fx);
     fy = fmaf(rx, g, fy);

@@ -147,3 +147,15 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
   }
   return PTROM_OK;
 }
+
+extern "C" int ptrom_pair_config(ptrom_ctx *ctx, int op, int64_t n, int32_t *out) {
+  if (!ctx || !out || op < 0 || op >= OP_COUNT || n < 1 || n > kMaxN) return PTROM_EINVAL;
+  const PairCfg c = ctx->tune.get(op, n);
+  const bool sym = c.sym && has_sym(op);
+  out[0] = c.staging;
+  out[1] = c.k;
+  out[2] = c.waves_per_simd;
+  out[3] = sym ? 1 : 0;
+  out[4] = sym ? 0 : pair_splits(op, c, ctx->num_cus, n);
+  return PTROM_OK;
+}

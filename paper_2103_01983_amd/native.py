@@ -85,6 +85,7 @@ SIGNATURES = {
     "ptrom_combine_f64": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp]),
     "ptrom_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "ptrom_load_tuning": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "ptrom_pair_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -515,3 +516,16 @@ def autotune(cache_path=None, device=None):
 def load_tuning(cache_path, device=None):
     c = context(device)
     _check(c, lib().ptrom_load_tuning(c, cache_path.encode()), "ptrom_load_tuning")
+
+
+PAIR_OPS = {"velocity": 0, "block_jacobian": 1, "jvp": 2, "vjp": 3, "stream_function": 4}
+
+
+def pair_config(op, n, device=None, ctx=None):
+    """The launch the library picks for pair operation ``op`` (a name of
+    PAIR_OPS) at n bodies: dict(staging, k, waves_per_simd, sym, splits)."""
+    c = context(device) if ctx is None else ctx
+    out = (ctypes.c_int32 * 5)()
+    _check(c, lib().ptrom_pair_config(c, PAIR_OPS[op], int(n), out), "ptrom_pair_config")
+    return dict(staging=int(out[0]), k=int(out[1]), waves_per_simd=int(out[2]), sym=int(out[3]),
+                splits=int(out[4]))

@@ -38,7 +38,8 @@ def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap, newton_tol=1e-6):
 
 def pod(S, M, center=None):
     """POD of the rows of S (device FP64 [k, nd]) by the method of snapshots.
-    Returns (Phi as device FP64 [M, nd] rows = modes, sigma [M] host)."""
+    Returns (Phi as device FP64 [M, nd] rows = modes, sigma [M] host); each
+    mode's sign makes its largest-magnitude entry positive."""
     X = S if center is None else (S - center[None, :]).contiguous()
     G = native.gram_f64(X).cpu().numpy()
     w, V = np.linalg.eigh(G)
@@ -53,6 +54,13 @@ def pod(S, M, center=None):
         R = np.linalg.cholesky(G2).T
         Rinv = torch.tensor(np.ascontiguousarray(np.linalg.inv(R)), dtype=torch.float64, device=S.device)
         Phi = native.combine_f64(Phi, Rinv)
+    # sign convention: each mode's entry of largest magnitude is positive
+    # (lowest row on ties), which fixes W_phi and so the clustering
+    P = Phi.cpu().numpy()
+    flip = P[np.arange(M), np.argmax(np.abs(P), axis=1)] < 0.0
+    if flip.any():
+        D = np.diag(np.where(flip, -1.0, 1.0))
+        Phi = native.combine_f64(Phi, torch.tensor(D, dtype=torch.float64, device=S.device))
     return Phi, sig
 
 

@@ -75,6 +75,30 @@ def shear_layer(n=131072, seed=1005, delta=0.01, thickness=0.05, amp=1e-3):
     return Cloud(_soa(r * np.cos(th), r * np.sin(th)), np.full(n, 1.0 / n), delta, dict(kind="shear_layer"))
 
 
+# single-vortex study: N -> (dt, Gamma of the centre body, t_f)
+SINGLE_VORTEX = {
+    100: (0.01, 500.0, 20.0), 500: (2.5e-3, 1e4, 5.0), 1000: (2.5e-4, 1e5, 0.5),
+    2000: (1.25e-4, 2e5, 0.25), 3000: (1e-4, 3e5, 0.2), 4000: (7.5e-5, 4e5, 0.15),
+    5000: (5e-5, 6.75e5, 0.1),
+}
+
+
+def single_vortex(n, gamma_center=None):
+    """Deterministic initial state of the single-vortex study: N bodies evenly
+    spaced on the diagonal from (-N, -N) to (N, N), Gamma = 0.01 except the
+    centre body (index N // 2), delta = 0.  ``meta`` carries the study's dt
+    and t_f for the listed N."""
+    dt, gc, tf = SINGLE_VORTEX.get(n, (None, None, None))
+    if gamma_center is not None:
+        gc = gamma_center
+    if gc is None:
+        raise ValueError(f"no study conditions for N={n}; pass gamma_center")
+    s = np.linspace(-n, n, n)
+    g = np.full(n, 0.01)
+    g[n // 2] = gc
+    return Cloud(_soa(s, s.copy()), g, 0.0, dict(kind="single_vortex", dt=dt, tf=tf))
+
+
 def unit_vectors(n, k, seed):
     """k random unit vectors of length 2n (Gaussian, normalized)."""
     rng = np.random.default_rng(seed)

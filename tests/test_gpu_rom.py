@@ -114,3 +114,36 @@ def test_rom_rejects_bad_ids(dev, trained):
     bad["ids"][0] = len(art["Gt"]) + 5
     with pytest.raises(native.PtromError):
         native.Rom(bad)
+
+
+@pytest.mark.parametrize("mode", [native.JAC_PAPER, native.JAC_EXACT])
+def test_surrogate_on_its_target_at_zero_core(dev, trained, mode):
+    # delta = 0 and one more source placed on sampled target 0 for every xhat
+    # (its own x0 and mode rows): finite, and equal to the oracle, which
+    # drops such a pair like the self pair.
+    cl, art, ex = trained
+    ns = len(art["sample"])
+    a = dict(art)
+    a["delta"] = 0.0
+    Nc = art["Gt"].size
+    M = art["Phibar"].shape[1]
+    a["xqt0"] = np.vstack([art["xqt0"], [[art["xbar0"][0], art["xbar0"][ns]]]])
+    a["Phit"] = np.concatenate([art["Phit"], np.stack([art["Phibar"][0], art["Phibar"][ns]])[None]])
+    a["Gt"] = np.append(art["Gt"], f32(0.3))
+    off_ = np.asarray(art["off"]).copy()
+    ids = list(art["ids"])
+    ids.insert(int(off_[1]), Nc)
+    off_[1:] += 1
+    a["off"], a["ids"] = off_, np.asarray(ids, dtype=np.int64)
+    nd = 2 * ns
+    rng = np.random.default_rng(3)
+    xh = rng.standard_normal(M) * 0.05
+    xp, fp = rng.standard_normal(nd) * 0.1 + art["xbar0"], rng.standard_normal(nd) * 0.1
+    xb, fb, rb, C = oracle.Rom(a, jac_mode=mode).hyperpair(xh, xp, fp)
+    t = lambda v: torch.tensor(v, dtype=torch.float64, device=dev)
+    gx, gf, gr, gC = native.Rom(a, jac_mode=mode).hyperpair(t(xh), t(xp), t(fp))
+    for g in (gx, gf, gr, gC):
+        assert torch.isfinite(g).all()
+    assert rel(gf.cpu().numpy(), fb) <= 1e-5
+    assert rel(gr.cpu().numpy(), rb) <= 1e-5
+    assert rel(gC.cpu().numpy() - a["Phibar"], C - a["Phibar"]) <= 1e-5

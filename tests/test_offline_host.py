@@ -79,3 +79,31 @@ def test_barnes_hut_theta_zero_is_exact_and_lists_cover_all():
         for k in oo.find_clusters(tree, i, 0.0, "barnes-hut", 1.5, cl.gamma):
             members.extend([k[1]] if k[0] == 0 else keys_nodes[k].members)
         assert sorted(members) == [j for j in range(150) if j != i]
+
+
+@pytest.mark.parametrize("criterion,theta", [("neighbor", 0.0), ("barnes-hut", 2.0)])
+def test_lists_with_coincident_cells_match_oracle(criterion, theta):
+    # Bodies evenly spaced on a line with equal Gamma: the weighted mean of
+    # two bodies symmetric about a third sits exactly on it at x^0, and such
+    # cells must be opened by both implementations.
+    cl = W.single_vortex(100)
+    n = cl.n
+    S = oo.trapezoid_snapshots(cl.xy, cl.gamma, 0.0, 0.01, 2000)
+    Phi, sig = oo.pod(S, 13)
+    rng = np.random.default_rng(12)
+    fired = 0
+    for trial in range(8):
+        sg = np.ones(13) if trial == 0 else rng.choice([-1.0, 1.0], 13)
+        P = np.ascontiguousarray(oo.weighted_points(Phi * sg, sig))
+        tree = oo.QuadTree(P, 16)
+        targets = np.arange(n)
+        ox, oP, oG, ooff, oids, okeys = oo.cluster_artifacts(tree, targets, 0.0, cl.xy, Phi, cl.gamma,
+                                                             criterion, theta)
+        kind = native.NEIGHBOR if criterion == "neighbor" else native.BARNES_HUT
+        r = native.cluster_build(P, cl.xy, np.ascontiguousarray(Phi), cl.gamma, 16, 0.0, targets, kind, theta)
+        assert np.array_equal(r["off"], ooff) and np.array_equal(r["ids"], oids)
+        np.testing.assert_allclose(r["xqt0"], ox, rtol=0, atol=1e-12)
+        fired += sum(oo.find_clusters(tree, i, 0.0, criterion, theta, cl.gamma)
+                     != oo.find_clusters(tree, i, 0.0, criterion, theta, cl.gamma, cl.xy) for i in range(n))
+    if criterion == "neighbor":
+        assert fired > 0

@@ -155,3 +155,95 @@ def test_full_pipeline_small():
     out = oracle.Rom(art).run(12, tol=1e-4)
     assert out["status"] == 0
     assert np.all(np.isfinite(out["hist"]))
+
+
+def _with_extra_source(art, target, x0, phit, gt):
+    """Copy of ``art`` with one more surrogate source appended to the list of
+    sampled target ``target``."""
+    a = dict(art)
+    Nc = art["Gt"].size
+    a["xqt0"] = np.vstack([art["xqt0"], np.asarray(x0, float)[None]])
+    a["Phit"] = np.concatenate([art["Phit"], np.asarray(phit, float)[None]])
+    a["Gt"] = np.append(art["Gt"], gt)
+    off_ = np.asarray(art["off"]).copy()
+    ids = list(art["ids"])
+    ids.insert(int(off_[target + 1]), Nc)
+    off_[target + 1:] += 1
+    a["off"], a["ids"] = off_, np.asarray(ids, dtype=np.int64)
+    return a
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_surrogate_on_its_target_adds_nothing(small_problem, mode):
+    # At delta = 0 a surrogate that sits exactly on its sampled target has no
+    # defined velocity; like the excluded self pair it contributes nothing,
+    # so velocity, residual and Jacobian equal those of the list without it.
+    cl, _, Phi, sig, tree = small_problem
+    n = cl.n
+    sample = np.array([3, 40, 150])
+    art = off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, 0.0, 1e-3)
+    t = 1
+    rows = off.sampled_rows(sample, n)
+    # same initial position and same mode rows as body 40: coincident for all xhat
+    extra = _with_extra_source(art, t, [cl.xy[40], cl.xy[n + 40]], [Phi[40], Phi[n + 40]], 0.7)
+    xh = np.random.default_rng(4).standard_normal(Phi.shape[1]) * 0.01
+    xp, fp = cl.xy[rows] + 0.01, np.zeros(rows.size)
+    a = oracle.Rom(art, jac_mode=mode).hyperpair(xh, xp, fp)
+    b = oracle.Rom(extra, jac_mode=mode).hyperpair(xh, xp, fp)
+    for u, v in zip(a, b):
+        assert np.all(np.isfinite(v))
+        np.testing.assert_array_equal(u, v)
+
+
+def _line_problem(n=100, steps=2000):
+    """Bodies evenly spaced on the diagonal around one strong vortex, delta = 0
+    (the single-vortex study's initial state): Gamma-weighted means of two
+    bodies symmetric about a third fall exactly on it."""
+    s = np.linspace(-n, n, n)
+    g = np.full(n, 0.01)
+    g[n // 2] = 500.0
+    xy = np.concatenate([s, s])
+    S = off.trapezoid_snapshots(xy, g, 0.0, 0.01, steps)
+    return xy, g, S
+
+
+def test_cells_on_their_target_are_opened():
+    xy, g, S = _line_problem()
+    n = g.size
+    Phi, sig = off.pod(S, 13)
+    rng = np.random.default_rng(11)
+    by_key_fired = 0
+    for trial in range(16):
+        sg = np.ones(13) if trial == 0 else rng.choice([-1.0, 1.0], 13)
+        tree = off.QuadTree(off.weighted_points(Phi * sg, sig), 16)
+        nodes = {nd.key: nd for nd in tree.nodes}
+        for i in range(n):
+            plain = off.find_clusters(tree, i, 0.0, gamma=g)
+            guarded = off.find_clusters(tree, i, 0.0, gamma=g, xy0=xy)
+            # every other body is still represented exactly once
+            members = []
+            for k in guarded:
+                members.extend([k[1]] if k[0] == 0 else nodes[k].members)
+            assert sorted(members) == [j for j in range(n) if j != i]
+            for k in guarded:
+                if k[0] != 0:
+                    x0c = off.node_surrogates(nodes[k], xy, Phi, g)[0]
+                    assert np.hypot(*(x0c - [xy[i], xy[n + i]])) > 1e-9 * (1 + np.hypot(xy[i], xy[n + i]))
+            if plain != guarded:
+                by_key_fired += 1
+                # only coincident cells were opened
+                for k in set(plain) - set(guarded):
+                    assert off.coincides(nodes[k], i, xy, g)
+    assert by_key_fired > 0  # the configuration does produce coincident cells
+
+
+def test_pod_sign_convention():
+    rng = np.random.default_rng(8)
+    S = rng.standard_normal((40, 15))
+    Phi, sig = off.pod(S, 5)
+    for m in range(5):
+        j = np.argmax(np.abs(Phi[:, m]))
+        assert Phi[j, m] > 0
+    # the same basis for a column-permuted snapshot set
+    Phi2, _ = off.pod(S[:, rng.permutation(15)], 5)
+    np.testing.assert_allclose(Phi2, Phi, atol=1e-12)
