@@ -18,8 +18,9 @@
 // shared-memory traffic is needed.  Workgroups pop items from a device
 // counter (persistent launch).  Forward sums land in F[J][.][N], reactions
 // in R[I][.][N]; a final kernel adds, per body, its forward slots
-// J >= block(b) and reaction slots I < block(b) in a fixed order with Kahan
-// compensation, so results are bitwise reproducible.
+// J >= block(b) and reaction slots I < block(b) in a fixed order (Kahan
+// compensated sums over 8 contiguous slot ranges, combined in range order), so
+// results are bitwise reproducible.
 #include "pair_core.h"
 
 namespace ptrom {
@@ -196,23 +197,48 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Per body b (in block B = b / tb) the slots to add are, in this order, its
+// forward slots J = B .. nb-1 and its reaction slots I = 0 .. B-1.  A
+// workgroup takes 64 consecutive bodies (tb is a multiple of 64, so one wave
+// shares B) and kSlices contiguous ranges of that slot list; each range is
+// added with Kahan compensation, then the ranges are combined in slice order.
+constexpr int kSlices = 8;
+
 template <int OP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kSlices)
     sym_reduce_kernel(int n, int tb, int nb, const float *__restrict__ F, const float *__restrict__ R,
                       float *__restrict__ out, float *__restrict__ out2) {
   constexpr int NA = Traits<OP>::NACC;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
-  const int B = b / tb;
-  float v[NA];
+  __shared__ float part[NA][kSlices][64];
+  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  const int b = blockIdx.x * 64 + lane;
+  const bool ok = b < n;
+  const int B = (blockIdx.x * 64) / tb;
+  const int nf = nb - B;  // forward slots come first
+  const int q0 = (slice * nb) / kSlices, q1 = ((slice + 1) * nb) / kSlices;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     float s = 0.0f, c = 0.0f;
-    for (int J = B; J < nb; ++J) kahan_add(s, c, F[(size_t)(J * NA + a) * n + b]);
-    for (int I = 0; I < B; ++I) kahan_add(s, c, R[(size_t)(I * NA + a) * n + b]);
-    v[a] = s - c;
+    if (ok) {
+      for (int q = q0; q < q1; ++q) {
+        const float v = q < nf ? F[(size_t)((B + q) * NA + a) * n + b] : R[(size_t)((q - nf) * NA + a) * n + b];
+        kahan_add(s, c, v);
+      }
+    }
+    part[a][slice][lane] = s - c;
   }
-  store_final<OP>(n, b, v, out, out2);
+  __syncthreads();
+  if (slice == 0 && ok) {
+    float v[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      float s = 0.0f, c = 0.0f;
+#pragma unroll
+      for (int w = 0; w < kSlices; ++w) kahan_add(s, c, part[a][w][lane]);
+      v[a] = s - c;
+    }
+    store_final<OP>(n, b, v, out, out2);
+  }
 }
 
 template <int OP, int K>
@@ -227,7 +253,7 @@ hipError_t launch_sym_t(int n, const float *xy, const float *gam, const float *a
   hipLaunchKernelGGL(sym_reset_kernel, dim3(1), dim3(64), 0, st, counter);
   hipLaunchKernelGGL((pair_sym_kernel<OP, K>), dim3(grid), dim3(kBlock), 0, st, n, xy, gam, aux, d2, nb,
                      counter, F, R);
-  hipLaunchKernelGGL(sym_reduce_kernel<OP>, dim3((n + 255) / 256), dim3(256), 0, st, n, tb, nb, F, R, out,
+  hipLaunchKernelGGL(sym_reduce_kernel<OP>, dim3((n + 63) / 64), dim3(64 * kSlices), 0, st, n, tb, nb, F, R, out,
                      out2);
   return hipGetLastError();
 }

@@ -12,15 +12,21 @@
 //   gather    one wave64 per sampled target walks its entries (lanes stride),
 //             does the pair arithmetic in FP32 (velocity and the 2x2 self
 //             block B_i; in the exact mode sum_e G_e D_e instead), reduces
-//             across the wave with shuffles, and writes the trapezoid residual
-//             rows rbar = xbar - xbar_prev - dt/2 (fbar + fbar_prev) and the
-//             rows of C = Phibar - dt/2 dfbar/dxhat in FP64;
-//   solve     G = A C, b = A rbar (FP64), the relative reduced gradient
-//             |G^T b| / |G_1^T b_1|, Householder QR of G in one wave and
-//             xhat -= alpha G^+ b.
+//             across the wave with DPP row reductions, and writes the
+//             trapezoid residual rows rbar = xbar - xbar_prev - dt/2 (fbar +
+//             fbar_prev) and the rows of C = Phibar - dt/2 dfbar/dxhat (FP64);
+//   solve     G' = A [C | rbar] (FP64, four columns per thread), the Gram
+//             matrix G'^T G' = [G^T G, G^T b; ...], the relative reduced
+//             gradient |G^T b| / |G_1^T b_1|, and in one wave a Cholesky
+//             factorisation of G^T G held one row per lane, forward and back
+//             substitution by lane broadcasts, and one refinement step on the
+//             true residual b - G x (corrected semi-normal equations), then
+//             xhat -= alpha x.
 // ptrom_rom_run keeps the whole loop (all steps, all iterations) inside one
-// workgroup with A, C, rbar and the previous-step rows in LDS when they fit;
-// ptrom_rom_hyperpair runs the gather over many workgroups (large sample sets).
+// workgroup with A, [C | rbar] and the previous-step rows in LDS when they
+// fit; ptrom_rom_hyperpair runs the gather over many workgroups (large sample
+// sets).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -32,12 +38,13 @@ namespace {
 
 constexpr int kMaxM = 32;
 constexpr int kMaxMr = 64;
+constexpr int kMaxLdc = 36;   // columns of [C | rbar] rounded up to 4
+constexpr int kLt = kMaxM + 1;  // row stride of the transposed factor in LDS (bank spread)
 constexpr int kRunThreads = 1024;
 constexpr double kInv2PiD = 0.15915494309189533576888376337251;
-constexpr size_t kMaxDynLds = 40 * 1024;  // keeps the workgroup under 64 KB of LDS
 
 struct RomDev {
-  int M, Mr, ns, nd, jac_mode, max_iter, ew;
+  int M, Mr, ns, nd, jac_mode, max_iter, ew, ldc;
   int64_t nnz;
   float d2, dt;
   double tol, alpha;
@@ -45,20 +52,58 @@ struct RomDev {
   const float *ent;             // [nnz][ew]: r0x r0y Gamma pad Dx[M] Dy[M]
   const int *off;               // [ns+1]
   const double *A;              // [Mr][nd]
-  // scratch used when the LDS copies do not fit
-  double *xbar_prev, *fbar, *fbar_prev, *rbar, *C;
+  // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
+  // leading dimension ldc
+  double *xbar_prev, *fbar, *fbar_prev, *C;
 };
 
+// Wave-wide sums by DPP: within each row of 16 lanes swap neighbours
+// (quad_perm [1,0,3,2] and [2,3,0,1]), then mirror the half row and the row,
+// so every lane holds its row's sum; the four row sums are then read out and
+// added in a fixed order.  Must be called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)(u & 0xffffffffull));
+  const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float wsum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
 __device__ __forceinline__ double wsumd(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 // xbar_i (both rows) at xhat, FP64
@@ -75,17 +120,19 @@ __device__ __forceinline__ void sampled_position(const RomDev &d, int i, const d
 }
 
 // HyperPair rows of sampled target i, computed by one whole wave.
-// xh: FP64 xhat, xf: FP32 copy.  Any output pointer may be null.
+// xh: FP64 xhat, xf: FP32 copy.  Any output pointer may be null.  Row q of
+// rbar is rbar_out[q * rs], row q of C is C_out[q * ldc .. + M).
 template <bool EXACT>
 __device__ void gather_target(const RomDev &d, int i, int lane, const double *xh, const float *xf,
                               const double *xbar_prev, const double *fbar_prev, double *xbar_out,
-                              double *fbar_out, double *rbar_out, double *C_out) {
+                              double *fbar_out, double *rbar_out, int rs, double *C_out, int ldc) {
   const int M = d.M, ns = d.ns, ew = d.ew;
   double tx, ty;
   sampled_position(d, i, xh, tx, ty);
   float fx = 0.f, fy = 0.f, ba = 0.f, bb = 0.f, bc = 0.f;
   float ex[EXACT ? kMaxM : 1], ey[EXACT ? kMaxM : 1];
   if constexpr (EXACT) {
+#pragma unroll
     for (int m = 0; m < kMaxM; ++m) ex[m] = ey[m] = 0.f;
   }
   const int e0 = d.off[i], e1 = d.off[i + 1];
@@ -109,9 +156,12 @@ __device__ void gather_target(const RomDev &d, int i, int lane, const double *xh
     const float dd = fmaf(ry, ry, -rx * rx);
     if constexpr (EXACT) {
       const float h00 = g2 * a2, h01 = g2 * (dd - d.d2), h10 = g2 * (dd + d.d2);
-      for (int m = 0; m < M; ++m) {
-        ex[m] = fmaf(h00, Dx[m], fmaf(h01, Dy[m], ex[m]));
-        ey[m] = fmaf(h10, Dx[m], fmaf(-h00, Dy[m], ey[m]));
+#pragma unroll
+      for (int m = 0; m < kMaxM; ++m) {
+        if (m < M) {
+          ex[m] = fmaf(h00, Dx[m], fmaf(h01, Dy[m], ex[m]));
+          ey[m] = fmaf(h10, Dx[m], fmaf(-h00, Dy[m], ey[m]));
+        }
       }
     } else {
       ba = fmaf(g2, a2, ba);
@@ -131,20 +181,29 @@ __device__ void gather_target(const RomDev &d, int i, int lane, const double *xh
       fbar_out[ns + i] = Fy;
     }
     if (rbar_out) {
-      rbar_out[i] = (tx - xbar_prev[i]) - hdt * (Fx + fbar_prev[i]);
-      rbar_out[ns + i] = (ty - xbar_prev[ns + i]) - hdt * (Fy + fbar_prev[ns + i]);
+      rbar_out[(size_t)i * rs] = (tx - xbar_prev[i]) - hdt * (Fx + fbar_prev[i]);
+      rbar_out[(size_t)(ns + i) * rs] = (ty - xbar_prev[ns + i]) - hdt * (Fy + fbar_prev[ns + i]);
     }
   }
   if (C_out) {
     if constexpr (EXACT) {
       // C_i = Phibar_i - dt/2 sum_e G_e (Phibar_i - Phit_c)
-      for (int m = 0; m < M; ++m) {
-        const double jx = wsum(ex[m]) * kInv2PiD, jy = wsum(ey[m]) * kInv2PiD;
-        if (lane == m) {
-          const double px = d.Phibar[(size_t)i * M + m], py = d.Phibar[(size_t)(ns + i) * M + m];
-          C_out[(size_t)i * M + m] = px - hdt * jx;
-          C_out[(size_t)(ns + i) * M + m] = py - hdt * jy;
+      double jx = 0.0, jy = 0.0;
+#pragma unroll
+      for (int m = 0; m < kMaxM; ++m) {
+        if (m < M) {
+          const float sx = wsum(ex[m]), sy = wsum(ey[m]);
+          if (lane == m) {
+            jx = sx * kInv2PiD;
+            jy = sy * kInv2PiD;
+          }
         }
+      }
+      if (lane < M) {
+        const int m = lane;
+        const double px = d.Phibar[(size_t)i * M + m], py = d.Phibar[(size_t)(ns + i) * M + m];
+        C_out[(size_t)i * ldc + m] = px - hdt * jx;
+        C_out[(size_t)(ns + i) * ldc + m] = py - hdt * jy;
       }
     } else {
       // C_i = Phibar_i - dt/2 B_i Phibar_i (the paper's inexact Jacobian)
@@ -152,8 +211,8 @@ __device__ void gather_target(const RomDev &d, int i, int lane, const double *xh
       if (lane < M) {
         const int m = lane;
         const double px = d.Phibar[(size_t)i * M + m], py = d.Phibar[(size_t)(ns + i) * M + m];
-        C_out[(size_t)i * M + m] = px - hdt * (B00 * px + B01 * py);
-        C_out[(size_t)(ns + i) * M + m] = py - hdt * (B10 * px - B00 * py);
+        C_out[(size_t)i * ldc + m] = px - hdt * (B00 * px + B01 * py);
+        C_out[(size_t)(ns + i) * ldc + m] = py - hdt * (B10 * px - B00 * py);
       }
     }
   }
@@ -175,10 +234,42 @@ __global__ void __launch_bounds__(256)
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= d.ns) return;
-  gather_target<EXACT>(d, wave, lane, xh, xf, xbar_prev, fbar_prev, xbar, fbar, rbar, C);
+  gather_target<EXACT>(d, wave, lane, xh, xf, xbar_prev, fbar_prev, xbar, fbar, rbar, 1, C, d.M);
 }
 
 // ----------------------------------------------------------- device-resident loop
+
+// Solves (L L^T) x = rhs for the factor held one row per lane (a[j] = L_lj on
+// lane l, j <= l) and its transpose in LDS (Lt[i * kLt + k] = L_ki).  rhs_i is
+// given on lane i; x is written to xs[] and lane i's component returned.  A
+// zero pivot drops its direction (component 0).
+__device__ __forceinline__ double chol_solve(const double (&a)[kMaxM], const double *Lt, int M, int lane,
+                                             double rhs, double *xs) {
+  // forward: L y = rhs; lane i keeps rhs_i - sum_{j<k} L_ij y_j
+  double acc = rhs, ymine = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) {
+    if (k < M) {
+      const double lkk = lane_d(a[k], k);
+      const double yk = lkk != 0.0 ? lane_d(acc, k) / lkk : 0.0;
+      if (lane == k) ymine = yk;
+      acc = fma(-a[k], yk, acc);
+    }
+  }
+  // backward: L^T x = y; lane i keeps y_i - sum_{j>k} L_ji x_j
+  double acc2 = ymine, xmine = 0.0;
+#pragma unroll
+  for (int k = kMaxM - 1; k >= 0; --k) {
+    if (k < M) {
+      const double ukk = lane_d(a[k], k);
+      const double xk = ukk != 0.0 ? lane_d(acc2, k) / ukk : 0.0;
+      if (lane == k) xmine = xk;
+      if (lane == 0) xs[k] = xk;
+      if (lane < k) acc2 = fma(-Lt[lane * kLt + k], xk, acc2);
+    }
+  }
+  return xmine;
+}
 
 template <bool EXACT>
 __global__ void __launch_bounds__(kRunThreads)
@@ -186,28 +277,28 @@ __global__ void __launch_bounds__(kRunThreads)
                    int *__restrict__ iters) {
   __shared__ double xh[kMaxM];
   __shared__ float xf[kMaxM];
-  __shared__ double G[kMaxMr * kMaxM];
-  __shared__ double b[kMaxMr];
-  __shared__ double sol[kMaxM];
+  __shared__ double Gp[kMaxMr * kMaxLdc];          // G' = A [C | rbar | 0]
+  __shared__ double Nw[(kMaxM + 1) * (kMaxM + 1)];  // G'^T G', then L^T
+  __shared__ double rr[kMaxMr], xs[kMaxM], dxs[kMaxM];
   __shared__ double s_eps, s_g1;
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
-  const int M = d.M, Mr = d.Mr, nd = d.nd;
+  const int M = d.M, Mr = d.Mr, nd = d.nd, ldc = d.ldc, M1 = M + 1;
 
-  // A, C, rbar, fbar, fbar_prev, xbar_prev: LDS copies when they fit
+  // A, [C | rbar], fbar, fbar_prev, xbar_prev: LDS copies when they fit
   const double *A = d.A;
-  double *C = d.C, *rbar = d.rbar, *fbar = d.fbar, *fbar_prev = d.fbar_prev, *xbar_prev = d.xbar_prev;
+  double *Cp = d.C, *fbar = d.fbar, *fbar_prev = d.fbar_prev, *xbar_prev = d.xbar_prev;
   if (lds_arrays) {
     double *p = dyn;
     double *Al = p; p += (size_t)Mr * nd;
-    C = p; p += (size_t)nd * M;
-    rbar = p; p += nd;
+    Cp = p; p += (size_t)nd * ldc;
     fbar = p; p += nd;
     fbar_prev = p; p += nd;
     xbar_prev = p;
     for (int t = tid; t < Mr * nd; t += kRunThreads) Al[t] = d.A[t];
     A = Al;
   }
+  for (int t = tid; t < nd * ldc; t += kRunThreads) Cp[t] = 0.0;  // padding columns stay zero
   if (tid < M) {
     xh[tid] = xhat[tid];
     xf[tid] = (float)xhat[tid];
@@ -215,73 +306,102 @@ __global__ void __launch_bounds__(kRunThreads)
   __syncthreads();
   // previous-step terms for the first step: HyperPair at the initial xhat
   for (int i = wave; i < d.ns; i += nwaves)
-    gather_target<EXACT>(d, i, lane, xh, xf, nullptr, nullptr, xbar_prev, fbar_prev, nullptr, nullptr);
+    gather_target<EXACT>(d, i, lane, xh, xf, nullptr, nullptr, xbar_prev, fbar_prev, nullptr, 0, nullptr, 0);
   __syncthreads();
 
+  const int nblk = ldc / 4;
+  const int npair = M1 * (M1 + 1) / 2;
   for (int step = 0; step < nsteps; ++step) {
     int k = 1;
     for (;;) {
       for (int i = wave; i < d.ns; i += nwaves)
-        gather_target<EXACT>(d, i, lane, xh, xf, xbar_prev, fbar_prev, nullptr, fbar, rbar, C);
+        gather_target<EXACT>(d, i, lane, xh, xf, xbar_prev, fbar_prev, nullptr, fbar, Cp + M, ldc, Cp, ldc);
       __syncthreads();
-      // G = A C, b = A rbar
-      for (int t = tid; t < Mr * (M + 1); t += kRunThreads) {
-        const int r = t / (M + 1), c = t % (M + 1);
-        const double *a = A + (size_t)r * nd;
-        double s = 0.0;
-        if (c < M) {
-          for (int q = 0; q < nd; ++q) s += a[q] * C[(size_t)q * M + c];
-          G[r * M + c] = s;
-        } else {
-          for (int q = 0; q < nd; ++q) s += a[q] * rbar[q];
-          b[r] = s;
+      // G' = A [C | rbar | 0], four columns per thread
+      for (int t = tid; t < Mr * nblk; t += kRunThreads) {
+        const int r = t / nblk, c0 = (t - r * nblk) * 4;
+        const double *arow = A + (size_t)r * nd;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int q = 0; q < nd; ++q) {
+          const double av = arow[q];
+          const double *c = Cp + (size_t)q * ldc + c0;
+          s0 = fma(av, c[0], s0);
+          s1 = fma(av, c[1], s1);
+          s2 = fma(av, c[2], s2);
+          s3 = fma(av, c[3], s3);
         }
+        double *g = Gp + r * ldc + c0;
+        g[0] = s0;
+        g[1] = s1;
+        g[2] = s2;
+        g[3] = s3;
+      }
+      __syncthreads();
+      // G'^T G' over the first M + 1 columns (lower triangle, mirrored)
+      for (int t = tid; t < npair; t += kRunThreads) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        double sum = 0.0;
+        for (int r = 0; r < Mr; ++r) sum = fma(Gp[r * ldc + i], Gp[r * ldc + j], sum);
+        Nw[i * M1 + j] = sum;
+        Nw[j * M1 + i] = sum;
       }
       __syncthreads();
       if (wave == 0) {
         // relative reduced gradient |G^T b| / |G_1^T b_1|
-        double gn = 0.0;
-        if (lane < M) {
-          double s = 0.0;
-          for (int r = 0; r < Mr; ++r) s += G[r * M + lane] * b[r];
-          gn = s * s;
-        }
-        gn = sqrt(wsumd(gn));
-        if (k == 1 && lane == 0) s_g1 = gn;
+        const double gl = lane < M ? Nw[lane * M1 + M] : 0.0;
+        const double gn = sqrt(wsumd(gl * gl));
         const double g1 = (k == 1) ? gn : s_g1;
         const double eps = g1 > 0.0 ? gn / g1 : 0.0;
-        // Householder QR of G (Mr x M, Mr <= 64: one row per lane) applied to b
-        for (int kk = 0; kk < M; ++kk) {
-          const double gkk = G[kk * M + kk];
-          double v = (lane >= kk && lane < Mr) ? G[lane * M + kk] : 0.0;
-          const double nrm = sqrt(wsumd(v * v));
-          if (nrm == 0.0) continue;
-          const double alpha = gkk > 0.0 ? -nrm : nrm;
-          if (lane == kk) v -= alpha;
-          const double vn2 = wsumd(v * v);
-          for (int j = kk + 1; j < M; ++j) {
-            const double gj = (lane < Mr) ? G[lane * M + j] : 0.0;
-            const double s = wsumd(v * gj) * 2.0 / vn2;
-            if (lane >= kk && lane < Mr) G[lane * M + j] = gj - s * v;
+        // Cholesky of G^T G, row `lane` in registers
+        double a[kMaxM];
+#pragma unroll
+        for (int j = 0; j < kMaxM; ++j) a[j] = (j < M && lane < M) ? Nw[lane * M1 + j] : 0.0;
+#pragma unroll
+        for (int kk = 0; kk < kMaxM; ++kk) {
+          if (kk < M) {
+            const double piv = lane_d(a[kk], kk);
+            const bool pos = piv > 0.0;
+            const double lkk = pos ? sqrt(piv) : 0.0;
+            const double inv = pos ? 1.0 / lkk : 0.0;
+            a[kk] = lane == kk ? lkk : a[kk] * inv;
+#pragma unroll
+            for (int j = kk + 1; j < kMaxM; ++j) {
+              if (j < M) {
+                const double ljk = lane_d(a[kk], j);
+                a[j] = fma(-a[kk], ljk, a[j]);
+              }
+            }
           }
-          {
-            const double bj = (lane < Mr) ? b[lane] : 0.0;
-            const double s = wsumd(v * bj) * 2.0 / vn2;
-            if (lane >= kk && lane < Mr) b[lane] = bj - s * v;
-          }
-          if (lane == kk) G[kk * M + kk] = alpha;
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // all reads of Nw done
+        // L^T into LDS: Lt[i * kLt + k] = L_ki for k >= i
+#pragma unroll
+        for (int j = 0; j < kMaxM; ++j)
+          if (j < M && lane < M && lane >= j) Nw[j * kLt + lane] = a[j];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        double xl = chol_solve(a, Nw, M, lane, gl, xs);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // one refinement step on the true residual: r' = b - G x, G^T r'
+        if (lane < Mr) {
+          double rv = Gp[lane * ldc + M];
+#pragma unroll
+          for (int j = 0; j < kMaxM; ++j)
+            if (j < M) rv = fma(-Gp[lane * ldc + j], xs[j], rv);
+          rr[lane] = rv;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        double g2 = 0.0;
+        if (lane < M)
+          for (int r = 0; r < Mr; ++r) g2 = fma(Gp[r * ldc + lane], rr[r], g2);
+        xl += chol_solve(a, Nw, M, lane, g2, dxs);
+        if (lane < M) {
+          xh[lane] -= d.alpha * xl;
+          xf[lane] = (float)xh[lane];
         }
         if (lane == 0) {
-          for (int kk = M - 1; kk >= 0; --kk) {
-            double s = b[kk];
-            for (int j = kk + 1; j < M; ++j) s -= G[kk * M + j] * sol[j];
-            sol[kk] = s / G[kk * M + kk];
-          }
-          for (int m = 0; m < M; ++m) {
-            xh[m] -= d.alpha * sol[m];
-            xf[m] = (float)xh[m];
-          }
+          if (k == 1) s_g1 = gn;
           s_eps = eps;
         }
       }
@@ -306,8 +426,8 @@ __global__ void __launch_bounds__(kRunThreads)
   if (tid < M) xhat[tid] = xh[tid];
 }
 
-size_t run_lds_bytes(int M, int Mr, int nd) {
-  return sizeof(double) * ((size_t)Mr * nd + (size_t)nd * M + 4 * (size_t)nd);
+size_t run_lds_bytes(int Mr, int nd, int ldc) {
+  return sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 3 * (size_t)nd);
 }
 
 }  // namespace
@@ -316,6 +436,7 @@ struct ptrom_rom {
   ptrom_ctx *ctx = nullptr;
   RomDev d{};
   void *buf = nullptr;
+  size_t max_dyn_lds = 0;  // dynamic LDS the run kernel may take on this device
 };
 
 extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptrom_rom **out) {
@@ -365,17 +486,40 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
 
   auto rom = new ptrom_rom();
   rom->ctx = ctx;
+  {
+    // dynamic LDS the run kernel may request: the device's per-workgroup
+    // limit minus the kernel's static LDS
+    int maxsh = 0;
+    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
+      maxsh = 64 * 1024;
+    size_t stat = 0;
+    const void *kernels[2] = {reinterpret_cast<const void *>(rom_run_kernel<false>),
+                              reinterpret_cast<const void *>(rom_run_kernel<true>)};
+    for (const void *k : kernels) {
+      hipFuncAttributes fa{};
+      if (hipFuncGetAttributes(&fa, k) == hipSuccess) stat = std::max(stat, fa.sharedSizeBytes);
+    }
+    size_t dyn = size_t(maxsh) > stat ? size_t(maxsh) - stat : 0;
+    for (const void *k : kernels)
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)) != hipSuccess) {
+        dyn = 64 * 1024 > stat ? 64 * 1024 - stat : 0;
+        (void)hipGetLastError();
+        break;
+      }
+    rom->max_dyn_lds = dyn;
+  }
   RomDev &d = rom->d;
   d.M = M; d.Mr = s.Mr; d.ns = s.ns; d.nd = nd; d.jac_mode = s.jac_mode; d.max_iter = s.max_iter;
   d.ew = ew; d.nnz = s.nnz;
+  d.ldc = (M + 1 + 3) / 4 * 4;
   d.d2 = float(s.delta) * float(s.delta);
   d.dt = float(s.dt);
   d.tol = s.tol; d.alpha = s.alpha;
 
   const size_t bytes[] = {align256(phibar.size() * 4), align256(xbar0.size() * 4), align256(ent.size() * 4),
                           align256(off32.size() * 4), align256(size_t(s.Mr) * nd * 8),
-                          align256(nd * 8), align256(nd * 8), align256(nd * 8), align256(nd * 8),
-                          align256(size_t(nd) * M * 8)};
+                          align256(nd * 8), align256(nd * 8), align256(nd * 8),
+                          align256(size_t(nd) * ((M + 4) / 4 * 4) * 8)};
   constexpr int NB = sizeof(bytes) / sizeof(bytes[0]);
   size_t total = 0;
   for (size_t b : bytes) total += b;
@@ -391,7 +535,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   }
   d.Phibar = (float *)ptrs[0]; d.xbar0 = (float *)ptrs[1]; d.ent = (float *)ptrs[2]; d.off = (int *)ptrs[3];
   d.A = (double *)ptrs[4]; d.xbar_prev = (double *)ptrs[5]; d.fbar = (double *)ptrs[6];
-  d.fbar_prev = (double *)ptrs[7]; d.rbar = (double *)ptrs[8]; d.C = (double *)ptrs[9];
+  d.fbar_prev = (double *)ptrs[7]; d.C = (double *)ptrs[8];
   hipError_t e = hipMemcpy(ptrs[0], phibar.data(), phibar.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[1], xbar0.data(), xbar0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[2], ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
@@ -444,8 +588,8 @@ extern "C" int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *x
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   const RomDev &d = rom->d;
-  const size_t lds = run_lds_bytes(d.M, d.Mr, d.nd);
-  const int use_lds = lds <= kMaxDynLds;
+  const size_t lds = run_lds_bytes(d.Mr, d.nd, d.ldc);
+  const int use_lds = lds <= rom->max_dyn_lds;
   const size_t shmem = use_lds ? lds : 0;
   if (d.jac_mode == PTROM_JAC_EXACT)
     hipLaunchKernelGGL(rom_run_kernel<true>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, xhat,

@@ -48,12 +48,15 @@ def test_pod_matches_oracle_svd(dev):
     Phi_o, sig_o = oo.pod(S, M)
     Phi_g, sig_g = po.pod(torch.tensor(np.ascontiguousarray(S.T), device=dev), M)
     Phi_g = Phi_g.cpu().numpy().T
-    np.testing.assert_allclose(sig_g, sig_o, rtol=1e-10)
+    # the method of snapshots works on S^T S, whose eigenvalues carry an
+    # absolute error of order nd eps sigma_1^2 (Gram rounding); a mode's error
+    # is that over its eigenvalue gap, here of the order of sigma_m^2
+    err2 = 10 * nd * EPS * sig_o[0] ** 2
+    np.testing.assert_allclose(sig_g ** 2, sig_o ** 2, rtol=0, atol=err2)
     np.testing.assert_allclose(Phi_g.T @ Phi_g, np.eye(M), atol=1e-13)
     # the same signs: each mode's largest-magnitude entry is positive
     for m in range(M):
-        # Gram route loses accuracy as sigma_m^2 / sigma_1^2 shrinks
-        assert np.abs(Phi_g[:, m] - Phi_o[:, m]).max() <= 1e-12 * (sig_o[0] / sig_o[m]) ** 2
+        assert np.abs(Phi_g[:, m] - Phi_o[:, m]).max() <= err2 / sig_o[m] ** 2
 
 
 def test_single_vortex_training_and_online_rom(dev):

@@ -147,3 +147,45 @@ def test_surrogate_on_its_target_at_zero_core(dev, trained, mode):
     assert rel(gf.cpu().numpy(), fb) <= 1e-5
     assert rel(gr.cpu().numpy(), rb) <= 1e-5
     assert rel(gC.cpu().numpy() - a["Phibar"], C - a["Phibar"]) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def trained_shapes():
+    """Well-conditioned artifacts at the paper's single-vortex sizes (M = 21,
+    M_r = n_s = 42), at the largest supported basis (M = 32, M_r = 64) and
+    with a sample set too large for the run kernel's LDS copies (n_s = 400).
+    Phi and Phi_r are random orthonormal bases (a trained basis of this rank
+    would need far richer snapshots); the clustering, sampling and gappy
+    operator are built exactly as in training."""
+    out = {}
+    cl = W.counter_rotating_patches(640, seed=41, delta=0.02)
+    n = cl.n
+    rng = np.random.default_rng(42)
+    for M, Mr, ns in [(21, 42, 42), (32, 64, 32), (8, 16, 400)]:
+        Phi = np.linalg.qr(rng.standard_normal((2 * n, M)))[0]
+        sig = np.sort(rng.uniform(1.0, 10.0, M))[::-1]
+        tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+        sample = np.sort(rng.choice(n, ns, replace=False))
+        Phi_r = np.linalg.qr(rng.standard_normal((2 * n, Mr)))[0]
+        A = off.gappy_operator(Phi_r, sample)
+        out[(M, Mr, ns)] = rounded(off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A))
+    return out
+
+
+@pytest.mark.parametrize("shape", [(21, 42, 42), (32, 64, 32), (8, 16, 400)])
+@pytest.mark.parametrize("mode", [native.JAC_PAPER, native.JAC_EXACT])
+def test_rom_run_shapes(dev, trained_shapes, shape, mode):
+    art = trained_shapes[shape]
+    M = shape[0]
+    steps, K = 12, 3
+    o = oracle.Rom(art, jac_mode=mode).run(steps, tol=0.0, max_iter=K)
+    rom = native.Rom(art, tol=0.0, max_iter=K, jac_mode=mode)
+    xh = torch.zeros(M, dtype=torch.float64, device=dev)
+    hist = torch.empty(steps * M, dtype=torch.float64, device=dev)
+    it = torch.empty(steps, dtype=torch.int32, device=dev)
+    rom.run(steps, xh, hist, it)
+    torch.cuda.synchronize()
+    assert np.all(it.cpu().numpy() == K)
+    h = hist.cpu().numpy().reshape(steps, M)
+    assert np.all(np.isfinite(h))
+    assert rel(h, o["hist"]) <= 1e-5
