@@ -242,13 +242,14 @@ int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const double *xbar_p
 /* nsteps online time steps in one device-resident launch (one workgroup),
  * starting from xhat (device FP64 [M], updated in place).  Per step:
  * Gauss-Newton iterations (Algorithm "Gauss-Newton") of HyperPair + the FP64
- * least-squares step dxhat = -argmin |A C nu + A rbar|, solved by Cholesky
- * of (AC)^T (AC) with one refinement on the true residual, xhat += alpha
- * dxhat, until the relative reduced gradient |(AC)^T A rbar| / (its
- * first-iteration value) <= tol or max_iter iterations.  A direction with a
- * non-positive Cholesky pivot is left out of the step.  xhat_hist (device
- * [nsteps][M]) and iters (device int32 [nsteps]) may be NULL.  Asynchronous;
- * iteration caps are reported in iters only. */
+ * least-squares step dxhat = -argmin |A C nu + A rbar|, solved through the
+ * normal equations (AC)^T (AC) by Gauss-Jordan elimination with one
+ * refinement on the true residual, xhat += alpha dxhat, until the relative
+ * reduced gradient |(AC)^T A rbar| / (its first-iteration value) <= tol or
+ * max_iter iterations.  A direction with a non-positive pivot is left out of
+ * the step.  xhat_hist (device [nsteps][M]) and iters (device int32
+ * [nsteps]) may be NULL.  Asynchronous; iteration caps are reported in iters
+ * only. */
 int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, int32_t *iters,
                   ptrom_stream stream);
 

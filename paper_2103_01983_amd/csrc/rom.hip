@@ -2,30 +2,31 @@
 // Gauss-Newton loop around it (Algorithm "Gauss-Newton").
 //
 // Entry layout.  Each interaction-list entry e = (target i, surrogate c) is
-// stored as r0_e = xbar0_i - xqt0_c (2), Gamma~_c, pad, D_e = Phibar_i - Phit_c
-// (2 x M), so that the pair separation at generalized coordinates xhat is
+// stored as r0_e = xbar0_i - xqt0_c (2), Gamma~_c, pad, then the columns of
+// D_e = Phibar_i - Phit_c as (x, y) pairs (2 x M), so that the pair separation at generalized coordinates xhat is
 // r_e = r0_e + D_e xhat, which equals xbar_i - p_c with p_c = xqt0_c + Phit_c
 // xhat (Algorithm "HyperPair" preamble).  The gather then streams contiguous
 // entry rows (coalesced) with no projection pass and no indirection.
 //
-// Per Gauss-Newton iteration:
-//   gather    one wave64 per sampled target walks its entries (lanes stride),
-//             does the pair arithmetic in FP32 (velocity and the 2x2 self
-//             block B_i; in the exact mode sum_e G_e D_e instead), reduces
-//             across the wave with DPP row reductions, and writes the
-//             trapezoid residual rows rbar = xbar - xbar_prev - dt/2 (fbar +
-//             fbar_prev) and the rows of C = Phibar - dt/2 dfbar/dxhat (FP64);
-//   solve     G' = A [C | rbar] (FP64, four columns per thread), the Gram
-//             matrix G'^T G' = [G^T G, G^T b; ...], the relative reduced
-//             gradient |G^T b| / |G_1^T b_1|, and in one wave a Cholesky
-//             factorisation of G^T G held one row per lane, forward and back
-//             substitution by lane broadcasts, and one refinement step on the
-//             true residual b - G x (corrected semi-normal equations), then
+// Per Gauss-Newton iteration (ptrom_rom_run, one workgroup of 512 threads):
+//   gather    paper Jacobian, when the per-entry terms fit in LDS: one thread
+//             per list entry computes the pair terms in FP32 (each entry row
+//             is loaded whole), groups of 16/32/64 lanes add them per target
+//             (DPP row reductions) and write the velocity and trapezoid
+//             residual rows rbar = xbar - xbar_prev - dt/2 (fbar + fbar_prev)
+//             and the 2x2 blocks B_i, then one thread per element forms
+//             C = Phibar - dt/2 B Phibar (FP64).  Otherwise (exact Jacobian,
+//             long lists) a group of lanes per target does all of that.
+//   solve     G' = A [C | rbar] and the Gram matrix G'^T G' = [G^T G, G^T b;
+//             ...] on the FP64 matrix cores, the relative reduced gradient
+//             |G^T b| / |G_1^T b_1|, Gauss-Jordan inversion of G^T G inside
+//             one wave (columns in registers, pivot columns broadcast from
+//             their lanes, no barriers), x = (G^T G)^+ G^T b and one
+//             refinement step on the true residual b - G x, then
 //             xhat -= alpha x.
-// ptrom_rom_run keeps the whole loop (all steps, all iterations) inside one
-// workgroup with A, [C | rbar] and the previous-step rows in LDS when they
-// fit; ptrom_rom_hyperpair runs the gather over many workgroups (large sample
-// sets).
+// A, [C | rbar], Phibar, xbar0 and the previous-step rows live in LDS when
+// they fit.  ptrom_rom_hyperpair runs the gather over many workgroups, one
+// wave per target (large sample sets).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -38,18 +39,17 @@ namespace {
 
 constexpr int kMaxM = 32;
 constexpr int kMaxMr = 64;
-constexpr int kMaxLdc = 36;   // columns of [C | rbar] rounded up to 4
 constexpr int kLt = kMaxM + 1;  // row stride of the transposed factor in LDS (bank spread)
-constexpr int kRunThreads = 1024;
+constexpr int kRunThreads = 512;  // 8 waves: up to 256 VGPRs per lane
 constexpr double kInv2PiD = 0.15915494309189533576888376337251;
 
 struct RomDev {
-  int M, Mr, ns, nd, jac_mode, max_iter, ew, ldc;
+  int M, Mr, ns, nd, jac_mode, max_iter, ew, ldc, glanes, maxlen;
   int64_t nnz;
   float d2, dt;
   double tol, alpha;
   const float *Phibar, *xbar0;  // [nd][M], [nd]
-  const float *ent;             // [nnz][ew]: r0x r0y Gamma pad Dx[M] Dy[M]
+  const float *ent;             // [nnz][ew]: r0x r0y Gamma pad (Dx_m Dy_m) pairs
   const int *off;               // [ns+1]
   const double *A;              // [Mr][nd]
   // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
@@ -106,114 +106,170 @@ __device__ __forceinline__ double wsumd(double v) {
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
-// xbar_i (both rows) at xhat, FP64
-__device__ __forceinline__ void sampled_position(const RomDev &d, int i, const double *xh, double &tx,
-                                                 double &ty) {
-  const int M = d.M, ns = d.ns;
-  tx = d.xbar0[i];
-  ty = d.xbar0[ns + i];
-  const float *px = d.Phibar + (size_t)i * M, *py = d.Phibar + (size_t)(ns + i) * M;
+// xbar_i (both rows) at xhat, FP64; Phibar [nd][M] and xbar0 [nd] (FP32)
+__device__ __forceinline__ void sampled_position(const float *Phibar, const float *xbar0, int M, int ns, int i,
+                                                 const double *xh, double &tx, double &ty) {
+  tx = xbar0[i];
+  ty = xbar0[ns + i];
+  const float *px = Phibar + (size_t)i * M, *py = Phibar + (size_t)(ns + i) * M;
   for (int m = 0; m < M; ++m) {
     tx += (double)px[m] * xh[m];
     ty += (double)py[m] * xh[m];
   }
 }
 
-// HyperPair rows of sampled target i, computed by one whole wave.
-// xh: FP64 xhat, xf: FP32 copy.  Any output pointer may be null.  Row q of
-// rbar is rbar_out[q * rs], row q of C is C_out[q * ldc .. + M).
-template <bool EXACT>
-__device__ void gather_target(const RomDev &d, int i, int lane, const double *xh, const float *xf,
-                              const double *xbar_prev, const double *fbar_prev, double *xbar_out,
-                              double *fbar_out, double *rbar_out, int rs, double *C_out, int ldc) {
-  const int M = d.M, ns = d.ns, ew = d.ew;
-  double tx, ty;
-  sampled_position(d, i, xh, tx, ty);
-  float fx = 0.f, fy = 0.f, ba = 0.f, bb = 0.f, bc = 0.f;
-  float ex[EXACT ? kMaxM : 1], ey[EXACT ? kMaxM : 1];
-  if constexpr (EXACT) {
+// One entry row in registers: r0x r0y Gamma~ pad, then (Dx_m, Dy_m) pairs,
+// padded to whole float4 chunks.
+constexpr int kMaxEw = 4 + 2 * kMaxM;
+
+constexpr int kShortEw = 36;  // rows of bases with M <= 16
+
+template <int EW>
+__device__ __forceinline__ void load_entry(const float *ent, int ew, int e, float (&v)[EW]) {
+  const float4 *p = reinterpret_cast<const float4 *>(ent + (size_t)e * ew);
 #pragma unroll
-    for (int m = 0; m < kMaxM; ++m) ex[m] = ey[m] = 0.f;
+  for (int c = 0; c < EW / 4; ++c) {
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c * 4 < ew) q = p[c];
+    v[4 * c] = q.x;
+    v[4 * c + 1] = q.y;
+    v[4 * c + 2] = q.z;
+    v[4 * c + 3] = q.w;
   }
-  const int e0 = d.off[i], e1 = d.off[i + 1];
-  for (int e = e0 + lane; e < e1; e += 64) {
-    const float *E = d.ent + (size_t)e * ew;
-    const float4 head = *reinterpret_cast<const float4 *>(E);
-    float rx = head.x, ry = head.y;
-    const float *Dx = E + 4, *Dy = E + 4 + M;
-    for (int m = 0; m < M; ++m) {
-      rx = fmaf(Dx[m], xf[m], rx);
-      ry = fmaf(Dy[m], xf[m], ry);
-    }
-    const float q = fmaf(rx, rx, fmaf(ry, ry, d.d2));
-    // a surrogate exactly on its target (possible at delta = 0) adds nothing
-    const float r = q > 0.f ? 1.0f / q : 0.f;
-    const float g = head.z * r;
-    fx = fmaf(-ry, g, fx);
-    fy = fmaf(rx, g, fy);
-    const float g2 = g * r;
-    const float a2 = (rx + rx) * ry;
-    const float dd = fmaf(ry, ry, -rx * rx);
-    if constexpr (EXACT) {
-      const float h00 = g2 * a2, h01 = g2 * (dd - d.d2), h10 = g2 * (dd + d.d2);
+}
+
+template <bool EXACT>
+struct GatherAcc {
+  float fx = 0.f, fy = 0.f, ba = 0.f, bb = 0.f, bc = 0.f;
+  float ex[EXACT ? kMaxM : 1] = {}, ey[EXACT ? kMaxM : 1] = {};
+};
+
+// Velocity and Jacobian terms of one (target, surrogate) entry at xhat:
+// r = r0 + D xhat; the 2x2 block (or, exact mode, its product with D).
+template <bool EXACT, int EW>
+__device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *row, const float *xf, int M,
+                                            float d2, GatherAcc<EXACT> &a) {
+  float rx = v[0], ry = v[1];
 #pragma unroll
-      for (int m = 0; m < kMaxM; ++m) {
-        if (m < M) {
-          ex[m] = fmaf(h00, Dx[m], fmaf(h01, Dy[m], ex[m]));
-          ey[m] = fmaf(h10, Dx[m], fmaf(-h00, Dy[m], ey[m]));
+  for (int m = 0; m < (EW - 4) / 2; ++m)
+    if (m < M) {
+      rx = fmaf(v[4 + 2 * m], xf[m], rx);
+      ry = fmaf(v[5 + 2 * m], xf[m], ry);
+    }
+  const float q = fmaf(rx, rx, fmaf(ry, ry, d2));
+  // a surrogate exactly on its target (possible at delta = 0) adds nothing
+  const float r = q > 0.f ? 1.0f / q : 0.f;
+  const float g = v[2] * r;
+  a.fx = fmaf(-ry, g, a.fx);
+  a.fy = fmaf(rx, g, a.fy);
+  const float g2 = g * r;
+  const float a2 = (rx + rx) * ry;
+  const float dd = fmaf(ry, ry, -rx * rx);
+  if constexpr (EXACT) {
+    // D re-read from the row (cache hit) so the register copy is not kept live
+    const float h00 = g2 * a2, h01 = g2 * (dd - d2), h10 = g2 * (dd + d2);
+#pragma unroll
+    for (int m = 0; m < kMaxM; ++m)
+      if (m < M) {
+        const float dx = row[4 + 2 * m], dy = row[5 + 2 * m];
+        a.ex[m] = fmaf(h00, dx, fmaf(h01, dy, a.ex[m]));
+        a.ey[m] = fmaf(h10, dx, fmaf(-h00, dy, a.ey[m]));
+      }
+  } else {
+    a.ba = fmaf(g2, a2, a.ba);
+    a.bb = fmaf(g2, dd - d2, a.bb);
+    a.bc = fmaf(g2, dd + d2, a.bc);
+  }
+}
+
+// Sum over an aligned group of G = 16, 32 or 64 lanes (G uniform); every lane
+// of the group receives the same value.  All 64 lanes must be active.
+__device__ __forceinline__ float gsum(float v, int G) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G == 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// HyperPair rows of sampled target t, computed by a group of G lanes (gl =
+// lane in the group).  Lanes of invalid groups (t >= ns) take part in the
+// group sums only.  xh: FP64 xhat, xf: FP32 copy; Phibar / xbar0 may be LDS
+// copies.  Any output pointer may be null.  Row q of rbar is rbar_out[q * rs],
+// row q of C is C_out[q * ldc .. + M).
+template <bool EXACT>
+__device__ void gather_group(const RomDev &d, const float *Phibar, const float *xbar0, int t, bool valid, int gl,
+                             int G, const double *xh, const float *xf, const double *xbar_prev,
+                             const double *fbar_prev, double *xbar_out, double *fbar_out, double *rbar_out, int rs,
+                             double *C_out, int ldc) {
+  const int M = d.M, ns = d.ns;
+  GatherAcc<EXACT> a;
+  if (valid) {
+    // two entries per lane per pass: both rows are requested before either
+    // is used, halving the exposed load latency on long lists
+    const int e1 = d.off[t + 1];
+    int e = d.off[t] + gl;
+    if constexpr (!EXACT) {
+      if (d.ew <= kShortEw) {
+        for (; e + G < e1; e += 2 * G) {
+          float v0[kShortEw], v1[kShortEw];
+          load_entry(d.ent, d.ew, e, v0);
+          load_entry(d.ent, d.ew, e + G, v1);
+          entry_terms<false>(v0, nullptr, xf, M, d.d2, a);
+          entry_terms<false>(v1, nullptr, xf, M, d.d2, a);
         }
       }
-    } else {
-      ba = fmaf(g2, a2, ba);
-      bb = fmaf(g2, dd - d.d2, bb);
-      bc = fmaf(g2, dd + d.d2, bc);
+    }
+    for (; e < e1; e += G) {
+      float v[kMaxEw];
+      load_entry(d.ent, d.ew, e, v);
+      entry_terms<EXACT>(v, d.ent + (size_t)e * d.ew, xf, M, d.d2, a);
     }
   }
-  const double Fx = wsum(fx) * kInv2PiD, Fy = wsum(fy) * kInv2PiD;
+  const double Fx = gsum(a.fx, G) * kInv2PiD, Fy = gsum(a.fy, G) * kInv2PiD;
   const double hdt = 0.5 * (double)d.dt;
-  if (lane == 0) {
+  if (valid && gl == 0) {
+    double tx, ty;
+    sampled_position(Phibar, xbar0, M, ns, t, xh, tx, ty);
     if (xbar_out) {
-      xbar_out[i] = tx;
-      xbar_out[ns + i] = ty;
+      xbar_out[t] = tx;
+      xbar_out[ns + t] = ty;
     }
     if (fbar_out) {
-      fbar_out[i] = Fx;
-      fbar_out[ns + i] = Fy;
+      fbar_out[t] = Fx;
+      fbar_out[ns + t] = Fy;
     }
     if (rbar_out) {
-      rbar_out[(size_t)i * rs] = (tx - xbar_prev[i]) - hdt * (Fx + fbar_prev[i]);
-      rbar_out[(size_t)(ns + i) * rs] = (ty - xbar_prev[ns + i]) - hdt * (Fy + fbar_prev[ns + i]);
+      rbar_out[(size_t)t * rs] = (tx - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+      rbar_out[(size_t)(ns + t) * rs] = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
     }
   }
   if (C_out) {
     if constexpr (EXACT) {
-      // C_i = Phibar_i - dt/2 sum_e G_e (Phibar_i - Phit_c)
-      double jx = 0.0, jy = 0.0;
+      // C_t = Phibar_t - dt/2 sum_e G_e (Phibar_t - Phit_c)
 #pragma unroll
       for (int m = 0; m < kMaxM; ++m) {
         if (m < M) {
-          const float sx = wsum(ex[m]), sy = wsum(ey[m]);
-          if (lane == m) {
-            jx = sx * kInv2PiD;
-            jy = sy * kInv2PiD;
+          const double jx = gsum(a.ex[m], G) * kInv2PiD, jy = gsum(a.ey[m], G) * kInv2PiD;
+          if (valid && gl == (m & (G - 1))) {
+            const double px = Phibar[(size_t)t * M + m], py = Phibar[(size_t)(ns + t) * M + m];
+            C_out[(size_t)t * ldc + m] = px - hdt * jx;
+            C_out[(size_t)(ns + t) * ldc + m] = py - hdt * jy;
           }
         }
       }
-      if (lane < M) {
-        const int m = lane;
-        const double px = d.Phibar[(size_t)i * M + m], py = d.Phibar[(size_t)(ns + i) * M + m];
-        C_out[(size_t)i * ldc + m] = px - hdt * jx;
-        C_out[(size_t)(ns + i) * ldc + m] = py - hdt * jy;
-      }
     } else {
-      // C_i = Phibar_i - dt/2 B_i Phibar_i (the paper's inexact Jacobian)
-      const double B00 = wsum(ba) * kInv2PiD, B01 = wsum(bb) * kInv2PiD, B10 = wsum(bc) * kInv2PiD;
-      if (lane < M) {
-        const int m = lane;
-        const double px = d.Phibar[(size_t)i * M + m], py = d.Phibar[(size_t)(ns + i) * M + m];
-        C_out[(size_t)i * ldc + m] = px - hdt * (B00 * px + B01 * py);
-        C_out[(size_t)(ns + i) * ldc + m] = py - hdt * (B10 * px - B00 * py);
-      }
+      // C_t = Phibar_t - dt/2 B_t Phibar_t (the paper's inexact Jacobian)
+      const double B00 = gsum(a.ba, G) * kInv2PiD, B01 = gsum(a.bb, G) * kInv2PiD,
+                   B10 = gsum(a.bc, G) * kInv2PiD;
+      if (valid)
+        for (int m = gl; m < M; m += G) {
+          const double px = Phibar[(size_t)t * M + m], py = Phibar[(size_t)(ns + t) * M + m];
+          C_out[(size_t)t * ldc + m] = px - hdt * (B00 * px + B01 * py);
+          C_out[(size_t)(ns + t) * ldc + m] = py - hdt * (B10 * px - B00 * py);
+        }
     }
   }
 }
@@ -234,69 +290,86 @@ __global__ void __launch_bounds__(256)
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= d.ns) return;
-  gather_target<EXACT>(d, wave, lane, xh, xf, xbar_prev, fbar_prev, xbar, fbar, rbar, 1, C, d.M);
+  gather_group<EXACT>(d, d.Phibar, d.xbar0, wave, true, lane, 64, xh, xf, xbar_prev, fbar_prev, xbar, fbar, rbar, 1,
+                      C, d.M);
 }
 
 // ----------------------------------------------------------- device-resident loop
 
-// Solves (L L^T) x = rhs for the factor held one row per lane (a[j] = L_lj on
-// lane l, j <= l) and its transpose in LDS (Lt[i * kLt + k] = L_ki).  rhs_i is
-// given on lane i; x is written to xs[] and lane i's component returned.  A
-// zero pivot drops its direction (component 0).
-__device__ __forceinline__ double chol_solve(const double (&a)[kMaxM], const double *Lt, int M, int lane,
-                                             double rhs, double *xs) {
-  // forward: L y = rhs; lane i keeps rhs_i - sum_{j<k} L_ij y_j
-  double acc = rhs, ymine = 0.0;
-#pragma unroll
-  for (int k = 0; k < kMaxM; ++k) {
-    if (k < M) {
-      const double lkk = lane_d(a[k], k);
-      const double yk = lkk != 0.0 ? lane_d(acc, k) / lkk : 0.0;
-      if (lane == k) ymine = yk;
-      acc = fma(-a[k], yk, acc);
-    }
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 tile of D = X Y (X: rows x K, Y: K x cols) on one wave with the
+// FP64 matrix-core instruction (16 x 16 x 4 per step): lane l supplies
+// X(l % 16, k0 + l / 16) and Y(k0 + l / 16, l % 16) and receives, in register
+// r, D(4 r + l / 16, l % 16) (tile-local indices).  xa / yb return 0 outside
+// the matrices.  The wave must be fully active.
+template <class FX, class FY>
+__device__ __forceinline__ dbl4 mfma_tile(int K, int lane, FX xa, FY yb) {
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int r = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + kq;
+    const double a = k < K ? xa(r, k) : 0.0;
+    const double b = k < K ? yb(k, r) : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  // backward: L^T x = y; lane i keeps y_i - sum_{j>k} L_ji x_j
-  double acc2 = ymine, xmine = 0.0;
-#pragma unroll
-  for (int k = kMaxM - 1; k >= 0; --k) {
-    if (k < M) {
-      const double ukk = lane_d(a[k], k);
-      const double xk = ukk != 0.0 ? lane_d(acc2, k) / ukk : 0.0;
-      if (lane == k) xmine = xk;
-      if (lane == 0) xs[k] = xk;
-      if (lane < k) acc2 = fma(-Lt[lane * kLt + k], xk, acc2);
-    }
-  }
-  return xmine;
+  return acc;
+}
+
+// Sum over aligned groups of 8 lanes (all lanes active); every lane of the
+// group receives the sum.
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  return v;
 }
 
 template <bool EXACT>
 __global__ void __launch_bounds__(kRunThreads)
-    rom_run_kernel(RomDev d, int nsteps, int lds_arrays, double *__restrict__ xhat, double *__restrict__ hist,
-                   int *__restrict__ iters) {
+    rom_run_kernel(RomDev d, int nsteps, int lds_arrays, int entry_par, double *__restrict__ xhat,
+                   double *__restrict__ hist, int *__restrict__ iters) {
   __shared__ double xh[kMaxM];
   __shared__ float xf[kMaxM];
-  __shared__ double Gp[kMaxMr * kMaxLdc];          // G' = A [C | rbar | 0]
-  __shared__ double Nw[(kMaxM + 1) * (kMaxM + 1)];  // G'^T G', then L^T
-  __shared__ double rr[kMaxMr], xs[kMaxM], dxs[kMaxM];
-  __shared__ double s_eps, s_g1;
+  __shared__ double rr[kMaxMr], gq[kMaxM], xs[kMaxM], gvec[kMaxM];
+  __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
-  const int M = d.M, Mr = d.Mr, nd = d.nd, ldc = d.ldc, M1 = M + 1;
+  const int M = d.M, Mr = d.Mr, nd = d.nd, ns = d.ns, ldc = d.ldc, M1 = M + 1;
+  const int lg = M1;  // row stride of G'
+  const double hdt = 0.5 * (double)d.dt;
+  // G' = A [C | rbar] (Mr x (M + 1)) and the Gauss-Jordan tableau [N | I]
+  // (rows padded to kMaxM, columns to 64: one column per lane of a wave) at
+  // the front of the dynamic LDS
+  double *Gp = dyn, *T0 = Gp + (size_t)Mr * lg;
 
-  // A, [C | rbar], fbar, fbar_prev, xbar_prev: LDS copies when they fit
+  // A, [C | rbar], fbar, fbar_prev, xbar_prev, the per-target 2x2 blocks,
+  // Phibar, xbar0 and the per-entry terms: LDS copies when they fit
   const double *A = d.A;
-  double *Cp = d.C, *fbar = d.fbar, *fbar_prev = d.fbar_prev, *xbar_prev = d.xbar_prev;
+  const float *Phibar = d.Phibar, *xbar0 = d.xbar0;
+  double *Cp = d.C, *fbar = d.fbar, *fbar_prev = d.fbar_prev, *xbar_prev = d.xbar_prev, *bt = nullptr,
+         *xcur = nullptr;
+  float *ct = nullptr;
   if (lds_arrays) {
-    double *p = dyn;
+    double *p = T0 + (size_t)kMaxM * 64;
     double *Al = p; p += (size_t)Mr * nd;
     Cp = p; p += (size_t)nd * ldc;
     fbar = p; p += nd;
     fbar_prev = p; p += nd;
-    xbar_prev = p;
+    xbar_prev = p; p += nd;
+    bt = p; p += 3 * (size_t)ns;
+    xcur = p; p += nd;
+    float *f = reinterpret_cast<float *>(p);
+    float *Pl = f; f += (size_t)nd * M;
+    float *xl = f; f += nd;
+    ct = f;
     for (int t = tid; t < Mr * nd; t += kRunThreads) Al[t] = d.A[t];
+    for (int t = tid; t < nd * M; t += kRunThreads) Pl[t] = d.Phibar[t];
+    for (int t = tid; t < nd; t += kRunThreads) xl[t] = d.xbar0[t];
     A = Al;
+    Phibar = Pl;
+    xbar0 = xl;
   }
   for (int t = tid; t < nd * ldc; t += kRunThreads) Cp[t] = 0.0;  // padding columns stay zero
   if (tid < M) {
@@ -304,106 +377,222 @@ __global__ void __launch_bounds__(kRunThreads)
     xf[tid] = (float)xhat[tid];
   }
   __syncthreads();
+  // targets are taken by groups of G lanes, 64 / G per wave
+  const int G = d.glanes, tpw = 64 / G, gl = lane & (G - 1), slot = lane / G;
   // previous-step terms for the first step: HyperPair at the initial xhat
-  for (int i = wave; i < d.ns; i += nwaves)
-    gather_target<EXACT>(d, i, lane, xh, xf, nullptr, nullptr, xbar_prev, fbar_prev, nullptr, 0, nullptr, 0);
+  for (int base = wave * tpw; base < ns; base += nwaves * tpw)
+    gather_group<EXACT>(d, Phibar, xbar0, base + slot, base + slot < ns, gl, G, xh, xf, nullptr, nullptr,
+                        xbar_prev, fbar_prev, nullptr, 0, nullptr, 0);
   __syncthreads();
 
-  const int nblk = ldc / 4;
-  const int npair = M1 * (M1 + 1) / 2;
+  const int tr = (Mr + 15) / 16, tc = (M1 + 15) / 16;
+  const int nnz = (int)d.nnz;
   for (int step = 0; step < nsteps; ++step) {
     int k = 1;
     for (;;) {
-      for (int i = wave; i < d.ns; i += nwaves)
-        gather_target<EXACT>(d, i, lane, xh, xf, xbar_prev, fbar_prev, nullptr, fbar, Cp + M, ldc, Cp, ldc);
-      __syncthreads();
-      // G' = A [C | rbar | 0], four columns per thread
-      for (int t = tid; t < Mr * nblk; t += kRunThreads) {
-        const int r = t / nblk, c0 = (t - r * nblk) * 4;
-        const double *arow = A + (size_t)r * nd;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int q = 0; q < nd; ++q) {
-          const double av = arow[q];
-          const double *c = Cp + (size_t)q * ldc + c0;
-          s0 = fma(av, c[0], s0);
-          s1 = fma(av, c[1], s1);
-          s2 = fma(av, c[2], s2);
-          s3 = fma(av, c[3], s3);
+      // ---- HyperPair: velocity rows, residual rows (column M of [C | rbar]) and C
+      if (!EXACT && entry_par) {
+        // one thread per entry; the five per-entry terms go to LDS.  The
+        // sampled rows at the current xhat are formed alongside.
+        for (int e = tid; e < nnz; e += kRunThreads) {
+          float v[kMaxEw];
+          load_entry(d.ent, d.ew, e, v);
+          GatherAcc<false> a;
+          entry_terms<false>(v, nullptr, xf, M, d.d2, a);
+          ct[e] = a.fx;
+          ct[nnz + e] = a.fy;
+          ct[2 * nnz + e] = a.ba;
+          ct[3 * nnz + e] = a.bb;
+          ct[4 * nnz + e] = a.bc;
         }
-        double *g = Gp + r * ldc + c0;
-        g[0] = s0;
-        g[1] = s1;
-        g[2] = s2;
-        g[3] = s3;
-      }
-      __syncthreads();
-      // G'^T G' over the first M + 1 columns (lower triangle, mirrored)
-      for (int t = tid; t < npair; t += kRunThreads) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= t) ++i;
-        const int j = t - i * (i + 1) / 2;
-        double sum = 0.0;
-        for (int r = 0; r < Mr; ++r) sum = fma(Gp[r * ldc + i], Gp[r * ldc + j], sum);
-        Nw[i * M1 + j] = sum;
-        Nw[j * M1 + i] = sum;
-      }
-      __syncthreads();
-      if (wave == 0) {
-        // relative reduced gradient |G^T b| / |G_1^T b_1|
-        const double gl = lane < M ? Nw[lane * M1 + M] : 0.0;
-        const double gn = sqrt(wsumd(gl * gl));
-        const double g1 = (k == 1) ? gn : s_g1;
-        const double eps = g1 > 0.0 ? gn / g1 : 0.0;
-        // Cholesky of G^T G, row `lane` in registers
-        double a[kMaxM];
-#pragma unroll
-        for (int j = 0; j < kMaxM; ++j) a[j] = (j < M && lane < M) ? Nw[lane * M1 + j] : 0.0;
-#pragma unroll
-        for (int kk = 0; kk < kMaxM; ++kk) {
-          if (kk < M) {
-            const double piv = lane_d(a[kk], kk);
-            const bool pos = piv > 0.0;
-            const double lkk = pos ? sqrt(piv) : 0.0;
-            const double inv = pos ? 1.0 / lkk : 0.0;
-            a[kk] = lane == kk ? lkk : a[kk] * inv;
-#pragma unroll
-            for (int j = kk + 1; j < kMaxM; ++j) {
-              if (j < M) {
-                const double ljk = lane_d(a[kk], j);
-                a[j] = fma(-a[kk], ljk, a[j]);
+        for (int q = tid; q < nd; q += kRunThreads) {
+          double x = xbar0[q];
+          const float *ph = Phibar + (size_t)q * M;
+          for (int m = 0; m < M; ++m) x += (double)ph[m] * xh[m];
+          xcur[q] = x;
+        }
+        __syncthreads();
+        // per-target sums (one thread per target for short lists, else
+        // groups of G lanes), residual rows and the 2x2 blocks
+        auto finish = [&](int t, float s0, float s1, float s2, float s3, float s4) {
+          const double Fx = s0 * kInv2PiD, Fy = s1 * kInv2PiD;
+          fbar[t] = Fx;
+          fbar[ns + t] = Fy;
+          Cp[(size_t)t * ldc + M] = (xcur[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+          Cp[(size_t)(ns + t) * ldc + M] = (xcur[ns + t] - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+          bt[3 * t] = s2 * kInv2PiD;
+          bt[3 * t + 1] = s3 * kInv2PiD;
+          bt[3 * t + 2] = s4 * kInv2PiD;
+        };
+        if (d.maxlen <= 64) {
+          for (int t = tid; t < ns; t += kRunThreads) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+            const int e1 = d.off[t + 1];
+            for (int e = d.off[t]; e < e1; ++e) {
+              s0 += ct[e];
+              s1 += ct[nnz + e];
+              s2 += ct[2 * nnz + e];
+              s3 += ct[3 * nnz + e];
+              s4 += ct[4 * nnz + e];
+            }
+            finish(t, s0, s1, s2, s3, s4);
+          }
+        } else {
+          for (int base = wave * tpw; base < ns; base += nwaves * tpw) {
+            const int t = base + slot;
+            const bool valid = t < ns;
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+            if (valid) {
+              const int e1 = d.off[t + 1];
+              for (int e = d.off[t] + gl; e < e1; e += G) {
+                s0 += ct[e];
+                s1 += ct[nnz + e];
+                s2 += ct[2 * nnz + e];
+                s3 += ct[3 * nnz + e];
+                s4 += ct[4 * nnz + e];
               }
             }
+            s0 = gsum(s0, G);
+            s1 = gsum(s1, G);
+            s2 = gsum(s2, G);
+            s3 = gsum(s3, G);
+            s4 = gsum(s4, G);
+            if (valid && gl == 0) finish(t, s0, s1, s2, s3, s4);
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // all reads of Nw done
-        // L^T into LDS: Lt[i * kLt + k] = L_ki for k >= i
+        __syncthreads();
+        // C = Phibar - dt/2 B Phibar (the paper's inexact Jacobian), one element per thread
+        for (int q = tid; q < nd * M; q += kRunThreads) {
+          const int row = q / M, m = q - row * M;
+          const int t = row < ns ? row : row - ns;
+          const double px = Phibar[(size_t)t * M + m], py = Phibar[(size_t)(ns + t) * M + m];
+          const double B00 = bt[3 * t], B01 = bt[3 * t + 1], B10 = bt[3 * t + 2];
+          Cp[(size_t)row * ldc + m] = row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py);
+        }
+      } else {
+        for (int base = wave * tpw; base < ns; base += nwaves * tpw)
+          gather_group<EXACT>(d, Phibar, xbar0, base + slot, base + slot < ns, gl, G, xh, xf, xbar_prev,
+                              fbar_prev, nullptr, fbar, Cp + M, ldc, Cp, ldc);
+      }
+      __syncthreads();
+      // ---- G' = A [C | rbar] on the matrix cores (Mr x (M + 1))
+      for (int tile = wave; tile < tr * tc; tile += nwaves) {
+        const int i0 = (tile / tc) * 16, j0 = (tile % tc) * 16;
+        const dbl4 acc = mfma_tile(
+            nd, lane, [&](int i, int q) { return i0 + i < Mr ? A[(size_t)(i0 + i) * nd + q] : 0.0; },
+            [&](int q, int j) { return j0 + j < ldc ? Cp[(size_t)q * ldc + j0 + j] : 0.0; });
 #pragma unroll
-        for (int j = 0; j < kMaxM; ++j)
-          if (j < M && lane < M && lane >= j) Nw[j * kLt + lane] = a[j];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        double xl = chol_solve(a, Nw, M, lane, gl, xs);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // one refinement step on the true residual: r' = b - G x, G^T r'
-        if (lane < Mr) {
-          double rv = Gp[lane * ldc + M];
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + 4 * r + (lane >> 4), col = j0 + (lane & 15);
+          if (row < Mr && col < M1) Gp[row * lg + col] = acc[r];
+        }
+      }
+      __syncthreads();
+      // ---- Gram G'^T G' into the tableau [N | I | g]: N = G^T G, g = G^T b
+      for (int tile = wave; tile < tc * tc; tile += nwaves) {
+        const int i0 = (tile / tc) * 16, j0 = (tile % tc) * 16;
+        const dbl4 acc = mfma_tile(
+            Mr, lane, [&](int i, int q) { return i0 + i < M1 ? Gp[q * lg + i0 + i] : 0.0; },
+            [&](int q, int j) { return j0 + j < M1 ? Gp[q * lg + j0 + j] : 0.0; });
 #pragma unroll
-          for (int j = 0; j < kMaxM; ++j)
-            if (j < M) rv = fma(-Gp[lane * ldc + j], xs[j], rv);
-          rr[lane] = rv;
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + 4 * r + (lane >> 4), col = j0 + (lane & 15);
+          if (row < M && col < M) T0[row * 64 + col] = acc[r];
+          if (row < M && col == M) gvec[row] = acc[r];
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        double g2 = 0.0;
-        if (lane < M)
-          for (int r = 0; r < Mr; ++r) g2 = fma(Gp[r * ldc + lane], rr[r], g2);
-        xl += chol_solve(a, Nw, M, lane, g2, dxs);
-        if (lane < M) {
-          xh[lane] -= d.alpha * xl;
-          xf[lane] = (float)xh[lane];
+      }
+      // identity block and zero padding of the tableau
+      for (int t = tid; t < kMaxM * 64; t += kRunThreads) {
+        const int i = t >> 6, j = t & 63;
+        if (i >= M || j >= M) T0[t] = (i < M && j - M == i) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      // ---- in wave 0: the relative reduced gradient |G^T b| / |G_1^T b_1|,
+      // then Gauss-Jordan inversion of N = G^T G (symmetric positive
+      // semi-definite) on the tableau [N | I] in LDS, lane j owning column j
+      // (a wave needs no barriers).  Each step loads the pivot column and
+      // the lane's own column in chunks of 8 rows (rows past M are padding),
+      // updates them and stores them back.  A non-positive pivot leaves its
+      // direction out (its row of the inverse is zero).
+      if (wave == 0) {
+        const double gv = lane < M ? gvec[lane] : 0.0;
+        const double gn = sqrt(wsumd(gv * gv));
+        if (lane == 0) s_gn = gn;
+        for (int kk = 0; kk < M; ++kk) {
+          const double piv = T0[kk * 64 + kk];
+          double ip = 0.0;
+          if (piv > 0.0) {
+            // reciprocal: hardware estimate refined by two Newton steps
+            ip = __builtin_amdgcn_rcp(piv);
+            ip = fma(ip, fma(-piv, ip, 1.0), ip);
+            ip = fma(ip, fma(-piv, ip, 1.0), ip);
+          }
+          const double rk = T0[kk * 64 + lane] * ip;
+#pragma unroll
+          for (int i0 = 0; i0 < kMaxM; i0 += 8) {
+            if (i0 < M) {
+              double c[8], o[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) c[u] = T0[(i0 + u) * 64 + kk];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) o[u] = T0[(i0 + u) * 64 + lane];
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+              for (int u = 0; u < 8; ++u) T0[(i0 + u) * 64 + lane] = i0 + u == kk ? rk : fma(-c[u], rk, o[u]);
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        if (lane == 0) {
-          if (k == 1) s_g1 = gn;
-          s_eps = eps;
-        }
+      }
+      __syncthreads();
+      // ---- x = N^+ g, then one refinement step: r' = b - G x, g' = G^T r',
+      // x += N^+ g' (8 lanes per dot product)
+      const double *Pc = T0;
+      {
+        const int o = tid >> 3, part = tid & 7;
+        double s = 0.0;
+        if (o < M)
+          for (int j = part; j < M; j += 8) s = fma(Pc[o * 64 + M + j], gvec[j], s);
+        s = sum8(s);
+        if (o < M && part == 0) xs[o] = s;
+      }
+      __syncthreads();
+      {
+        const int o = tid >> 3, part = tid & 7;
+        double s = 0.0;
+        if (o < Mr)
+          for (int j = part; j < M; j += 8) s = fma(Gp[o * lg + j], xs[j], s);
+        s = sum8(s);
+        if (o < Mr && part == 0) rr[o] = Gp[o * lg + M] - s;
+      }
+      __syncthreads();
+      {
+        const int o = tid >> 3, part = tid & 7;
+        double s = 0.0;
+        if (o < M)
+          for (int r = part; r < Mr; r += 8) s = fma(Gp[r * lg + o], rr[r], s);
+        s = sum8(s);
+        if (o < M && part == 0) gq[o] = s;
+      }
+      __syncthreads();
+      {
+        const int o = tid >> 3, part = tid & 7;
+        double s = 0.0;
+        if (o < M)
+          for (int j = part; j < M; j += 8) s = fma(Pc[o * 64 + M + j], gq[j], s);
+        s = sum8(s);
+        if (o < M && part == 0) xs[o] += s;
+      }
+      __syncthreads();
+      if (tid < M) {
+        xh[tid] -= d.alpha * xs[tid];
+        xf[tid] = (float)xh[tid];
+      }
+      if (tid == 0) {
+        const double gn = s_gn;
+        if (k == 1) s_g1 = gn;
+        const double g1 = k == 1 ? gn : s_g1;
+        s_eps = g1 > 0.0 ? gn / g1 : 0.0;
       }
       __syncthreads();
       ++k;
@@ -415,10 +604,10 @@ __global__ void __launch_bounds__(kRunThreads)
     // previous-step terms: sampled rows at the accepted xhat, velocity of
     // the last HyperPair evaluation
     for (int q = tid; q < nd; q += kRunThreads) {
-      const int i = q < d.ns ? q : q - d.ns;
+      const int i = q < ns ? q : q - ns;
       double tx, ty;
-      sampled_position(d, i, xh, tx, ty);
-      xbar_prev[q] = q < d.ns ? tx : ty;
+      sampled_position(Phibar, xbar0, M, ns, i, xh, tx, ty);
+      xbar_prev[q] = q < ns ? tx : ty;
       fbar_prev[q] = fbar[q];
     }
     __syncthreads();
@@ -426,8 +615,17 @@ __global__ void __launch_bounds__(kRunThreads)
   if (tid < M) xhat[tid] = xh[tid];
 }
 
-size_t run_lds_bytes(int Mr, int nd, int ldc) {
-  return sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 3 * (size_t)nd);
+// dynamic LDS of the run kernel: G' and the tableaux always; the copies of
+// the arrays when lds_arrays; the per-entry terms only in the entry-parallel
+// gather
+size_t solve_lds_bytes(int M, int Mr) {
+  return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)kMaxM * 64);
+}
+
+size_t run_lds_bytes(int M, int Mr, int nd, int ns, int ldc, int64_t nnz, bool entry_par) {
+  return solve_lds_bytes(M, Mr) +
+         sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 4 * (size_t)nd + 3 * (size_t)ns) +
+         sizeof(float) * ((size_t)nd * (M + 1) + (entry_par ? 5 * (size_t)nnz : 0));
 }
 
 }  // namespace
@@ -479,8 +677,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       E[1] = float(s.xbar0[s.ns + i] - s.xqt0[2 * c + 1]);
       E[2] = float(s.Gt[c]);
       for (int m = 0; m < M; ++m) {
-        E[4 + m] = float(s.Phibar[(size_t)i * M + m] - s.Phit[(size_t)(2 * c) * M + m]);
-        E[4 + M + m] = float(s.Phibar[(size_t)(s.ns + i) * M + m] - s.Phit[(size_t)(2 * c + 1) * M + m]);
+        E[4 + 2 * m] = float(s.Phibar[(size_t)i * M + m] - s.Phit[(size_t)(2 * c) * M + m]);
+        E[5 + 2 * m] = float(s.Phibar[(size_t)(s.ns + i) * M + m] - s.Phit[(size_t)(2 * c + 1) * M + m]);
       }
     }
 
@@ -512,6 +710,22 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.M = M; d.Mr = s.Mr; d.ns = s.ns; d.nd = nd; d.jac_mode = s.jac_mode; d.max_iter = s.max_iter;
   d.ew = ew; d.nnz = s.nnz;
   d.ldc = (M + 1 + 3) / 4 * 4;
+  {
+    // run-kernel gather: groups of G lanes per target, chosen to minimise
+    // (rounds of 16 waves over the targets) x (entry passes of the longest list)
+    int64_t maxlen = 0;
+    for (int i = 0; i < s.ns; ++i) maxlen = std::max<int64_t>(maxlen, s.off[i + 1] - s.off[i]);
+    d.maxlen = int(std::min<int64_t>(maxlen, int64_t(1) << 30));
+    int64_t best = -1;
+    for (int G : {16, 32, 64}) {
+      const int64_t per_round = int64_t(kRunThreads / 64) * (64 / G);
+      const int64_t cost = (s.ns + per_round - 1) / per_round * std::max<int64_t>(1, (maxlen + G - 1) / G);
+      if (best < 0 || cost < best) {
+        best = cost;
+        d.glanes = G;
+      }
+    }
+  }
   d.d2 = float(s.delta) * float(s.delta);
   d.dt = float(s.dt);
   d.tol = s.tol; d.alpha = s.alpha;
@@ -588,15 +802,20 @@ extern "C" int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *x
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   const RomDev &d = rom->d;
-  const size_t lds = run_lds_bytes(d.Mr, d.nd, d.ldc);
+  // entry-parallel gather (paper Jacobian) when its per-entry terms fit in LDS
+  // next to the other copies; otherwise the grouped gather
+  int entry_par = d.jac_mode == PTROM_JAC_PAPER &&
+                  run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, true) <= rom->max_dyn_lds;
+  const size_t lds = run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, entry_par != 0);
   const int use_lds = lds <= rom->max_dyn_lds;
-  const size_t shmem = use_lds ? lds : 0;
+  if (!use_lds) entry_par = 0;
+  const size_t shmem = use_lds ? lds : solve_lds_bytes(d.M, d.Mr);
   if (d.jac_mode == PTROM_JAC_EXACT)
-    hipLaunchKernelGGL(rom_run_kernel<true>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, xhat,
+    hipLaunchKernelGGL(rom_run_kernel<true>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, 0, xhat,
                        xhat_hist, iters);
   else
-    hipLaunchKernelGGL(rom_run_kernel<false>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, xhat,
-                       xhat_hist, iters);
+    hipLaunchKernelGGL(rom_run_kernel<false>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, entry_par,
+                       xhat, xhat_hist, iters);
   PTROM_CHECK_HIP(ctx, hipGetLastError());
   return PTROM_OK;
 }
