@@ -14,7 +14,10 @@ loops and recursion, written for checking by eye against the paper:
 * Stage 3  Tier-II LSPG with clustered sources over every body, residual
            snapshots and their POD basis Phi_r (``tier2_residual_basis``);
 * Stage 4  greedy sample selection (Algorithm "greedy sampling",
-           ``greedy_sample``) and the gappy operator A = [P Phi_r]^+.
+           ``greedy_sample``) and the gappy operator A = [P Phi_r]^+;
+* parametric: surrogate membership, the online reassignment of clustered
+           circulations for a new parameter (``reassign_circulation``) and
+           training over several parameters (``train_parametric``).
 
 Readings of passages the paper leaves open (each also listed in the design
 notes):
@@ -32,6 +35,9 @@ notes):
     1e-9 (1 + |x_i|)); an unpruned leaf is expanded into its bodies, the
     target itself excluded;
   - a POD mode's sign makes its largest-magnitude entry positive;
+  - parametric training: one POD of all training snapshots; clustering
+    weights = mean |Gamma| over the training points; only Gamma~ is
+    reassigned per parameter (surrogate positions and rows stay fixed);
   - the greedy loop processes the residual basis in n_it groups and, after
     the first group, uses the gappy-POD reconstruction error of each group
     from the already-processed vectors on the current sample; ties go to the
@@ -327,3 +333,53 @@ def train(cloud, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, 
     A = gappy_operator(Phi_r, sample)
     art = rom_artifacts(sample, tree, pc, xy0, Phi, g, d, dt, A=A)
     return art, dict(S=S, Phi=Phi, sigma=sigma, tree=tree, Phi_r=Phi_r, sigma_r=sr, tier2=t2)
+
+
+# ----------------------------------------------------------------- parametric
+
+def surrogate_members(tree, keys):
+    """The bodies each unique surrogate stands for: the body itself, or every
+    body of the cell (the tree keeps the bodies of each cluster)."""
+    by_key = {nd.key: nd for nd in tree.nodes}
+    return [[k[1]] if k[0] == 0 else list(by_key[k].members) for k in keys]
+
+
+def reassign_circulation(members, gamma_mu):
+    """Gamma~ of every surrogate at parameter mu: the sum of its members'
+    circulations (online computations: clustered circulations are reloaded
+    for a new parameter without retraining)."""
+    g = np.asarray(gamma_mu, dtype=np.float64)
+    return np.array([float(np.sum(g[np.asarray(m, dtype=np.int64)])) for m in members])
+
+
+def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, jac_mode=0):
+    """Stages 1-4 over several training parameters.  ``clouds`` share x^0 and
+    delta and differ in Gamma (the parameter).  Snapshots of every training
+    point form one snapshot matrix (Stage 1 over the sampled parametric
+    points); the clustering weights are the mean |Gamma| over the training
+    points; Tier II runs at every training point with its reassigned Gamma~
+    and its residual snapshots are pooled (Stage 3)."""
+    x0 = np.asarray(clouds[0].xy, dtype=np.float64)
+    d = float(clouds[0].delta)
+    n = x0.size // 2
+    S = np.hstack([trapezoid_snapshots(x0, np.asarray(c.gamma, float), d, dt, nsnap) for c in clouds])
+    Phi, sigma = pod(S, M)
+    tree = QuadTree(weighted_points(Phi, sigma), depth)
+    wgt = np.mean([np.abs(np.asarray(c.gamma, float)) for c in clouds], axis=0)
+    full = rom_artifacts(np.arange(n), tree, pc, x0, Phi, wgt, d, dt)
+    mem_full = surrogate_members(tree, full["keys"])
+    R, t2 = [], []
+    for c in clouds:
+        a = dict(full)
+        a["Gt"] = reassign_circulation(mem_full, c.gamma)
+        out = oracle.Rom(a, jac_mode=jac_mode).run(nsnap, tol=tol, max_iter=max_iter, resid_cap=nsnap * max_iter)
+        R.append(out["resid"])
+        t2.append(out)
+    U, sr, _ = np.linalg.svd(np.vstack(R).T, full_matrices=False)
+    Phi_r = U[:, :Mr].copy()
+    sample = greedy_sample(Phi_r, ns)
+    A = gappy_operator(Phi_r, sample)
+    art = rom_artifacts(sample, tree, pc, x0, Phi, wgt, d, dt, A=A)
+    art["members"] = surrogate_members(tree, art["keys"])
+    return art, dict(S=S, Phi=Phi, sigma=sigma, tree=tree, Phi_r=Phi_r, sigma_r=sr[:Mr].copy(), tier2=t2,
+                     weights=wgt)

@@ -99,6 +99,32 @@ def single_vortex(n, gamma_center=None):
     return Cloud(_soa(s, s.copy()), g, 0.0, dict(kind="single_vortex", dt=dt, tf=tf))
 
 
+def vortex_pair(mu, n=500, half=52.93, delta=0.2121):
+    """Vortex-pair parametric study: n bodies on the diagonal from (-half,
+    -half) to (half, half), Gamma = 0.01 except the end bodies, which carry
+    mu = (Gamma_1, Gamma_N); core delta (the initial spacing per coordinate)."""
+    s = np.linspace(-half, half, n)
+    g = np.full(n, 0.01)
+    g[0], g[-1] = float(mu[0]), float(mu[1])
+    return Cloud(_soa(s, s.copy()), g, float(delta), dict(kind="vortex_pair", mu=tuple(float(m) for m in mu)))
+
+
+def latin_hypercube(k, lo, hi, seed):
+    """k points of a Latin hypercube in the box [lo, hi]^2 (one per row and
+    column stratum, uniform inside its cell)."""
+    rng = np.random.default_rng(seed)
+    pts = np.empty((k, 2))
+    for dim in range(2):
+        pts[:, dim] = (rng.permutation(k) + rng.uniform(size=k)) / k
+    return lo + (hi - lo) * pts
+
+
+def parameter_grid(m, lo, hi):
+    """m x m grid of parameter points spanning [lo, hi]^2 (row-major)."""
+    g = np.linspace(lo, hi, m)
+    return np.array([(a, b) for a in g for b in g])
+
+
 def unit_vectors(n, k, seed):
     """k random unit vectors of length 2n (Gaussian, normalized)."""
     rng = np.random.default_rng(seed)

@@ -247,3 +247,45 @@ def test_pod_sign_convention():
     # the same basis for a column-permuted snapshot set
     Phi2, _ = off.pod(S[:, rng.permutation(15)], 5)
     np.testing.assert_allclose(Phi2, Phi, atol=1e-12)
+
+
+def test_reassigned_circulation_pins(small_problem):
+    cl, _, Phi, sig, tree = small_problem
+    n = cl.n
+    sample = np.array([0, 7, 100, 150, 191])
+    art = off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3)
+    mem = off.surrogate_members(tree, art["keys"])
+    # at the training parameter the reassignment is the training Gamma~
+    np.testing.assert_array_equal(off.reassign_circulation(mem, cl.gamma), art["Gt"])
+    rng = np.random.default_rng(3)
+    ga, gb = rng.standard_normal(n), rng.standard_normal(n)
+    ra, rb = off.reassign_circulation(mem, ga), off.reassign_circulation(mem, gb)
+    # linear in Gamma
+    np.testing.assert_allclose(off.reassign_circulation(mem, 2.0 * ga - gb), 2.0 * ra - rb, rtol=0, atol=1e-12)
+    # every target's list carries the total circulation of all other bodies
+    for t, i in enumerate(sample):
+        ids = art["ids"][art["off"][t]:art["off"][t + 1]]
+        assert ra[ids].sum() == pytest.approx(ga.sum() - ga[i], abs=1e-11)
+
+
+def test_parametric_training_small():
+    # two training parameters of a small vortex pair; the online ROM with the
+    # reassigned circulation follows the FOM at a training point and stays
+    # finite at an untrained one
+    mus = [(40.0, 55.0), (60.0, 30.0)]
+    clouds = [W.vortex_pair(m, n=48, half=5.0, delta=0.21) for m in mus]
+    dt, steps = 0.01, 40
+    art, ex = off.train_parametric(clouds, dt, steps, M=16, Mr=32, ns=24, depth=6, pc=1.0, tol=1e-6)
+    assert ex["S"].shape[1] == 2 * steps
+    n = clouds[0].n
+    x0 = clouds[0].xy
+    for mu, trained in [(mus[0], True), ((50.0, 45.0), False)]:
+        a = dict(art)
+        a["Gt"] = off.reassign_circulation(art["members"], W.vortex_pair(mu, n=48, half=5.0).gamma)
+        out = oracle.Rom(a).run(steps, tol=1e-6, max_iter=100)
+        assert out["status"] == 0 and np.all(np.isfinite(out["hist"]))
+        if trained:
+            rec = x0[:, None] + ex["Phi"] @ out["hist"].T
+            S = ex["S"][:, :steps]
+            err = np.linalg.norm(rec - S) / np.linalg.norm(S - x0[:, None])
+            assert err < 0.05, err
