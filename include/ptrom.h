@@ -253,6 +253,30 @@ int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const double *xbar_p
 int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, int32_t *iters,
                   ptrom_stream stream);
 
+/* Parametric queries (online computations: the tree keeps the bodies of each
+ * cluster, so the clustered circulations are reloaded for a new parameter
+ * without retraining).
+ *
+ * ptrom_rom_members: the bodies of each surrogate, HOST CSR arrays mem_off
+ * [Nc+1] (mem_off[0] = 0, every surrogate non-empty) and mem_ids (body ids in
+ * [0, n)), as from ptrom_cluster_members; copied to the device.  SYNCHRONISES
+ * when it replaces an earlier membership.
+ *
+ * ptrom_rom_reassign: Gamma~_q[c] = sum over the members j of c of
+ * gamma_q[q][j], for nq queries; gamma_q device FP32 [nq][n], gt_q device FP32
+ * [nq][Nc] (sums accumulated in FP64).  Asynchronous.
+ *
+ * ptrom_rom_run_batched: nq independent online runs in one launch, one
+ * workgroup per query, query q using the circulations gt_q[q] (device FP32
+ * [nq][Nc]) and its own xhat[q] (device FP64 [nq][M], in place), xhat_hist
+ * [nq][nsteps][M] and iters [nq][nsteps] (both may be NULL).  Surrogate
+ * positions and rows are those of the artifacts.  EINVAL when the run arrays
+ * of one query do not fit in a workgroup's LDS.  Asynchronous. */
+int ptrom_rom_members(ptrom_rom *rom, int64_t n, const int64_t *mem_off, const int64_t *mem_ids);
+int ptrom_rom_reassign(ptrom_rom *rom, int nq, const float *gamma_q, float *gt_q, ptrom_stream stream);
+int ptrom_rom_run_batched(ptrom_rom *rom, int nq, const float *gt_q, int nsteps, double *xhat,
+                          double *xhat_hist, int32_t *iters, ptrom_stream stream);
+
 /* ------------------------------------------------------------------------
  * Offline training helpers (training hierarchy, Stages 2-3).
  * ---------------------------------------------------------------------- */
@@ -289,6 +313,14 @@ int ptrom_cluster_sizes(const ptrom_clusters *c, int64_t *nc, int64_t *nnz);
 int ptrom_cluster_fetch(const ptrom_clusters *c, double *xqt0, double *phit, double *gt, int64_t *off,
                         int64_t *ids, int64_t *keys);
 void ptrom_cluster_destroy(ptrom_clusters *c);
+
+/* The bodies each unique surrogate stands for, in surrogate order (the body
+ * itself, or every body of the cell in increasing id order): CSR arrays in
+ * caller HOST memory, mem_off [Nc+1] and mem_ids [*nmem].  *nmem is always
+ * written; either array may be NULL (call once with NULLs to size them).
+ * Online computations reassign clustered circulations for a new parameter
+ * from this membership. */
+int ptrom_cluster_members(const ptrom_clusters *c, int64_t *nmem, int64_t *mem_off, int64_t *mem_ids);
 
 /* FP64 Gram matrix G = X X^T of k device rows X [k][nd] (row-major);
  * G [k][k] device.  Used for the POD by the method of snapshots. */

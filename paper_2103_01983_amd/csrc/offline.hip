@@ -155,6 +155,7 @@ struct ptrom_clusters {
   int M = 0;
   std::vector<double> xqt0, phit, gt;
   std::vector<int64_t> off, ids, keys;
+  std::vector<int64_t> mem_off, mem_ids;  // bodies of each unique surrogate (CSR)
 };
 
 extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *xy0, const double *phi,
@@ -216,6 +217,7 @@ extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *
   r->nc = int64_t(keys.size());
   r->keys = keys;
   r->xqt0.assign(2 * r->nc, 0.0);
+  r->mem_off.assign(1, 0);
   r->phit.assign(2 * r->nc * M, 0.0);
   r->gt.assign(r->nc, 0.0);
   // node lookup by key
@@ -227,6 +229,8 @@ extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *
     const int64_t key = keys[c];
     if (key < kNodeTag) {
       const int64_t j = key;
+      r->mem_ids.push_back(j);
+      r->mem_off.push_back(int64_t(r->mem_ids.size()));
       r->xqt0[2 * c] = xy0[j];
       r->xqt0[2 * c + 1] = xy0[n + j];
       r->gt[c] = gamma[j];
@@ -238,6 +242,10 @@ extern "C" int ptrom_cluster_build(int64_t n, const double *wpts, const double *
     }
     auto it = std::lower_bound(nk.begin(), nk.end(), std::make_pair(key, -1));
     const QNode &q = T.nodes[it->second];
+    const size_t m0 = r->mem_ids.size();
+    for (int t = q.first; t < q.first + q.count; ++t) r->mem_ids.push_back(T.perm[t]);
+    std::sort(r->mem_ids.begin() + m0, r->mem_ids.end());  // the subtree's ranges are grouped by quadrant
+    r->mem_off.push_back(int64_t(r->mem_ids.size()));
     double wsum = 0.0, gsum = 0.0;
     for (int t = q.first; t < q.first + q.count; ++t) {
       wsum += std::fabs(gamma[T.perm[t]]);
@@ -371,5 +379,13 @@ extern "C" int ptrom_combine_f64(ptrom_ctx *ctx, int64_t nd, int k, const double
   hipLaunchKernelGGL(combine_f64_kernel, dim3((unsigned)((nd + 255) / 256), M), dim3(256), 0,
                      (hipStream_t)stream, nd, k, X, M, T, Y);
   PTROM_CHECK_HIP(ctx, hipGetLastError());
+  return PTROM_OK;
+}
+
+extern "C" int ptrom_cluster_members(const ptrom_clusters *c, int64_t *nmem, int64_t *mem_off, int64_t *mem_ids) {
+  if (!c || !nmem) return PTROM_EINVAL;
+  *nmem = int64_t(c->mem_ids.size());
+  if (mem_off) std::memcpy(mem_off, c->mem_off.data(), c->mem_off.size() * sizeof(int64_t));
+  if (mem_ids) std::memcpy(mem_ids, c->mem_ids.data(), c->mem_ids.size() * sizeof(int64_t));
   return PTROM_OK;
 }

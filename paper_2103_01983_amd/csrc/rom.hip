@@ -29,6 +29,7 @@
 // wave per target (large sample sets).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "internal.h"
@@ -44,12 +45,12 @@ constexpr int kRunThreads = 512;  // 8 waves: up to 256 VGPRs per lane
 constexpr double kInv2PiD = 0.15915494309189533576888376337251;
 
 struct RomDev {
-  int M, Mr, ns, nd, jac_mode, max_iter, ew, ldc, glanes, maxlen;
+  int M, Mr, ns, nd, jac_mode, max_iter, ew, ldc, glanes, maxlen, Nc;
   int64_t nnz;
   float d2, dt;
   double tol, alpha;
   const float *Phibar, *xbar0;  // [nd][M], [nd]
-  const float *ent;             // [nnz][ew]: r0x r0y Gamma pad (Dx_m Dy_m) pairs
+  const float *ent;             // [nnz][ew]: r0x r0y Gamma~ surrogate-id (Dx_m Dy_m) pairs
   const int *off;               // [ns+1]
   const double *A;              // [Mr][nd]
   // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
@@ -147,8 +148,8 @@ struct GatherAcc {
 // Velocity and Jacobian terms of one (target, surrogate) entry at xhat:
 // r = r0 + D xhat; the 2x2 block (or, exact mode, its product with D).
 template <bool EXACT, int EW>
-__device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *row, const float *xf, int M,
-                                            float d2, GatherAcc<EXACT> &a) {
+__device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *row, const float *xf, const float *gt,
+                                            int M, float d2, GatherAcc<EXACT> &a) {
   float rx = v[0], ry = v[1];
 #pragma unroll
   for (int m = 0; m < (EW - 4) / 2; ++m)
@@ -159,7 +160,9 @@ __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *r
   const float q = fmaf(rx, rx, fmaf(ry, ry, d2));
   // a surrogate exactly on its target (possible at delta = 0) adds nothing
   const float r = q > 0.f ? 1.0f / q : 0.f;
-  const float g = v[2] * r;
+  // Gamma~ of the training parameter, or of the query (table indexed by the
+  // surrogate id kept in the row)
+  const float g = (gt ? gt[__builtin_bit_cast(int, v[3])] : v[2]) * r;
   a.fx = fmaf(-ry, g, a.fx);
   a.fy = fmaf(rx, g, a.fy);
   const float g2 = g * r;
@@ -200,8 +203,8 @@ __device__ __forceinline__ float gsum(float v, int G) {
 // copies.  Any output pointer may be null.  Row q of rbar is rbar_out[q * rs],
 // row q of C is C_out[q * ldc .. + M).
 template <bool EXACT>
-__device__ void gather_group(const RomDev &d, const float *Phibar, const float *xbar0, int t, bool valid, int gl,
-                             int G, const double *xh, const float *xf, const double *xbar_prev,
+__device__ void gather_group(const RomDev &d, const float *Phibar, const float *xbar0, const float *gt, int t,
+                             bool valid, int gl, int G, const double *xh, const float *xf, const double *xbar_prev,
                              const double *fbar_prev, double *xbar_out, double *fbar_out, double *rbar_out, int rs,
                              double *C_out, int ldc) {
   const int M = d.M, ns = d.ns;
@@ -217,15 +220,15 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
           float v0[kShortEw], v1[kShortEw];
           load_entry(d.ent, d.ew, e, v0);
           load_entry(d.ent, d.ew, e + G, v1);
-          entry_terms<false>(v0, nullptr, xf, M, d.d2, a);
-          entry_terms<false>(v1, nullptr, xf, M, d.d2, a);
+          entry_terms<false>(v0, nullptr, xf, gt, M, d.d2, a);
+          entry_terms<false>(v1, nullptr, xf, gt, M, d.d2, a);
         }
       }
     }
     for (; e < e1; e += G) {
       float v[kMaxEw];
       load_entry(d.ent, d.ew, e, v);
-      entry_terms<EXACT>(v, d.ent + (size_t)e * d.ew, xf, M, d.d2, a);
+      entry_terms<EXACT>(v, d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
     }
   }
   const double Fx = gsum(a.fx, G) * kInv2PiD, Fy = gsum(a.fy, G) * kInv2PiD;
@@ -290,8 +293,8 @@ __global__ void __launch_bounds__(256)
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= d.ns) return;
-  gather_group<EXACT>(d, d.Phibar, d.xbar0, wave, true, lane, 64, xh, xf, xbar_prev, fbar_prev, xbar, fbar, rbar, 1,
-                      C, d.M);
+  gather_group<EXACT>(d, d.Phibar, d.xbar0, nullptr, wave, true, lane, 64, xh, xf, xbar_prev, fbar_prev, xbar, fbar,
+                      rbar, 1, C, d.M);
 }
 
 // ----------------------------------------------------------- device-resident loop
@@ -328,8 +331,8 @@ __device__ __forceinline__ double sum8(double v) {
 
 template <bool EXACT>
 __global__ void __launch_bounds__(kRunThreads)
-    rom_run_kernel(RomDev d, int nsteps, int lds_arrays, int entry_par, double *__restrict__ xhat,
-                   double *__restrict__ hist, int *__restrict__ iters) {
+    rom_run_kernel(RomDev d, int nsteps, int lds_arrays, int entry_par, const float *__restrict__ gtq,
+                   double *__restrict__ xhat, double *__restrict__ hist, int *__restrict__ iters) {
   __shared__ double xh[kMaxM];
   __shared__ float xf[kMaxM];
   __shared__ double rr[kMaxMr], gq[kMaxM], xs[kMaxM], gvec[kMaxM];
@@ -351,6 +354,10 @@ __global__ void __launch_bounds__(kRunThreads)
   double *Cp = d.C, *fbar = d.fbar, *fbar_prev = d.fbar_prev, *xbar_prev = d.xbar_prev, *bt = nullptr,
          *xcur = nullptr;
   float *ct = nullptr;
+  const float *gt = nullptr;
+  xhat += (size_t)blockIdx.x * M;
+  if (hist) hist += (size_t)blockIdx.x * nsteps * M;
+  if (iters) iters += (size_t)blockIdx.x * nsteps;
   if (lds_arrays) {
     double *p = T0 + (size_t)kMaxM * 64;
     double *Al = p; p += (size_t)Mr * nd;
@@ -363,7 +370,13 @@ __global__ void __launch_bounds__(kRunThreads)
     float *f = reinterpret_cast<float *>(p);
     float *Pl = f; f += (size_t)nd * M;
     float *xl = f; f += nd;
-    ct = f;
+    ct = f; f += entry_par ? 5 * (size_t)d.nnz : 0;
+    if (gtq) {
+      // this query's clustered circulations (one workgroup per query)
+      float *gl_ = f;
+      for (int t = tid; t < d.Nc; t += kRunThreads) gl_[t] = gtq[(size_t)blockIdx.x * d.Nc + t];
+      gt = gl_;
+    }
     for (int t = tid; t < Mr * nd; t += kRunThreads) Al[t] = d.A[t];
     for (int t = tid; t < nd * M; t += kRunThreads) Pl[t] = d.Phibar[t];
     for (int t = tid; t < nd; t += kRunThreads) xl[t] = d.xbar0[t];
@@ -381,7 +394,7 @@ __global__ void __launch_bounds__(kRunThreads)
   const int G = d.glanes, tpw = 64 / G, gl = lane & (G - 1), slot = lane / G;
   // previous-step terms for the first step: HyperPair at the initial xhat
   for (int base = wave * tpw; base < ns; base += nwaves * tpw)
-    gather_group<EXACT>(d, Phibar, xbar0, base + slot, base + slot < ns, gl, G, xh, xf, nullptr, nullptr,
+    gather_group<EXACT>(d, Phibar, xbar0, gt, base + slot, base + slot < ns, gl, G, xh, xf, nullptr, nullptr,
                         xbar_prev, fbar_prev, nullptr, 0, nullptr, 0);
   __syncthreads();
 
@@ -398,7 +411,7 @@ __global__ void __launch_bounds__(kRunThreads)
           float v[kMaxEw];
           load_entry(d.ent, d.ew, e, v);
           GatherAcc<false> a;
-          entry_terms<false>(v, nullptr, xf, M, d.d2, a);
+          entry_terms<false>(v, nullptr, xf, gt, M, d.d2, a);
           ct[e] = a.fx;
           ct[nnz + e] = a.fy;
           ct[2 * nnz + e] = a.ba;
@@ -471,7 +484,7 @@ __global__ void __launch_bounds__(kRunThreads)
         }
       } else {
         for (int base = wave * tpw; base < ns; base += nwaves * tpw)
-          gather_group<EXACT>(d, Phibar, xbar0, base + slot, base + slot < ns, gl, G, xh, xf, xbar_prev,
+          gather_group<EXACT>(d, Phibar, xbar0, gt, base + slot, base + slot < ns, gl, G, xh, xf, xbar_prev,
                               fbar_prev, nullptr, fbar, Cp + M, ldc, Cp, ldc);
       }
       __syncthreads();
@@ -622,10 +635,24 @@ size_t solve_lds_bytes(int M, int Mr) {
   return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)kMaxM * 64);
 }
 
-size_t run_lds_bytes(int M, int Mr, int nd, int ns, int ldc, int64_t nnz, bool entry_par) {
+size_t run_lds_bytes(int M, int Mr, int nd, int ns, int ldc, int64_t nnz, bool entry_par, int64_t nc_table) {
   return solve_lds_bytes(M, Mr) +
          sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 4 * (size_t)nd + 3 * (size_t)ns) +
-         sizeof(float) * ((size_t)nd * (M + 1) + (entry_par ? 5 * (size_t)nnz : 0));
+         sizeof(float) * ((size_t)nd * (M + 1) + (entry_par ? 5 * (size_t)nnz : 0) + (size_t)nc_table);
+}
+
+// Gamma~ of every surrogate for every query: the sum of its members' Gamma
+// (FP64 accumulation, members in increasing id order).
+__global__ void reassign_kernel(int nq, int64_t n, int Nc, const int *__restrict__ mem_off,
+                                const int *__restrict__ mem_ids, const float *__restrict__ gamma_q,
+                                float *__restrict__ gt_q) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nq * Nc) return;
+  const int q = int(t / Nc), c = int(t - (int64_t)q * Nc);
+  const float *g = gamma_q + (size_t)q * n;
+  double s = 0.0;
+  for (int k = mem_off[c]; k < mem_off[c + 1]; ++k) s += (double)g[mem_ids[k]];
+  gt_q[t] = (float)s;
 }
 
 }  // namespace
@@ -634,6 +661,8 @@ struct ptrom_rom {
   ptrom_ctx *ctx = nullptr;
   RomDev d{};
   void *buf = nullptr;
+  int *members = nullptr;  // device: mem_off [Nc+1] then mem_ids
+  int64_t n_bodies = 0;
   size_t max_dyn_lds = 0;  // dynamic LDS the run kernel may take on this device
 };
 
@@ -676,6 +705,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       E[0] = float(s.xbar0[i] - s.xqt0[2 * c]);
       E[1] = float(s.xbar0[s.ns + i] - s.xqt0[2 * c + 1]);
       E[2] = float(s.Gt[c]);
+      const int32_t cid = int32_t(c);
+      std::memcpy(&E[3], &cid, sizeof(cid));
       for (int m = 0; m < M; ++m) {
         E[4 + 2 * m] = float(s.Phibar[(size_t)i * M + m] - s.Phit[(size_t)(2 * c) * M + m]);
         E[5 + 2 * m] = float(s.Phibar[(size_t)(s.ns + i) * M + m] - s.Phit[(size_t)(2 * c + 1) * M + m]);
@@ -708,7 +739,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   }
   RomDev &d = rom->d;
   d.M = M; d.Mr = s.Mr; d.ns = s.ns; d.nd = nd; d.jac_mode = s.jac_mode; d.max_iter = s.max_iter;
-  d.ew = ew; d.nnz = s.nnz;
+  d.ew = ew; d.nnz = s.nnz; d.Nc = int(s.Nc);
   d.ldc = (M + 1 + 3) / 4 * 4;
   {
     // run-kernel gather: groups of G lanes per target, chosen to minimise
@@ -769,6 +800,7 @@ extern "C" void ptrom_rom_destroy(ptrom_rom *rom) {
   hipSetDevice(rom->ctx->device);
   hipDeviceSynchronize();
   if (rom->buf) hipFree(rom->buf);
+  if (rom->members) hipFree(rom->members);
   delete rom;
 }
 
@@ -793,6 +825,40 @@ extern "C" int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const dou
   return PTROM_OK;
 }
 
+namespace {
+
+// One launch of the device-resident loop over nq queries (one workgroup
+// each); gtq NULL means the training circulations of the entries.
+int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xhat, double *xhat_hist,
+               int32_t *iters, hipStream_t st) {
+  ptrom_ctx *ctx = rom->ctx;
+  const RomDev &d = rom->d;
+  const int64_t table = gtq ? d.Nc : 0;
+  // entry-parallel gather (paper Jacobian) when its per-entry terms fit in LDS
+  // next to the other copies; otherwise the grouped gather
+  int entry_par = d.jac_mode == PTROM_JAC_PAPER &&
+                  run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, true, table) <= rom->max_dyn_lds;
+  const size_t lds = run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, entry_par != 0, table);
+  const int use_lds = lds <= rom->max_dyn_lds;
+  if (!use_lds) {
+    entry_par = 0;
+    // the global-memory fallback has one scratch set: a single query only
+    if (nq != 1 || gtq)
+      return ctx->fail(PTROM_EINVAL, "batched queries need the run arrays to fit in LDS (sample set too large)");
+  }
+  const size_t shmem = use_lds ? lds : solve_lds_bytes(d.M, d.Mr);
+  if (d.jac_mode == PTROM_JAC_EXACT)
+    hipLaunchKernelGGL(rom_run_kernel<true>, dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, 0, gtq,
+                       xhat, xhat_hist, iters);
+  else
+    hipLaunchKernelGGL(rom_run_kernel<false>, dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, entry_par,
+                       gtq, xhat, xhat_hist, iters);
+  PTROM_CHECK_HIP(ctx, hipGetLastError());
+  return PTROM_OK;
+}
+
+}  // namespace
+
 extern "C" int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist,
                              int32_t *iters, ptrom_stream stream) {
   if (!rom) return PTROM_EINVAL;
@@ -800,22 +866,63 @@ extern "C" int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *x
   ctx->err.clear();
   if (!xhat || nsteps < 0) return ctx->fail(PTROM_EINVAL, "xhat required and nsteps >= 0");
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
-  hipStream_t st = (hipStream_t)stream;
-  const RomDev &d = rom->d;
-  // entry-parallel gather (paper Jacobian) when its per-entry terms fit in LDS
-  // next to the other copies; otherwise the grouped gather
-  int entry_par = d.jac_mode == PTROM_JAC_PAPER &&
-                  run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, true) <= rom->max_dyn_lds;
-  const size_t lds = run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, entry_par != 0);
-  const int use_lds = lds <= rom->max_dyn_lds;
-  if (!use_lds) entry_par = 0;
-  const size_t shmem = use_lds ? lds : solve_lds_bytes(d.M, d.Mr);
-  if (d.jac_mode == PTROM_JAC_EXACT)
-    hipLaunchKernelGGL(rom_run_kernel<true>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, 0, xhat,
-                       xhat_hist, iters);
-  else
-    hipLaunchKernelGGL(rom_run_kernel<false>, dim3(1), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, entry_par,
-                       xhat, xhat_hist, iters);
+  return launch_run(rom, 1, nullptr, nsteps, xhat, xhat_hist, iters, (hipStream_t)stream);
+}
+
+extern "C" int ptrom_rom_members(ptrom_rom *rom, int64_t n, const int64_t *mem_off, const int64_t *mem_ids) {
+  if (!rom) return PTROM_EINVAL;
+  ptrom_ctx *ctx = rom->ctx;
+  ctx->err.clear();
+  const int Nc = rom->d.Nc;
+  if (n < 1 || n > kMaxN || !mem_off || (Nc > 0 && !mem_ids)) return ctx->fail(PTROM_EINVAL, "bad membership");
+  if (mem_off[0] != 0) return ctx->fail(PTROM_EINVAL, "mem_off must start at 0");
+  for (int c = 0; c < Nc; ++c)
+    if (mem_off[c + 1] <= mem_off[c]) return ctx->fail(PTROM_EINVAL, "every surrogate needs at least one member");
+  const int64_t nmem = mem_off[Nc];
+  if (nmem > (int64_t(1) << 31) - 1) return ctx->fail(PTROM_EINVAL, "too many members");
+  std::vector<int> host(size_t(Nc) + 1 + size_t(nmem));
+  for (int c = 0; c <= Nc; ++c) host[c] = int(mem_off[c]);
+  for (int64_t k = 0; k < nmem; ++k) {
+    if (mem_ids[k] < 0 || mem_ids[k] >= n) return ctx->fail(PTROM_EINVAL, "member id out of [0, n)");
+    host[size_t(Nc) + 1 + size_t(k)] = int(mem_ids[k]);
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
+  if (rom->members) {
+    PTROM_CHECK_HIP(ctx, hipDeviceSynchronize());
+    PTROM_CHECK_HIP(ctx, hipFree(rom->members));
+    rom->members = nullptr;
+  }
+  if (hipMalloc(&rom->members, host.size() * sizeof(int)) != hipSuccess)
+    return ctx->fail(PTROM_ENOMEM, "membership allocation");
+  PTROM_CHECK_HIP(ctx, hipMemcpy(rom->members, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
+  rom->n_bodies = n;
+  return PTROM_OK;
+}
+
+extern "C" int ptrom_rom_reassign(ptrom_rom *rom, int nq, const float *gamma_q, float *gt_q, ptrom_stream stream) {
+  if (!rom) return PTROM_EINVAL;
+  ptrom_ctx *ctx = rom->ctx;
+  ctx->err.clear();
+  if (!rom->members) return ctx->fail(PTROM_EINVAL, "membership not set (ptrom_rom_members)");
+  if (nq < 1 || !gamma_q || !gt_q) return ctx->fail(PTROM_EINVAL, "nq >= 1 and both arrays required");
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
+  const int Nc = rom->d.Nc;
+  const int64_t total = int64_t(nq) * Nc;
+  if (total == 0) return PTROM_OK;
+  const int *mem_off = rom->members, *mem_ids = rom->members + Nc + 1;
+  hipLaunchKernelGGL(reassign_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream, nq,
+                     rom->n_bodies, Nc, mem_off, mem_ids, gamma_q, gt_q);
   PTROM_CHECK_HIP(ctx, hipGetLastError());
   return PTROM_OK;
+}
+
+extern "C" int ptrom_rom_run_batched(ptrom_rom *rom, int nq, const float *gt_q, int nsteps, double *xhat,
+                                     double *xhat_hist, int32_t *iters, ptrom_stream stream) {
+  if (!rom) return PTROM_EINVAL;
+  ptrom_ctx *ctx = rom->ctx;
+  ctx->err.clear();
+  if (nq < 1 || nq > 65535 || !gt_q || !xhat || nsteps < 0)
+    return ctx->fail(PTROM_EINVAL, "1 <= nq <= 65535, gt_q and xhat required, nsteps >= 0");
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
+  return launch_run(rom, nq, gt_q, nsteps, xhat, xhat_hist, iters, (hipStream_t)stream);
 }

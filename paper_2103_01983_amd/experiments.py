@@ -11,6 +11,13 @@ and reports SF = T_I / T_III, the time-averaged MAE_D and AE_H (paper's
 Hamiltonian, delta = 0) of the PTROM against the FOM.
 
     python -m paper_2103_01983_amd.experiments [--n 500] [--case 1]
+    python -m paper_2103_01983_amd.experiments --study vortex_pair
+
+The vortex-pair parametric study (results section, vortex pair parametric
+experiment): mu = (Gamma_1, Gamma_N) in [0.25, 1]^2 Gamma_max, four
+Latin-hypercube training points, a 6 x 6 grid of online queries run in one
+launch (one workgroup per query) after reassigning the clustered
+circulations of every query on the device.
 """
 from __future__ import annotations
 
@@ -24,6 +31,7 @@ import torch
 
 from . import native
 from . import offline
+from . import workloads as W
 from .workloads import single_vortex
 
 # narrow-width Bases Cases: case -> (tol, {N: (M, p_c)}); M_r = 2M, n_s = M_r
@@ -109,11 +117,92 @@ def run(n, case=1, depth=16, device=None):
                 report=info["report"])
 
 
+def vortex_pair_study(n=500, M=32, Mr=64, ns=32, pc=1.0, tol=1e-4, depth=16, gamma_max=255.0, t_f=5.0, dt=0.01,
+                      ntrain=4, grid=6, seed=2103, newton_tol=2e-5, device=None):
+    """Parametric vortex pair: offline training at ntrain Latin-hypercube
+    points, then grid x grid queries in one batched launch; accuracy of every
+    query against its trapezoid FOM.  The FP32 FOM's Newton tolerance sits
+    just above the rounding floor of states of magnitude ~50."""
+    dev = torch.device("cuda", 0) if device is None else device
+    steps = int(round(t_f / dt))
+    lo, hi = 0.25 * gamma_max, gamma_max
+    mus_train = W.latin_hypercube(ntrain, lo, hi, seed)
+    mus_q = W.parameter_grid(grid, lo, hi)
+    clouds = [W.vortex_pair(m, n=n) for m in mus_train]
+    t0 = time.perf_counter()
+    art, info = offline.train_parametric(clouds, dt=dt, nsnap=steps, M=M, Mr=Mr, ns=ns, depth=depth, pc=pc, tol=tol,
+                                         max_iter=100, device=dev, newton_tol=newton_tol)
+    t_off = time.perf_counter() - t0
+    rom = native.Rom(art, tol=tol, max_iter=100)
+    nq = len(mus_q)
+    G = torch.tensor(np.stack([np.asarray(W.vortex_pair(m, n=n).gamma, np.float32) for m in mus_q]), device=dev)
+    gt = rom.reassign(G)
+    xq = torch.zeros((nq, M), dtype=torch.float64, device=dev)
+    hq = torch.empty((nq, steps, M), dtype=torch.float64, device=dev)
+    iq = torch.empty((nq, steps), dtype=torch.int32, device=dev)
+    rom.run_batched(gt[:1], 2, xq[:1].clone())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gt = rom.reassign(G)
+    rom.run_batched(gt, steps, xq, hq, iq)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    x1 = torch.zeros((1, M), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rom.run_batched(gt[:1], steps, x1)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+
+    # trapezoid FOM of every query (timed per query) and the QoIs
+    Phi = info["Phi"]
+    xy0 = np.asarray(clouds[0].xy, np.float32).astype(np.float64)
+    length = float(np.hypot(xy0[n - 1] - xy0[0], xy0[2 * n - 1] - xy0[n]))
+    delta = float(clouds[0].delta)
+    maes, aes, t_fom = [], [], []
+    for q, m in enumerate(mus_q):
+        cl = W.vortex_pair(m, n=n)
+        g = torch.tensor(np.asarray(cl.gamma, np.float32), device=dev)
+        x = torch.tensor(xy0, dtype=torch.float32, device=dev)
+        traj_d = torch.empty((steps, 2 * n), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(steps):
+            native.implicit(x, g, delta, dt, 1, scheme=native.TRAPEZOID, newton_tol=newton_tol, gmres_tol=1e-4)
+            traj_d[t].copy_(x)
+        torch.cuda.synchronize()
+        t_fom.append(time.perf_counter() - t0)
+        traj = traj_d.double().cpu().numpy()
+        rec = xy0[None, :] + hq[q].cpu().numpy() @ Phi.T
+        maes.append(float(np.mean([offline.mae_distance(rec[t], traj[t], n, length) for t in range(steps)])))
+        hs = []
+        for t in range(0, steps, max(1, steps // 25)):
+            h1 = float(native.hamiltonian(torch.tensor(traj[t], dtype=torch.float32, device=dev), g, delta).item())
+            h3 = float(native.hamiltonian(torch.tensor(rec[t], dtype=torch.float32, device=dev), g, delta).item())
+            hs.append(abs((h3 - h1) / h1))
+        aes.append(float(np.mean(hs)))
+    it = iq.cpu().numpy()
+    return dict(study="vortex_pair_parametric", N=n, M=M, Mr=Mr, ns=ns, pc=pc, tol=tol, steps=steps, dt=dt,
+                gamma_max=gamma_max, train_mu=mus_train.tolist(), queries=nq, Nc=int(np.asarray(art["Gt"]).size),
+                nnz=int(np.asarray(art["ids"]).size), offline_seconds=t_off,
+                online_batched_seconds=t_batch, online_one_query_seconds=t_one,
+                batched_queries_per_one_query_time=nq * t_one / t_batch,
+                fom_seconds_per_query=float(np.mean(t_fom)), speedup_SF_per_query=float(np.mean(t_fom)) / (t_batch / nq),
+                mean_gn_iterations=float(it.mean()), max_gn_iterations=int(it.max()),
+                mae_d_time_avg_mean=float(np.mean(maes)), mae_d_time_avg_max=float(np.max(maes)),
+                ae_h_time_avg_mean=float(np.mean(aes)), ae_h_time_avg_max=float(np.max(aes)),
+                mae_d_per_query=maes, report=info["report"])
+
+
 def main(argv=None):
     p = argparse.ArgumentParser()
+    p.add_argument("--study", default="single_vortex", choices=["single_vortex", "vortex_pair"])
     p.add_argument("--n", type=int, nargs="+", default=[500])
     p.add_argument("--case", type=int, default=1)
     a = p.parse_args(argv)
+    if a.study == "vortex_pair":
+        print(json.dumps(vortex_pair_study()), flush=True)
+        return 0
     for n in a.n:
         print(json.dumps(run(n, a.case)), flush=True)
     return 0

@@ -81,6 +81,10 @@ SIGNATURES = {
     "ptrom_cluster_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "ptrom_cluster_fetch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptrom_cluster_destroy": (None, [_vp]),
+    "ptrom_cluster_members": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), _vp, _vp]),
+    "ptrom_rom_members": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
+    "ptrom_rom_reassign": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+    "ptrom_rom_run_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "ptrom_gram_f64": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp, _vp]),
     "ptrom_combine_f64": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp]),
     "ptrom_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p]),
@@ -406,6 +410,9 @@ class Rom:
         h = _vp()
         _check(c, lib().ptrom_rom_create(c, ctypes.byref(desc), ctypes.byref(h)), "ptrom_rom_create")
         self._h = h
+        self.Nc = Nc
+        if "mem_off" in art and "n" in art:
+            self.set_members(art["mem_off"], art["mem_ids"], art["n"])
 
     def close(self):
         if getattr(self, "_h", None):
@@ -440,6 +447,35 @@ class Rom:
                                               _ptr(hist, torch.float64, nsteps * self.M, "hist"),
                                               _ptr(iters, torch.int32, nsteps, "iters"), _stream(xhat)),
                "ptrom_rom_run")
+        return xhat
+
+    def set_members(self, mem_off, mem_ids, n):
+        """Bodies of each surrogate (CSR, host), for parametric queries."""
+        mem_off = np.ascontiguousarray(mem_off, dtype=np.int64)
+        mem_ids = np.ascontiguousarray(mem_ids, dtype=np.int64)
+        if mem_off.size != self.Nc + 1:
+            raise ValueError("mem_off must have Nc + 1 entries")
+        self.n = int(n)
+        _check(self._ctx, lib().ptrom_rom_members(self._h, self.n, mem_off.ctypes.data_as(_vp),
+                                                  mem_ids.ctypes.data_as(_vp) if mem_ids.size else None),
+               "ptrom_rom_members")
+
+    def reassign(self, gamma_q):
+        """Clustered circulations for parameters gamma_q (device FP32 [nq, n]): [nq, Nc]."""
+        nq = gamma_q.shape[0]
+        out = torch.empty((nq, self.Nc), dtype=torch.float32, device=gamma_q.device)
+        _check(self._ctx, lib().ptrom_rom_reassign(self._h, int(nq), _ptr(gamma_q, torch.float32, nq * self.n, "gamma_q"),
+                                                   _ptr(out, torch.float32, nq * self.Nc, "gt_q"), _stream(gamma_q)),
+               "ptrom_rom_reassign")
+        return out
+
+    def run_batched(self, gt_q, nsteps, xhat, hist=None, iters=None):
+        """nq online runs in one launch: gt_q [nq, Nc] FP32, xhat [nq, M] FP64 (in place)."""
+        nq = gt_q.shape[0]
+        _check(self._ctx, lib().ptrom_rom_run_batched(
+            self._h, int(nq), _ptr(gt_q, torch.float32, nq * self.Nc, "gt_q"), int(nsteps),
+            _ptr(xhat, torch.float64, nq * self.M, "xhat"), _ptr(hist, torch.float64, nq * nsteps * self.M, "hist"),
+            _ptr(iters, torch.int32, nq * nsteps, "iters"), _stream(gt_q)), "ptrom_rom_run_batched")
         return xhat
 
 
@@ -479,6 +515,13 @@ def cluster_build(wpts, xy0, phi, gamma, max_level, pc, targets, criterion=NEIGH
                               out["ids"].ctypes.data_as(_vp), out["keys"].ctypes.data_as(_vp))
         out["ids"] = out["ids"][:nnz]
         out["keys"] = out["keys"][:nc]
+        nmem = _i64()
+        L.ptrom_cluster_members(h, ctypes.byref(nmem), None, None)
+        out["mem_off"] = np.empty(nc + 1, np.int64)
+        out["mem_ids"] = np.empty(max(nmem.value, 1), np.int64)
+        L.ptrom_cluster_members(h, ctypes.byref(nmem), out["mem_off"].ctypes.data_as(_vp),
+                                out["mem_ids"].ctypes.data_as(_vp))
+        out["mem_ids"] = out["mem_ids"][:nmem.value]
         return out
     finally:
         L.ptrom_cluster_destroy(h)

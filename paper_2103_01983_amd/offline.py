@@ -82,7 +82,16 @@ def artifacts(sample, wpts, xy0, Phi_h, gamma, depth, pc, delta, dt, A, criterio
     rows = sample_rows(sample, n)
     return dict(M=Phi_h.shape[1], Mr=A.shape[0], sample=np.asarray(sample), Phibar=Phi_h[rows].copy(),
                 xbar0=np.asarray(xy0)[rows].copy(), xqt0=cl["xqt0"], Phit=cl["Phit"], Gt=cl["Gt"],
-                off=cl["off"], ids=cl["ids"], keys=cl["keys"], A=A, delta=float(delta), dt=float(dt))
+                off=cl["off"], ids=cl["ids"], keys=cl["keys"], A=A, delta=float(delta), dt=float(dt),
+                mem_off=cl["mem_off"], mem_ids=cl["mem_ids"], n=int(n))
+
+
+def reassign_host(art, gamma_mu):
+    """Clustered circulations of the artifacts' surrogates at parameter
+    gamma_mu (host, FP64): the sum of each surrogate's members."""
+    g = np.asarray(gamma_mu, dtype=np.float64)
+    off, ids = np.asarray(art["mem_off"]), np.asarray(art["mem_ids"])
+    return np.array([g[ids[off[c]:off[c + 1]]].sum() for c in range(off.size - 1)])
 
 
 def tier2(art, nsteps, tol, max_iter, alpha=1.0, jac_mode=native.JAC_PAPER, device=None, record=True):
@@ -229,3 +238,55 @@ def mae_distance(xA, xB, n, length):
     dx = xA[:n] - xB[:n]
     dy = xA[n:] - xB[n:]
     return float(np.mean(np.sqrt(dx * dx + dy * dy)) / length)
+
+
+def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100,
+                     jac_mode=native.JAC_PAPER, device=None, criterion=native.NEIGHBOR, theta=0.0, newton_tol=1e-6):
+    """Stages 1-4 over several training parameters on one GPU.  ``clouds``
+    share x^0 and delta and differ in Gamma.  One POD of the snapshots of all
+    training points; clustering weights = mean |Gamma| over the training
+    points; Tier II at every training point with its reassigned Gamma~; the
+    residual snapshots of all training points form Phi_r.  Returns
+    (artifacts with membership, info)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    t = {}
+    n = clouds[0].n
+    xy0_h = np.asarray(clouds[0].xy, np.float32).astype(np.float64)
+    x0 = torch.tensor(xy0_h, dtype=torch.float32, device=dev)
+    d = float(clouds[0].delta)
+
+    t0 = time.perf_counter()
+    S = torch.cat([trapezoid_snapshots(x0, torch.tensor(np.asarray(c.gamma, np.float32), device=dev), d, dt, nsnap,
+                                       newton_tol=newton_tol) for c in clouds])
+    torch.cuda.synchronize()
+    t["stage1_s"] = time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    Phi_d, sigma = pod(S, M)
+    Phi_h = np.ascontiguousarray(Phi_d.cpu().numpy().T)
+    wpts = weighted_points(Phi_h, sigma)
+    wgt = np.mean([np.abs(np.asarray(c.gamma, np.float32).astype(np.float64)) for c in clouds], axis=0)
+    t["stage2_s"] = time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    full = artifacts(np.arange(n), wpts, xy0_h, Phi_h, wgt, depth, pc, d, dt, np.zeros((M, 2 * n)), criterion, theta)
+    R, hists, its = [], [], []
+    for c in clouds:
+        a = dict(full)
+        a["Gt"] = reassign_host(full, np.asarray(c.gamma, np.float32).astype(np.float64))
+        r, h, i = tier2(a, nsnap, tol, max_iter, jac_mode=jac_mode, device=dev)
+        R.append(r)
+        hists.append(h)
+        its.append(i)
+    t["stage3_tier2_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Phir_d, sig_r = pod(torch.cat(R), Mr)
+    Phi_r = np.ascontiguousarray(Phir_d.cpu().numpy().T)
+    sample = greedy_sample(Phi_r, ns)
+    A = np.linalg.pinv(Phi_r[sample_rows(sample, n)])
+    art = artifacts(sample, wpts, xy0_h, Phi_h, wgt, depth, pc, d, dt, A, criterion, theta)
+    t["stage34_s"] = time.perf_counter() - t0
+    info = dict(Phi=Phi_h, sigma=sigma, sigma_r=sig_r, Phi_r=Phi_r, S=S.cpu().numpy(), wpts=wpts, weights=wgt,
+                tier2_hist=hists, tier2_iters=its, report=dict(t, nc=int(art["Gt"].size), nnz=int(art["ids"].size),
+                                                                  tier2_nc=int(full["Gt"].size)))
+    return art, info

@@ -107,3 +107,22 @@ def test_lists_with_coincident_cells_match_oracle(criterion, theta):
                      != oo.find_clusters(tree, i, 0.0, criterion, theta, cl.gamma, cl.xy) for i in range(n))
     if criterion == "neighbor":
         assert fired > 0
+
+
+@pytest.mark.parametrize("criterion,theta", [("neighbor", 1.0), ("barnes-hut", 1.0)])
+def test_members_match_oracle(criterion, theta):
+    cl, Phi, sigma = setup(300, 91)
+    P = np.ascontiguousarray(oo.weighted_points(Phi, sigma))
+    tree = oo.QuadTree(P, 6)
+    targets = np.arange(0, 300, 5)
+    *_, okeys = oo.cluster_artifacts(tree, targets, 1.0, cl.xy, Phi, cl.gamma, criterion, theta)
+    kind = native.NEIGHBOR if criterion == "neighbor" else native.BARNES_HUT
+    r = native.cluster_build(P, cl.xy, Phi, cl.gamma, 6, 1.0, targets, kind, theta)
+    mem = oo.surrogate_members(tree, okeys)
+    off = np.concatenate([[0], np.cumsum([len(m) for m in mem])])
+    assert np.array_equal(r["mem_off"], off)
+    assert np.array_equal(r["mem_ids"], np.concatenate([np.asarray(m) for m in mem]))
+    # host reassignment of the package equals the oracle's
+    g = np.random.default_rng(2).standard_normal(cl.n)
+    art = dict(mem_off=r["mem_off"], mem_ids=r["mem_ids"])
+    np.testing.assert_allclose(po.reassign_host(art, g), oo.reassign_circulation(mem, g), rtol=0, atol=1e-12)
