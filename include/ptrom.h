@@ -227,7 +227,10 @@ typedef struct {
 
 /* Copy the artifacts to the device (surrogate and sampled rows as FP32 for
  * the gather, A as FP64 for the least-squares solve).  Requires
- * 1 <= M <= 32, M <= Mr <= 64, 1 <= ns <= 2^20, ids in [0, Nc). */
+ * 1 <= M <= 96, M <= Mr <= 256, 1 <= ns <= 2^20, ids in [0, Nc); the exact
+ * Jacobian needs M <= 32 and Mr <= 64.  Bases beyond 32 / 64 take a blocked
+ * path whose per-query arrays must fit one workgroup's LDS (EINVAL from the
+ * run calls otherwise). */
 int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptrom_rom **out);
 void ptrom_rom_destroy(ptrom_rom *rom);
 

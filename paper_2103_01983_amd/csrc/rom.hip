@@ -38,9 +38,12 @@ using namespace ptrom;
 
 namespace {
 
-constexpr int kMaxM = 32;
-constexpr int kMaxMr = 64;
-constexpr int kLt = kMaxM + 1;  // row stride of the transposed factor in LDS (bank spread)
+// Small bases (M <= 32, M_r <= 64) take the register/single-wave path; larger
+// ones (paper Jacobian) the blocked path, up to kMaxM / kMaxMr.
+constexpr int kSmallM = 32;
+constexpr int kSmallMr = 64;
+constexpr int kMaxM = 96;
+constexpr int kMaxMr = 256;
 constexpr int kRunThreads = 512;  // 8 waves: up to 256 VGPRs per lane
 constexpr double kInv2PiD = 0.15915494309189533576888376337251;
 
@@ -121,7 +124,7 @@ __device__ __forceinline__ void sampled_position(const float *Phibar, const floa
 
 // One entry row in registers: r0x r0y Gamma~ pad, then (Dx_m, Dy_m) pairs,
 // padded to whole float4 chunks.
-constexpr int kMaxEw = 4 + 2 * kMaxM;
+constexpr int kMaxEw = 4 + 2 * kSmallM;
 
 constexpr int kShortEw = 36;  // rows of bases with M <= 16
 
@@ -142,7 +145,7 @@ __device__ __forceinline__ void load_entry(const float *ent, int ew, int e, floa
 template <bool EXACT>
 struct GatherAcc {
   float fx = 0.f, fy = 0.f, ba = 0.f, bb = 0.f, bc = 0.f;
-  float ex[EXACT ? kMaxM : 1] = {}, ey[EXACT ? kMaxM : 1] = {};
+  float ex[EXACT ? kSmallM : 1] = {}, ey[EXACT ? kSmallM : 1] = {};
 };
 
 // Velocity and Jacobian terms of one (target, surrogate) entry at xhat:
@@ -172,7 +175,7 @@ __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *r
     // D re-read from the row (cache hit) so the register copy is not kept live
     const float h00 = g2 * a2, h01 = g2 * (dd - d2), h10 = g2 * (dd + d2);
 #pragma unroll
-    for (int m = 0; m < kMaxM; ++m)
+    for (int m = 0; m < kSmallM; ++m)
       if (m < M) {
         const float dx = row[4 + 2 * m], dy = row[5 + 2 * m];
         a.ex[m] = fmaf(h00, dx, fmaf(h01, dy, a.ex[m]));
@@ -183,6 +186,39 @@ __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *r
     a.bb = fmaf(g2, dd - d2, a.bb);
     a.bc = fmaf(g2, dd + d2, a.bc);
   }
+}
+
+// The same terms for an entry row read straight from memory in float4 chunks
+// (bases with M > 32, paper Jacobian): r = r0 + D xhat, then the velocity and
+// the 2x2 block.
+__device__ __forceinline__ void entry_terms_stream(const float *row, const float *xf, const float *gt, int M, float d2,
+                                                   GatherAcc<false> &a) {
+  const float4 head = *reinterpret_cast<const float4 *>(row);
+  float rx = head.x, ry = head.y;
+  const float4 *p = reinterpret_cast<const float4 *>(row + 4);
+  const int nq = (2 * M + 3) / 4;  // chunks of two modes
+#pragma unroll 4
+  for (int c = 0; c < nq; ++c) {
+    const float4 q = p[c];
+    const int m = 2 * c;
+    rx = fmaf(q.x, xf[m], rx);
+    ry = fmaf(q.y, xf[m], ry);
+    if (m + 1 < M) {
+      rx = fmaf(q.z, xf[m + 1], rx);
+      ry = fmaf(q.w, xf[m + 1], ry);
+    }
+  }
+  const float qq = fmaf(rx, rx, fmaf(ry, ry, d2));
+  const float r = qq > 0.f ? 1.0f / qq : 0.f;
+  const float g = (gt ? gt[__builtin_bit_cast(int, head.w)] : head.z) * r;
+  a.fx = fmaf(-ry, g, a.fx);
+  a.fy = fmaf(rx, g, a.fy);
+  const float g2 = g * r;
+  const float a2 = (rx + rx) * ry;
+  const float dd = fmaf(ry, ry, -rx * rx);
+  a.ba = fmaf(g2, a2, a.ba);
+  a.bb = fmaf(g2, dd - d2, a.bb);
+  a.bc = fmaf(g2, dd + d2, a.bc);
 }
 
 // Sum over an aligned group of G = 16, 32 or 64 lanes (G uniform); every lane
@@ -215,7 +251,9 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
     const int e1 = d.off[t + 1];
     int e = d.off[t] + gl;
     if constexpr (!EXACT) {
-      if (d.ew <= kShortEw) {
+      if (M > kSmallM) {
+        for (; e < e1; e += G) entry_terms_stream(d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
+      } else if (d.ew <= kShortEw) {
         for (; e + G < e1; e += 2 * G) {
           float v0[kShortEw], v1[kShortEw];
           load_entry(d.ent, d.ew, e, v0);
@@ -253,7 +291,7 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
     if constexpr (EXACT) {
       // C_t = Phibar_t - dt/2 sum_e G_e (Phibar_t - Phit_c)
 #pragma unroll
-      for (int m = 0; m < kMaxM; ++m) {
+      for (int m = 0; m < kSmallM; ++m) {
         if (m < M) {
           const double jx = gsum(a.ex[m], G) * kInv2PiD, jy = gsum(a.ey[m], G) * kInv2PiD;
           if (valid && gl == (m & (G - 1))) {
@@ -307,8 +345,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // r, D(4 r + l / 16, l % 16) (tile-local indices).  xa / yb return 0 outside
 // the matrices.  The wave must be fully active.
 template <class FX, class FY>
-__device__ __forceinline__ dbl4 mfma_tile(int K, int lane, FX xa, FY yb) {
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+__device__ __forceinline__ dbl4 mfma_tile(int K, int lane, FX xa, FY yb, dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0}) {
   const int r = lane & 15, kq = lane >> 4;
 #pragma unroll 4
   for (int k0 = 0; k0 < K; k0 += 4) {
@@ -333,9 +370,9 @@ template <bool EXACT>
 __global__ void __launch_bounds__(kRunThreads)
     rom_run_kernel(RomDev d, int nsteps, int lds_arrays, int entry_par, const float *__restrict__ gtq,
                    double *__restrict__ xhat, double *__restrict__ hist, int *__restrict__ iters) {
-  __shared__ double xh[kMaxM];
-  __shared__ float xf[kMaxM];
-  __shared__ double rr[kMaxMr], gq[kMaxM], xs[kMaxM], gvec[kMaxM];
+  __shared__ double xh[kSmallM];
+  __shared__ float xf[kSmallM];
+  __shared__ double rr[kSmallMr], gq[kSmallM], xs[kSmallM], gvec[kSmallM];
   __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
@@ -343,7 +380,7 @@ __global__ void __launch_bounds__(kRunThreads)
   const int lg = M1;  // row stride of G'
   const double hdt = 0.5 * (double)d.dt;
   // G' = A [C | rbar] (Mr x (M + 1)) and the Gauss-Jordan tableau [N | I]
-  // (rows padded to kMaxM, columns to 64: one column per lane of a wave) at
+  // (rows padded to kSmallM, columns to 64: one column per lane of a wave) at
   // the front of the dynamic LDS
   double *Gp = dyn, *T0 = Gp + (size_t)Mr * lg;
 
@@ -359,7 +396,7 @@ __global__ void __launch_bounds__(kRunThreads)
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
   if (iters) iters += (size_t)blockIdx.x * nsteps;
   if (lds_arrays) {
-    double *p = T0 + (size_t)kMaxM * 64;
+    double *p = T0 + (size_t)kSmallM * 64;
     double *Al = p; p += (size_t)Mr * nd;
     Cp = p; p += (size_t)nd * ldc;
     fbar = p; p += nd;
@@ -515,7 +552,7 @@ __global__ void __launch_bounds__(kRunThreads)
         }
       }
       // identity block and zero padding of the tableau
-      for (int t = tid; t < kMaxM * 64; t += kRunThreads) {
+      for (int t = tid; t < kSmallM * 64; t += kRunThreads) {
         const int i = t >> 6, j = t & 63;
         if (i >= M || j >= M) T0[t] = (i < M && j - M == i) ? 1.0 : 0.0;
       }
@@ -542,7 +579,7 @@ __global__ void __launch_bounds__(kRunThreads)
           }
           const double rk = T0[kk * 64 + lane] * ip;
 #pragma unroll
-          for (int i0 = 0; i0 < kMaxM; i0 += 8) {
+          for (int i0 = 0; i0 < kSmallM; i0 += 8) {
             if (i0 < M) {
               double c[8], o[8];
 #pragma unroll
@@ -628,11 +665,283 @@ __global__ void __launch_bounds__(kRunThreads)
   if (tid < M) xhat[tid] = xh[tid];
 }
 
+// ----------------------------------------------------------- larger bases
+
+// Bases with M > 32 or M_r > 64 (paper Jacobian; M <= 96, M_r <= 256).  One
+// workgroup per query;
+// per Gauss-Newton iteration:
+//   gather    one thread per list entry (rows streamed from memory) into
+//             per-entry terms in LDS, per-target sums, then [C | rbar] in LDS;
+//   normal    N' = G'^T G' with G' = A [C | rbar] accumulated over 16-row
+//   matrix    blocks of A: the block is staged in LDS, G'_blk = A_blk [C |
+//             rbar] and N' += G'_blk^T G'_blk run on the FP64 matrix cores,
+//             each wave keeping its (lower-triangle) tiles of N' in registers;
+//   solve     Gauss-Jordan elimination of [N | g] in place (N = G^T G,
+//             g = G^T b) across the workgroup, each thread holding its
+//             elements in registers; the owners of the next pivot row and
+//             column publish them to LDS (one barrier a pivot).  A
+//             non-positive pivot leaves its direction out.
+// LDS: region 1 holds [C | rbar] and then the tableau; region 2 holds the
+// per-entry terms during the gather and the A / G' row blocks afterwards.
+constexpr int kMaxTiles = 4;   // lower-triangle tiles of N' per wave (M + 1 <= 112: 28 tiles)
+constexpr int kMaxElems = 19;  // tableau elements per thread (M (M + 1) <= 96 x 97)
+
+struct BigLayout {
+  size_t r1, r2, total;  // doubles
+};
+
+__host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, int64_t nnz, int nc_table) {
+  (void)Mr;
+  const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16;
+  BigLayout L;
+  L.r1 = (size_t)nd * M1 > (size_t)M * M1 ? (size_t)nd * M1 : (size_t)M * M1;
+  const size_t gather = 3 * (size_t)ns + nd + (5 * (size_t)nnz + 1) / 2;
+  const size_t blocks = 16 * (size_t)nd + 16 * (size_t)M1p;
+  L.r2 = gather > blocks ? gather : blocks;
+  L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)nc_table + 1) / 2;
+  return L;
+}
+
+__global__ void __launch_bounds__(kRunThreads)
+    rom_run_large_kernel(RomDev d, int nsteps, const float *__restrict__ gtq, double *__restrict__ xhat,
+                         double *__restrict__ hist, int *__restrict__ iters) {
+  __shared__ double xh[kMaxM], xs[kMaxM];
+  __shared__ float xf[kMaxM];
+  __shared__ double rowbuf[2][kMaxM + 1], colbuf[2][kMaxM], ipbuf[2];
+  __shared__ double s_eps, s_g1, s_gn;
+  extern __shared__ double dyn[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
+  const int M = d.M, Mr = d.Mr, nd = d.nd, ns = d.ns, M1 = M + 1, M1p = (M1 + 15) / 16 * 16;
+  const int nnz = (int)d.nnz;
+  const double hdt = 0.5 * (double)d.dt;
+  const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, gtq ? d.Nc : 0);
+  double *R1 = dyn, *R2 = dyn + L.r1;
+  double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
+  double *Cp = R1, *T = R1;                      // [C | rbar] (nd x M1), then [N | g] (M x M1)
+  double *bt = R2, *xcur = R2 + 3 * ns;          // gather phase
+  float *ct = reinterpret_cast<float *>(xcur + nd);
+  double *Ab = R2, *Gb = R2 + 16 * (size_t)nd;   // product phase
+  const float *gt = nullptr;
+  xhat += (size_t)blockIdx.x * M;
+  if (hist) hist += (size_t)blockIdx.x * nsteps * M;
+  if (iters) iters += (size_t)blockIdx.x * nsteps;
+  if (gtq) {
+    float *g = reinterpret_cast<float *>(xbar_prev + nd);
+    for (int t = tid; t < d.Nc; t += kRunThreads) g[t] = gtq[(size_t)blockIdx.x * d.Nc + t];
+    gt = g;
+  }
+  if (tid < M) {
+    xh[tid] = xhat[tid];
+    xf[tid] = (float)xhat[tid];
+  }
+  __syncthreads();
+
+  // HyperPair of the paper: per-entry terms, sampled rows, per-target sums.
+  // With res == false only fbar_out and the sampled rows (xbar_out) are kept.
+  auto hyperpair = [&](bool res, double *xbar_out, double *fbar_out) {
+    for (int e = tid; e < nnz; e += kRunThreads) {
+      GatherAcc<false> a;
+      entry_terms_stream(d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
+      ct[e] = a.fx;
+      ct[nnz + e] = a.fy;
+      ct[2 * nnz + e] = a.ba;
+      ct[3 * nnz + e] = a.bb;
+      ct[4 * nnz + e] = a.bc;
+    }
+    for (int q = tid; q < nd; q += kRunThreads) {
+      double x = d.xbar0[q];
+      const float *ph = d.Phibar + (size_t)q * M;
+      for (int m = 0; m < M; ++m) x += (double)ph[m] * xh[m];
+      xcur[q] = x;
+    }
+    __syncthreads();
+    for (int t = tid; t < ns; t += kRunThreads) {
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+      for (int e = d.off[t]; e < d.off[t + 1]; ++e) {
+        s0 += ct[e];
+        s1 += ct[nnz + e];
+        s2 += ct[2 * nnz + e];
+        s3 += ct[3 * nnz + e];
+        s4 += ct[4 * nnz + e];
+      }
+      const double Fx = s0 * kInv2PiD, Fy = s1 * kInv2PiD;
+      fbar_out[t] = Fx;
+      fbar_out[ns + t] = Fy;
+      if (res) {
+        Cp[(size_t)t * M1 + M] = (xcur[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+        Cp[(size_t)(ns + t) * M1 + M] = (xcur[ns + t] - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+        bt[3 * t] = s2 * kInv2PiD;
+        bt[3 * t + 1] = s3 * kInv2PiD;
+        bt[3 * t + 2] = s4 * kInv2PiD;
+      }
+    }
+    if (xbar_out)
+      for (int q = tid; q < nd; q += kRunThreads) xbar_out[q] = xcur[q];
+    __syncthreads();
+  };
+
+  hyperpair(false, xbar_prev, fbar_prev);  // previous-step terms for the first step
+
+  const int tcn = M1p / 16, ntile = tcn * (tcn + 1) / 2;
+  const int ne = M * M1;
+  for (int step = 0; step < nsteps; ++step) {
+    int k = 1;
+    for (;;) {
+      hyperpair(true, nullptr, fbar);
+      // C = Phibar - dt/2 B Phibar
+      for (int q = tid; q < nd * M; q += kRunThreads) {
+        const int row = q / M, m = q - row * M;
+        const int t = row < ns ? row : row - ns;
+        const double px = d.Phibar[(size_t)t * M + m], py = d.Phibar[(size_t)(ns + t) * M + m];
+        const double B00 = bt[3 * t], B01 = bt[3 * t + 1], B10 = bt[3 * t + 2];
+        Cp[(size_t)row * M1 + m] = row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py);
+      }
+      // N' = G'^T G' over 16-row blocks of A (the gather's LDS is free now)
+      dbl4 acc[kMaxTiles];
+#pragma unroll
+      for (int u = 0; u < kMaxTiles; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int rb = 0; rb < Mr; rb += 16) {
+        __syncthreads();  // C complete / previous block consumed
+        for (int t = tid; t < 16 * nd; t += kRunThreads) {
+          const int r = t / nd, q = t - r * nd;
+          Ab[t] = rb + r < Mr ? d.A[(size_t)(rb + r) * nd + q] : 0.0;
+        }
+        __syncthreads();
+        for (int tj = wave; tj < tcn; tj += nwaves) {
+          const int j0 = tj * 16;
+          const dbl4 g = mfma_tile(nd, lane, [&](int i, int q) { return Ab[(size_t)i * nd + q]; },
+                                   [&](int q, int j) { return j0 + j < M1 ? Cp[(size_t)q * M1 + j0 + j] : 0.0; });
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Gb[(4 * r + (lane >> 4)) * M1p + j0 + (lane & 15)] = g[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMaxTiles; ++u) {
+          const int tile = wave + u * nwaves;
+          if (tile < ntile) {
+            int ti = 0;
+            while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+            const int tj = tile - ti * (ti + 1) / 2;
+            acc[u] = mfma_tile(16, lane, [&](int i, int q) { return Gb[q * M1p + ti * 16 + i]; },
+                               [&](int q, int j) { return Gb[q * M1p + tj * 16 + j]; }, acc[u]);
+          }
+        }
+      }
+      __syncthreads();  // [C | rbar] is dead: the tableau takes region 1
+#pragma unroll
+      for (int u = 0; u < kMaxTiles; ++u) {
+        const int tile = wave + u * nwaves;
+        if (tile < ntile) {
+          int ti = 0;
+          while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+          const int tj = tile - ti * (ti + 1) / 2;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = ti * 16 + 4 * r + (lane >> 4), col = tj * 16 + (lane & 15);
+            const double v = acc[u][r];
+            if (row < M && col <= row) {  // lower triangle only: one writer per entry
+              T[(size_t)row * M1 + col] = v;
+              T[(size_t)col * M1 + row] = v;
+            } else if (row == M && col < M) {
+              T[(size_t)col * M1 + M] = v;  // g = G^T b
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+        double s = 0.0;
+        for (int i = lane; i < M; i += 64) s += T[(size_t)i * M1 + M] * T[(size_t)i * M1 + M];
+        const double gn = sqrt(wsumd(s));
+        if (lane == 0) s_gn = gn;
+      }
+      // Gauss-Jordan on [N | g]: thread tid owns elements tid + 512 u
+      {
+        double v[kMaxElems];
+        int ij[kMaxElems];
+#pragma unroll
+        for (int u = 0; u < kMaxElems; ++u) {
+          const int e = tid + u * kRunThreads;
+          const int i = e < ne ? e / M1 : 0;
+          ij[u] = e < ne ? (i << 16) | (e - i * M1) : -1;
+          v[u] = e < ne ? T[e] : 0.0;
+        }
+        auto publish = [&](int kk) {
+          const int b = kk & 1;
+          const int pe = kk * M1 + kk;
+          double pv = 0.0;
+#pragma unroll
+          for (int u = 0; u < kMaxElems; ++u) {
+            if (ij[u] >= 0) {
+              const int i = ij[u] >> 16, j = ij[u] & 0xffff;
+              if (i == kk) rowbuf[b][j] = v[u];
+              if (j == kk) colbuf[b][i] = v[u];
+            }
+            if (u == pe / kRunThreads) pv = v[u];
+          }
+          if (tid == pe % kRunThreads) ipbuf[b] = pv > 0.0 ? 1.0 / pv : 0.0;
+        };
+        publish(0);
+        __syncthreads();
+        for (int kk = 0; kk < M; ++kk) {
+          const int b = kk & 1;
+          const double ip = ipbuf[b];
+#pragma unroll
+          for (int u = 0; u < kMaxElems; ++u) {
+            if (ij[u] >= 0) {
+              const int i = ij[u] >> 16, j = ij[u] & 0xffff;
+              if (i == kk)
+                v[u] = j == kk ? ip : v[u] * ip;
+              else if (j == kk)
+                v[u] = -v[u] * ip;
+              else
+                v[u] = fma(-colbuf[b][i] * ip, rowbuf[b][j], v[u]);
+            }
+          }
+          if (kk + 1 < M) publish(kk + 1);
+          __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < kMaxElems; ++u)
+          if (ij[u] >= 0 && (ij[u] & 0xffff) == M) xs[ij[u] >> 16] = v[u];
+      }
+      __syncthreads();
+      if (tid < M) {
+        xh[tid] -= d.alpha * xs[tid];
+        xf[tid] = (float)xh[tid];
+      }
+      if (tid == 0) {
+        const double gn = s_gn;
+        if (k == 1) s_g1 = gn;
+        const double g1 = k == 1 ? gn : s_g1;
+        s_eps = g1 > 0.0 ? gn / g1 : 0.0;
+      }
+      __syncthreads();
+      ++k;
+      if (!(s_eps > d.tol) || k > d.max_iter) break;
+      __syncthreads();
+    }
+    if (tid < M && hist) hist[(size_t)step * M + tid] = xh[tid];
+    if (tid == 0 && iters) iters[step] = k - 1;
+    // previous-step terms: sampled rows at the accepted xhat, velocity of the
+    // last HyperPair evaluation
+    for (int q = tid; q < nd; q += kRunThreads) {
+      double x = d.xbar0[q];
+      const float *ph = d.Phibar + (size_t)q * M;
+      for (int m = 0; m < M; ++m) x += (double)ph[m] * xh[m];
+      xbar_prev[q] = x;
+      fbar_prev[q] = fbar[q];
+    }
+    __syncthreads();
+  }
+  if (tid < M) xhat[tid] = xh[tid];
+}
+
 // dynamic LDS of the run kernel: G' and the tableaux always; the copies of
 // the arrays when lds_arrays; the per-entry terms only in the entry-parallel
 // gather
 size_t solve_lds_bytes(int M, int Mr) {
-  return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)kMaxM * 64);
+  return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)kSmallM * 64);
 }
 
 size_t run_lds_bytes(int M, int Mr, int nd, int ns, int ldc, int64_t nnz, bool entry_par, int64_t nc_table) {
@@ -663,7 +972,8 @@ struct ptrom_rom {
   void *buf = nullptr;
   int *members = nullptr;  // device: mem_off [Nc+1] then mem_ids
   int64_t n_bodies = 0;
-  size_t max_dyn_lds = 0;  // dynamic LDS the run kernel may take on this device
+  size_t max_dyn_lds = 0;      // dynamic LDS the run kernel may take on this device
+  size_t max_dyn_lds_big = 0;  // same for the larger-basis kernel
 };
 
 extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptrom_rom **out) {
@@ -672,7 +982,9 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   if (!desc || !out) return ctx->fail(PTROM_EINVAL, "NULL argument");
   const ptrom_rom_desc &s = *desc;
   if (s.M < 1 || s.M > kMaxM || s.Mr < s.M || s.Mr > kMaxMr || s.ns < 1 || s.ns > (1 << 20))
-    return ctx->fail(PTROM_EINVAL, "need 1 <= M <= 32, M <= Mr <= 64, 1 <= ns <= 2^20");
+    return ctx->fail(PTROM_EINVAL, "need 1 <= M <= 96, M <= Mr <= 256, 1 <= ns <= 2^20");
+  if (s.jac_mode == PTROM_JAC_EXACT && (s.M > kSmallM || s.Mr > kSmallMr))
+    return ctx->fail(PTROM_EINVAL, "the exact Jacobian needs M <= 32 and Mr <= 64");
   const int nd = 2 * s.ns;
   if (s.Nc < 0 || s.nnz < 0 || s.Nc > kMaxN || s.nnz > (int64_t(1) << 31) - 1)
     return ctx->fail(PTROM_EINVAL, "bad Nc / nnz");
@@ -735,6 +1047,16 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
         (void)hipGetLastError();
         break;
       }
+    hipFuncAttributes fb{};
+    const void *big = reinterpret_cast<const void *>(rom_run_large_kernel);
+    size_t sb = 0;
+    if (hipFuncGetAttributes(&fb, big) == hipSuccess) sb = fb.sharedSizeBytes;
+    size_t dynb = size_t(maxsh) > sb ? size_t(maxsh) - sb : 0;
+    if (hipFuncSetAttribute(big, hipFuncAttributeMaxDynamicSharedMemorySize, int(dynb)) != hipSuccess) {
+      dynb = 64 * 1024 > sb ? 64 * 1024 - sb : 0;
+      (void)hipGetLastError();
+    }
+    rom->max_dyn_lds_big = dynb;
     rom->max_dyn_lds = dyn;
   }
   RomDev &d = rom->d;
@@ -833,6 +1155,16 @@ int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xha
                int32_t *iters, hipStream_t st) {
   ptrom_ctx *ctx = rom->ctx;
   const RomDev &d = rom->d;
+  if (d.M > kSmallM || d.Mr > kSmallMr) {
+    const BigLayout L = big_layout(d.M, d.Mr, d.nd, d.ns, d.nnz, gtq ? d.Nc : 0);
+    const size_t bytes = L.total * sizeof(double);
+    if (bytes > rom->max_dyn_lds_big)
+      return ctx->fail(PTROM_EINVAL, "basis, sample set and lists too large for one workgroup's LDS");
+    hipLaunchKernelGGL(rom_run_large_kernel, dim3(nq), dim3(kRunThreads), bytes, st, d, nsteps, gtq, xhat,
+                       xhat_hist, iters);
+    PTROM_CHECK_HIP(ctx, hipGetLastError());
+    return PTROM_OK;
+  }
   const int64_t table = gtq ? d.Nc : 0;
   // entry-parallel gather (paper Jacobian) when its per-entry terms fit in LDS
   // next to the other copies; otherwise the grouped gather

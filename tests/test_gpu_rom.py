@@ -189,3 +189,80 @@ def test_rom_run_shapes(dev, trained_shapes, shape, mode):
     h = hist.cpu().numpy().reshape(steps, M)
     assert np.all(np.isfinite(h))
     assert rel(h, o["hist"]) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def large_shapes():
+    """Bases beyond 32 (the blocked path): M = 48 / M_r = 96 / n_s = 48 and
+    the paper's vortex-pair sizes M = 85 / M_r = 110 / n_s = 60, with random
+    orthonormal Phi and Phi_r and the training clustering and sampling."""
+    out = {}
+    cl = W.counter_rotating_patches(640, seed=43, delta=0.02)
+    n = cl.n
+    rng = np.random.default_rng(44)
+    for M, Mr, ns in [(48, 96, 48), (85, 110, 60)]:
+        Phi = np.linalg.qr(rng.standard_normal((2 * n, M)))[0]
+        sig = np.sort(rng.uniform(1.0, 10.0, M))[::-1]
+        tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+        sample = np.sort(rng.choice(n, ns, replace=False))
+        Phi_r = np.linalg.qr(rng.standard_normal((2 * n, Mr)))[0]
+        A = off.gappy_operator(Phi_r, sample)
+        out[(M, Mr, ns)] = rounded(off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A))
+    return out
+
+
+@pytest.mark.parametrize("shape", [(48, 96, 48), (85, 110, 60)])
+def test_large_hyperpair_parity(dev, large_shapes, shape):
+    art = large_shapes[shape]
+    M = shape[0]
+    nd = 2 * shape[2]
+    rng = np.random.default_rng(5)
+    xh = rng.standard_normal(M) * 0.02
+    xp, fp = rng.standard_normal(nd) * 0.1 + art["xbar0"], rng.standard_normal(nd) * 0.1
+    xb, fb, rb, C = oracle.Rom(art).hyperpair(xh, xp, fp)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    gx, gf, gr, gC = native.Rom(art).hyperpair(t(xh), t(xp), t(fp))
+    assert rel(gx.cpu().numpy(), xb) <= 1e-14
+    assert rel(gf.cpu().numpy(), fb) <= 1e-5
+    assert rel(gr.cpu().numpy(), rb) <= 1e-5
+    assert rel(gC.cpu().numpy() - art["Phibar"], C - art["Phibar"]) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(48, 96, 48), (85, 110, 60)])
+def test_large_run_fixed_iterations(dev, large_shapes, shape):
+    art = large_shapes[shape]
+    M = shape[0]
+    steps, K = 10, 3
+    o = oracle.Rom(art).run(steps, tol=0.0, max_iter=K)
+    rom = native.Rom(art, tol=0.0, max_iter=K)
+    xh = torch.zeros(M, dtype=torch.float64, device=dev)
+    hist = torch.empty(steps * M, dtype=torch.float64, device=dev)
+    it = torch.empty(steps, dtype=torch.int32, device=dev)
+    rom.run(steps, xh, hist, it)
+    torch.cuda.synchronize()
+    assert np.all(it.cpu().numpy() == K)
+    h = hist.cpu().numpy().reshape(steps, M)
+    assert np.all(np.isfinite(h))
+    assert rel(h, o["hist"]) <= 1e-5
+
+
+def test_large_batched_queries(dev, large_shapes):
+    art = large_shapes[(48, 96, 48)]
+    M, steps, K, nq = 48, 8, 3, 3
+    scales = [1.0, 0.7, 1.3]
+    gt = np.stack([np.asarray(art["Gt"]) * s for s in scales]).astype(np.float32)
+    rom = native.Rom(art, tol=0.0, max_iter=K)
+    xq = torch.zeros((nq, M), dtype=torch.float64, device=dev)
+    hq = torch.empty((nq, steps, M), dtype=torch.float64, device=dev)
+    rom.run_batched(torch.tensor(gt, device=dev), steps, xq, hq, None)
+    torch.cuda.synchronize()
+    for q in range(nq):
+        aq = dict(art)
+        aq["Gt"] = gt[q].astype(np.float64)
+        o = oracle.Rom(aq).run(steps, tol=0.0, max_iter=K)
+        assert rel(hq[q].cpu().numpy(), o["hist"]) <= 1e-5, q
+
+
+def test_large_exact_jacobian_rejected(dev, large_shapes):
+    with pytest.raises(native.PtromError):
+        native.Rom(large_shapes[(48, 96, 48)], jac_mode=native.JAC_EXACT)
