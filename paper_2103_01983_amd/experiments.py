@@ -117,7 +117,7 @@ def run(n, case=1, depth=16, device=None):
                 report=info["report"])
 
 
-def vortex_pair_study(n=500, M=32, Mr=64, ns=32, pc=1.0, tol=1e-4, depth=16, gamma_max=255.0, t_f=5.0, dt=0.01,
+def vortex_pair_study(n=500, M=85, Mr=110, ns=60, pc=1.0, tol=1e-4, depth=16, gamma_max=255.0, t_f=5.0, dt=0.01,
                       ntrain=4, grid=6, seed=2103, newton_tol=2e-5, device=None):
     """Parametric vortex pair: offline training at ntrain Latin-hypercube
     points, then grid x grid queries in one batched launch; accuracy of every
@@ -199,9 +199,12 @@ def main(argv=None):
     p.add_argument("--study", default="single_vortex", choices=["single_vortex", "vortex_pair"])
     p.add_argument("--n", type=int, nargs="+", default=[500])
     p.add_argument("--case", type=int, default=1)
+    p.add_argument("--basis", type=int, nargs=3, default=[85, 110, 60], metavar=("M", "MR", "NS"),
+                   help="vortex pair: M, M_r, n_s (the paper's 85, 110, 60)")
     a = p.parse_args(argv)
     if a.study == "vortex_pair":
-        print(json.dumps(vortex_pair_study()), flush=True)
+        M, Mr, ns = a.basis
+        print(json.dumps(vortex_pair_study(M=M, Mr=Mr, ns=ns)), flush=True)
         return 0
     for n in a.n:
         print(json.dumps(run(n, a.case)), flush=True)
