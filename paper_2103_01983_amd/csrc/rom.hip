@@ -676,15 +676,15 @@ __global__ void __launch_bounds__(kRunThreads)
 //   matrix    blocks of A: the block is staged in LDS, G'_blk = A_blk [C |
 //             rbar] and N' += G'_blk^T G'_blk run on the FP64 matrix cores,
 //             each wave keeping its (lower-triangle) tiles of N' in registers;
-//   solve     Gauss-Jordan elimination of [N | g] in place (N = G^T G,
-//             g = G^T b) across the workgroup, each thread holding its
-//             elements in registers; the owners of the next pivot row and
-//             column publish them to LDS (one barrier a pivot).  A
-//             non-positive pivot leaves its direction out.
-// LDS: region 1 holds [C | rbar] and then the tableau; region 2 holds the
-// per-entry terms during the gather and the A / G' row blocks afterwards.
+//   solve     N = G^T G is inverted in place by blocked Gauss-Jordan over
+//             16 x 16 blocks: one wave inverts the pivot block in registers
+//             (a non-positive pivot leaves its direction out), the row and
+//             column panels and the rank-16 trailing update run on the FP64
+//             matrix cores; then x = N^-1 g with g = G^T b.
+// LDS: region 1 holds [C | rbar] and then N; region 2 holds the per-entry
+// terms during the gather, the A / G' row blocks during the product and the
+// panels during the inversion.
 constexpr int kMaxTiles = 4;   // lower-triangle tiles of N' per wave (M + 1 <= 112: 28 tiles)
-constexpr int kMaxElems = 19;  // tableau elements per thread (M (M + 1) <= 96 x 97)
 
 struct BigLayout {
   size_t r1, r2, total;  // doubles
@@ -692,12 +692,15 @@ struct BigLayout {
 
 __host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, int64_t nnz, int nc_table) {
   (void)Mr;
-  const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16;
+  const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16, Mp = (M + 15) / 16 * 16;
   BigLayout L;
-  L.r1 = (size_t)nd * M1 > (size_t)M * M1 ? (size_t)nd * M1 : (size_t)M * M1;
+  const size_t tab = (size_t)Mp * (Mp + 1);  // padded tableau, odd row stride
+  L.r1 = (size_t)nd * M1 > tab ? (size_t)nd * M1 : tab;
   const size_t gather = 3 * (size_t)ns + nd + (5 * (size_t)nnz + 1) / 2;
   const size_t blocks = 16 * (size_t)nd + 16 * (size_t)M1p;
+  const size_t inv = 2 * 16 * (size_t)Mp + 256 + Mp;  // row / column panels, block inverse, g
   L.r2 = gather > blocks ? gather : blocks;
+  L.r2 = L.r2 > inv ? L.r2 : inv;
   L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)nc_table + 1) / 2;
   return L;
 }
@@ -707,7 +710,6 @@ __global__ void __launch_bounds__(kRunThreads)
                          double *__restrict__ hist, int *__restrict__ iters) {
   __shared__ double xh[kMaxM], xs[kMaxM];
   __shared__ float xf[kMaxM];
-  __shared__ double rowbuf[2][kMaxM + 1], colbuf[2][kMaxM], ipbuf[2];
   __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
@@ -717,10 +719,12 @@ __global__ void __launch_bounds__(kRunThreads)
   const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, gtq ? d.Nc : 0);
   double *R1 = dyn, *R2 = dyn + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
-  double *Cp = R1, *T = R1;                      // [C | rbar] (nd x M1), then [N | g] (M x M1)
+  double *Cp = R1, *T = R1;                      // [C | rbar] (nd x M1), then N (Mp x Mp, stride ldT)
   double *bt = R2, *xcur = R2 + 3 * ns;          // gather phase
   float *ct = reinterpret_cast<float *>(xcur + nd);
   double *Ab = R2, *Gb = R2 + 16 * (size_t)nd;   // product phase
+  const int Mp = (M + 15) / 16 * 16, ldT = Mp + 1;
+  double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp, *gb = Pinv + 256;  // inversion
   const float *gt = nullptr;
   xhat += (size_t)blockIdx.x * M;
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
@@ -783,7 +787,6 @@ __global__ void __launch_bounds__(kRunThreads)
   hyperpair(false, xbar_prev, fbar_prev);  // previous-step terms for the first step
 
   const int tcn = M1p / 16, ntile = tcn * (tcn + 1) / 2;
-  const int ne = M * M1;
   for (int step = 0; step < nsteps; ++step) {
     int k = 1;
     for (;;) {
@@ -828,6 +831,12 @@ __global__ void __launch_bounds__(kRunThreads)
         }
       }
       __syncthreads();  // [C | rbar] is dead: the tableau takes region 1
+      // N = G^T G into the padded tableau T (Mp x Mp, row stride ldT; the
+      // padding is the identity), g = G^T b into gb
+      for (int t = tid; t < Mp * Mp; t += kRunThreads) {
+        const int i = t / Mp, j = t - i * Mp;
+        if (i >= M || j >= M) T[(size_t)i * ldT + j] = i == j ? 1.0 : 0.0;
+      }
 #pragma unroll
       for (int u = 0; u < kMaxTiles; ++u) {
         const int tile = wave + u * nwaves;
@@ -840,70 +849,105 @@ __global__ void __launch_bounds__(kRunThreads)
             const int row = ti * 16 + 4 * r + (lane >> 4), col = tj * 16 + (lane & 15);
             const double v = acc[u][r];
             if (row < M && col <= row) {  // lower triangle only: one writer per entry
-              T[(size_t)row * M1 + col] = v;
-              T[(size_t)col * M1 + row] = v;
+              T[(size_t)row * ldT + col] = v;
+              T[(size_t)col * ldT + row] = v;
             } else if (row == M && col < M) {
-              T[(size_t)col * M1 + M] = v;  // g = G^T b
+              gb[col] = v;  // g = G^T b
             }
           }
         }
       }
       __syncthreads();
       if (wave == 0) {
-        double s = 0.0;
-        for (int i = lane; i < M; i += 64) s += T[(size_t)i * M1 + M] * T[(size_t)i * M1 + M];
-        const double gn = sqrt(wsumd(s));
+        double sq = 0.0;
+        for (int i = lane; i < M; i += 64) sq += gb[i] * gb[i];
+        const double gn = sqrt(wsumd(sq));
         if (lane == 0) s_gn = gn;
       }
-      // Gauss-Jordan on [N | g]: thread tid owns elements tid + 512 u
-      {
-        double v[kMaxElems];
-        int ij[kMaxElems];
+      // ---- blocked Gauss-Jordan inversion of T in place (16 x 16 blocks).
+      // For pivot block K: P = T_KK is inverted by one wave (columns in
+      // registers; a non-positive pivot leaves its direction out), then on
+      // the matrix cores R_J = P^-1 T_KJ, T_IJ -= T_IK R_J and
+      // T_IK <- -T_IK P^-1 (I, J != K), and T_KK <- P^-1.
+      const int nb = Mp / 16;
+      for (int kb = 0; kb < nb; ++kb) {
+        const int k0 = kb * 16;
+        if (wave == 0) {
+          double a[16];
 #pragma unroll
-        for (int u = 0; u < kMaxElems; ++u) {
-          const int e = tid + u * kRunThreads;
-          const int i = e < ne ? e / M1 : 0;
-          ij[u] = e < ne ? (i << 16) | (e - i * M1) : -1;
-          v[u] = e < ne ? T[e] : 0.0;
-        }
-        auto publish = [&](int kk) {
-          const int b = kk & 1;
-          const int pe = kk * M1 + kk;
-          double pv = 0.0;
+          for (int i = 0; i < 16; ++i) a[i] = lane < 16 ? T[(size_t)(k0 + i) * ldT + k0 + lane] : 0.0;
 #pragma unroll
-          for (int u = 0; u < kMaxElems; ++u) {
-            if (ij[u] >= 0) {
-              const int i = ij[u] >> 16, j = ij[u] & 0xffff;
-              if (i == kk) rowbuf[b][j] = v[u];
-              if (j == kk) colbuf[b][i] = v[u];
+          for (int k = 0; k < 16; ++k) {
+            const double piv = lane_d(a[k], k);
+            double ip = 0.0;
+            if (piv > 0.0) {
+              ip = __builtin_amdgcn_rcp(piv);
+              ip = fma(ip, fma(-piv, ip, 1.0), ip);
+              ip = fma(ip, fma(-piv, ip, 1.0), ip);
             }
-            if (u == pe / kRunThreads) pv = v[u];
+            const double rj = a[k];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              if (i == k) continue;
+              const double ci = lane_d(a[i], k);
+              a[i] = lane == k ? -a[i] * ip : fma(-ci * ip, rj, a[i]);
+            }
+            a[k] = lane == k ? ip : rj * ip;
           }
-          if (tid == pe % kRunThreads) ipbuf[b] = pv > 0.0 ? 1.0 / pv : 0.0;
-        };
-        publish(0);
+          if (lane < 16)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Pinv[i * 16 + lane] = a[i];
+        }
         __syncthreads();
-        for (int kk = 0; kk < M; ++kk) {
-          const int b = kk & 1;
-          const double ip = ipbuf[b];
+        // row panel R = P^-1 T_K, (16 x Mp; the K block is not used)
+        for (int tj = wave; tj < nb; tj += nwaves) {
+          if (tj == kb) continue;
+          const int j0 = tj * 16;
+          const dbl4 r4 = mfma_tile(16, lane, [&](int i, int q) { return Pinv[i * 16 + q]; },
+                                    [&](int q, int j) { return T[(size_t)(k0 + q) * ldT + j0 + j]; });
 #pragma unroll
-          for (int u = 0; u < kMaxElems; ++u) {
-            if (ij[u] >= 0) {
-              const int i = ij[u] >> 16, j = ij[u] & 0xffff;
-              if (i == kk)
-                v[u] = j == kk ? ip : v[u] * ip;
-              else if (j == kk)
-                v[u] = -v[u] * ip;
-              else
-                v[u] = fma(-colbuf[b][i] * ip, rowbuf[b][j], v[u]);
-            }
-          }
-          if (kk + 1 < M) publish(kk + 1);
-          __syncthreads();
+          for (int r = 0; r < 4; ++r) Rp[(4 * r + (lane >> 4)) * Mp + j0 + (lane & 15)] = r4[r];
         }
+        __syncthreads();
+        // trailing update T_IJ -= T_IK R_J and the new column panel
+        // -T_IK P^-1 (kept aside until every trailing tile has read T_IK)
+        for (int tile = wave; tile < nb * nb; tile += nwaves) {
+          const int ti = tile / nb, tj = tile - ti * nb;
+          if (ti == kb) continue;
+          const int i0 = ti * 16, j0 = tj * 16;
+          if (tj == kb) {
+            const dbl4 c4 = mfma_tile(16, lane, [&](int i, int q) { return T[(size_t)(i0 + i) * ldT + k0 + q]; },
+                                      [&](int q, int j) { return Pinv[q * 16 + j]; });
 #pragma unroll
-        for (int u = 0; u < kMaxElems; ++u)
-          if (ij[u] >= 0 && (ij[u] & 0xffff) == M) xs[ij[u] >> 16] = v[u];
+            for (int r = 0; r < 4; ++r) Cpn[(i0 + 4 * r + (lane >> 4)) * 16 + (lane & 15)] = -c4[r];
+          } else {
+            dbl4 t4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t4[r] = T[(size_t)(i0 + 4 * r + (lane >> 4)) * ldT + j0 + (lane & 15)];
+            const dbl4 u4 = mfma_tile(16, lane, [&](int i, int q) { return -T[(size_t)(i0 + i) * ldT + k0 + q]; },
+                                      [&](int q, int j) { return Rp[q * Mp + j0 + j]; }, t4);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[(size_t)(i0 + 4 * r + (lane >> 4)) * ldT + j0 + (lane & 15)] = u4[r];
+          }
+        }
+        __syncthreads();
+        // write back the panels and the block inverse
+        for (int t = tid; t < 16 * Mp; t += kRunThreads) {
+          const int r = t / Mp, c = t - r * Mp;
+          if (c < k0 || c >= k0 + 16) T[(size_t)(k0 + r) * ldT + c] = Rp[r * Mp + c];
+          else T[(size_t)(k0 + r) * ldT + c] = Pinv[r * 16 + (c - k0)];
+          const int i = t >> 4, q = t & 15;  // column panel: row i, column k0 + q
+          if (i < k0 || i >= k0 + 16) T[(size_t)i * ldT + k0 + q] = Cpn[i * 16 + q];
+        }
+        __syncthreads();
+      }
+      // x = N^-1 g (8 lanes per row)
+      for (int o = tid >> 3; o < M; o += kRunThreads / 8) {
+        const int part = tid & 7;
+        double sx = 0.0;
+        for (int j = part; j < M; j += 8) sx = fma(T[(size_t)o * ldT + j], gb[j], sx);
+        sx = sum8(sx);
+        if (part == 0) xs[o] = sx;
       }
       __syncthreads();
       if (tid < M) {
