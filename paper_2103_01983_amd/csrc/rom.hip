@@ -55,6 +55,14 @@ struct RomDev {
   const float *Phibar, *xbar0;  // [nd][M], [nd]
   const float *ent;             // [nnz][ew]: r0x r0y Gamma~ surrogate-id (Dx_m Dy_m) pairs
   const int *off;               // [ns+1]
+  // point form used by the larger-basis kernel: P = nd + 2 Nc coordinates
+  // (the sampled rows, then x and y of every surrogate), basis rows stored
+  // mode-major pt[m][p] and reference positions p0[p], both FP64; per entry
+  // its target (etg) and surrogate (eid); gt0 the trained Gamma~
+  int P;
+  const double *pt, *p0;
+  const int *etg, *eid;
+  const float *gt0;
   const double *A;              // [Mr][nd]
   // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
   // leading dimension ldc
@@ -690,18 +698,18 @@ struct BigLayout {
   size_t r1, r2, total;  // doubles
 };
 
-__host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, int64_t nnz, int nc_table) {
+__host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, int64_t nnz, int Nc) {
   (void)Mr;
   const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16, Mp = (M + 15) / 16 * 16;
   BigLayout L;
   const size_t tab = (size_t)Mp * (Mp + 1);  // padded tableau, odd row stride
   L.r1 = (size_t)nd * M1 > tab ? (size_t)nd * M1 : tab;
-  const size_t gather = 3 * (size_t)ns + nd + (5 * (size_t)nnz + 1) / 2;
+  const size_t gather = 3 * (size_t)ns + nd + 2 * (size_t)Nc + (5 * (size_t)nnz + 1) / 2;
   const size_t blocks = 16 * (size_t)nd + 16 * (size_t)M1p;
   const size_t inv = 2 * 16 * (size_t)Mp + 256 + Mp;  // row / column panels, block inverse, g
   L.r2 = gather > blocks ? gather : blocks;
   L.r2 = L.r2 > inv ? L.r2 : inv;
-  L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)nc_table + 1) / 2;
+  L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)Nc + 1) / 2;
   return L;
 }
 
@@ -716,23 +724,22 @@ __global__ void __launch_bounds__(kRunThreads)
   const int M = d.M, Mr = d.Mr, nd = d.nd, ns = d.ns, M1 = M + 1, M1p = (M1 + 15) / 16 * 16;
   const int nnz = (int)d.nnz;
   const double hdt = 0.5 * (double)d.dt;
-  const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, gtq ? d.Nc : 0);
+  const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, d.Nc);
   double *R1 = dyn, *R2 = dyn + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
   double *Cp = R1, *T = R1;                      // [C | rbar] (nd x M1), then N (Mp x Mp, stride ldT)
-  double *bt = R2, *xcur = R2 + 3 * ns;          // gather phase
-  float *ct = reinterpret_cast<float *>(xcur + nd);
+  double *bt = R2, *pos = R2 + 3 * ns;           // gather phase: pos[0, nd) are the sampled rows
+  float *ct = reinterpret_cast<float *>(pos + d.P);
   double *Ab = R2, *Gb = R2 + 16 * (size_t)nd;   // product phase
   const int Mp = (M + 15) / 16 * 16, ldT = Mp + 1;
   double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp, *gb = Pinv + 256;  // inversion
-  const float *gt = nullptr;
   xhat += (size_t)blockIdx.x * M;
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
   if (iters) iters += (size_t)blockIdx.x * nsteps;
-  if (gtq) {
-    float *g = reinterpret_cast<float *>(xbar_prev + nd);
-    for (int t = tid; t < d.Nc; t += kRunThreads) g[t] = gtq[(size_t)blockIdx.x * d.Nc + t];
-    gt = g;
+  float *gt = reinterpret_cast<float *>(xbar_prev + nd);  // this query's Gamma~ per surrogate
+  {
+    const float *src = gtq ? gtq + (size_t)blockIdx.x * d.Nc : d.gt0;
+    for (int t = tid; t < d.Nc; t += kRunThreads) gt[t] = src[t];
   }
   if (tid < M) {
     xh[tid] = xhat[tid];
@@ -740,47 +747,80 @@ __global__ void __launch_bounds__(kRunThreads)
   }
   __syncthreads();
 
-  // HyperPair of the paper: per-entry terms, sampled rows, per-target sums.
-  // With res == false only fbar_out and the sampled rows (xbar_out) are kept.
-  auto hyperpair = [&](bool res, double *xbar_out, double *fbar_out) {
-    for (int e = tid; e < nnz; e += kRunThreads) {
-      GatherAcc<false> a;
-      entry_terms_stream(d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
-      ct[e] = a.fx;
-      ct[nnz + e] = a.fy;
-      ct[2 * nnz + e] = a.ba;
-      ct[3 * nnz + e] = a.bb;
-      ct[4 * nnz + e] = a.bc;
+  // positions at xhat in FP64: the sampled rows (p < nd) and the surrogates
+  // (Algorithm "HyperPair" preamble), one thread per coordinate
+  auto positions = [&](int np) {
+    constexpr int kB = 32;  // loads in flight per thread
+    for (int p = tid; p < np; p += kRunThreads) {
+      const double *col = d.pt + p;
+      double x0 = d.p0[p], x1 = 0.0;
+      for (int m0 = 0; m0 < M; m0 += kB) {
+        double v[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) v[u] = m0 + u < M ? col[(size_t)(m0 + u) * d.P] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kB; u += 2) {
+          x0 = fma(v[u], m0 + u < M ? xh[m0 + u] : 0.0, x0);
+          x1 = fma(v[u + 1], m0 + u + 1 < M ? xh[m0 + u + 1] : 0.0, x1);
+        }
+      }
+      pos[p] = x0 + x1;
     }
-    for (int q = tid; q < nd; q += kRunThreads) {
-      double x = d.xbar0[q];
-      const float *ph = d.Phibar + (size_t)q * M;
-      for (int m = 0; m < M; ++m) x += (double)ph[m] * xh[m];
-      xcur[q] = x;
+  };
+
+  // HyperPair of the paper: per-entry terms from the separations (taken in
+  // FP64, evaluated in FP32), per-target sums by groups of 8 lanes.  With
+  // res == false only fbar_out and the sampled rows (xbar_out) are kept.
+  auto hyperpair = [&](bool res, double *xbar_out, double *fbar_out) {
+    positions(d.P);
+    __syncthreads();
+    for (int e = tid; e < nnz; e += kRunThreads) {
+      const int t = d.etg[e], c = d.eid[e];
+      const float rx = (float)(pos[t] - pos[nd + 2 * c]);
+      const float ry = (float)(pos[ns + t] - pos[nd + 2 * c + 1]);
+      const float qq = fmaf(rx, rx, fmaf(ry, ry, d.d2));
+      const float r = qq > 0.f ? 1.0f / qq : 0.f;  // zero separation adds nothing
+      const float g = gt[c] * r, g2 = g * r;
+      const float a2 = (rx + rx) * ry, dd = fmaf(ry, ry, -rx * rx);
+      ct[e] = -ry * g;
+      ct[nnz + e] = rx * g;
+      ct[2 * nnz + e] = g2 * a2;
+      ct[3 * nnz + e] = g2 * (dd - d.d2);
+      ct[4 * nnz + e] = g2 * (dd + d.d2);
     }
     __syncthreads();
-    for (int t = tid; t < ns; t += kRunThreads) {
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
-      for (int e = d.off[t]; e < d.off[t + 1]; ++e) {
-        s0 += ct[e];
-        s1 += ct[nnz + e];
-        s2 += ct[2 * nnz + e];
-        s3 += ct[3 * nnz + e];
-        s4 += ct[4 * nnz + e];
-      }
-      const double Fx = s0 * kInv2PiD, Fy = s1 * kInv2PiD;
-      fbar_out[t] = Fx;
-      fbar_out[ns + t] = Fy;
-      if (res) {
-        Cp[(size_t)t * M1 + M] = (xcur[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
-        Cp[(size_t)(ns + t) * M1 + M] = (xcur[ns + t] - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
-        bt[3 * t] = s2 * kInv2PiD;
-        bt[3 * t + 1] = s3 * kInv2PiD;
-        bt[3 * t + 2] = s4 * kInv2PiD;
+    for (int t0 = 0; t0 < ns; t0 += kRunThreads / 8) {
+      const int t = t0 + (tid >> 3), part = tid & 7;
+      if (t < ns) {  // whole groups of 8 lanes are in or out
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+        for (int e = d.off[t] + part; e < d.off[t + 1]; e += 8) {
+          s0 += ct[e];
+          s1 += ct[nnz + e];
+          s2 += ct[2 * nnz + e];
+          s3 += ct[3 * nnz + e];
+          s4 += ct[4 * nnz + e];
+        }
+        s0 = sum8(s0);
+        s1 = sum8(s1);
+        s2 = sum8(s2);
+        s3 = sum8(s3);
+        s4 = sum8(s4);
+        if (part == 0) {
+          const double Fx = s0 * kInv2PiD, Fy = s1 * kInv2PiD;
+          fbar_out[t] = Fx;
+          fbar_out[ns + t] = Fy;
+          if (res) {
+            Cp[(size_t)t * M1 + M] = (pos[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+            Cp[(size_t)(ns + t) * M1 + M] = (pos[ns + t] - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+            bt[3 * t] = s2 * kInv2PiD;
+            bt[3 * t + 1] = s3 * kInv2PiD;
+            bt[3 * t + 2] = s4 * kInv2PiD;
+          }
+        }
       }
     }
     if (xbar_out)
-      for (int q = tid; q < nd; q += kRunThreads) xbar_out[q] = xcur[q];
+      for (int q = tid; q < nd; q += kRunThreads) xbar_out[q] = pos[q];
     __syncthreads();
   };
 
@@ -793,9 +833,9 @@ __global__ void __launch_bounds__(kRunThreads)
       hyperpair(true, nullptr, fbar);
       // C = Phibar - dt/2 B Phibar
       for (int q = tid; q < nd * M; q += kRunThreads) {
-        const int row = q / M, m = q - row * M;
+        const int m = q / nd, row = q - m * nd;
         const int t = row < ns ? row : row - ns;
-        const double px = d.Phibar[(size_t)t * M + m], py = d.Phibar[(size_t)(ns + t) * M + m];
+        const double px = d.pt[(size_t)m * d.P + t], py = d.pt[(size_t)m * d.P + ns + t];
         const double B00 = bt[3 * t], B01 = bt[3 * t + 1], B10 = bt[3 * t + 2];
         Cp[(size_t)row * M1 + m] = row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py);
       }
@@ -969,11 +1009,11 @@ __global__ void __launch_bounds__(kRunThreads)
     if (tid == 0 && iters) iters[step] = k - 1;
     // previous-step terms: sampled rows at the accepted xhat, velocity of the
     // last HyperPair evaluation
+    __syncthreads();  // the last solve's reads of region 2 are done
+    positions(nd);
+    __syncthreads();
     for (int q = tid; q < nd; q += kRunThreads) {
-      double x = d.xbar0[q];
-      const float *ph = d.Phibar + (size_t)q * M;
-      for (int m = 0; m < M; ++m) x += (double)ph[m] * xh[m];
-      xbar_prev[q] = x;
+      xbar_prev[q] = pos[q];
       fbar_prev[q] = fbar[q];
     }
     __syncthreads();
@@ -1030,7 +1070,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   if (s.jac_mode == PTROM_JAC_EXACT && (s.M > kSmallM || s.Mr > kSmallMr))
     return ctx->fail(PTROM_EINVAL, "the exact Jacobian needs M <= 32 and Mr <= 64");
   const int nd = 2 * s.ns;
-  if (s.Nc < 0 || s.nnz < 0 || s.Nc > kMaxN || s.nnz > (int64_t(1) << 31) - 1)
+  if (s.Nc < 0 || s.nnz < 0 || s.Nc > kMaxN || s.nnz > (int64_t(1) << 31) - 1 ||
+      nd + 2 * s.Nc > (int64_t(1) << 31) - 1)
     return ctx->fail(PTROM_EINVAL, "bad Nc / nnz");
   if (!s.Phibar || !s.xbar0 || !s.off || !s.A || (s.Nc > 0 && (!s.xqt0 || !s.Phit || !s.Gt)) ||
       (s.nnz > 0 && !s.ids))
@@ -1068,6 +1109,27 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
         E[5 + 2 * m] = float(s.Phibar[(size_t)(s.ns + i) * M + m] - s.Phit[(size_t)(2 * c + 1) * M + m]);
       }
     }
+
+  // point form: sampled rows then surrogate coordinates, mode-major FP64
+  const int64_t P = nd + 2 * s.Nc;
+  std::vector<double> pt(size_t(M) * P), p0(P);
+  for (int q = 0; q < nd; ++q) {
+    p0[q] = s.xbar0[q];
+    for (int m = 0; m < M; ++m) pt[(size_t)m * P + q] = s.Phibar[(size_t)q * M + m];
+  }
+  for (int64_t c = 0; c < s.Nc; ++c)
+    for (int k = 0; k < 2; ++k) {
+      p0[nd + 2 * c + k] = s.xqt0[2 * c + k];
+      for (int m = 0; m < M; ++m) pt[(size_t)m * P + nd + 2 * c + k] = s.Phit[(size_t)(2 * c + k) * M + m];
+    }
+  std::vector<int> etg(size_t(s.nnz > 0 ? s.nnz : 1), 0), eid(etg.size(), 0);
+  for (int i = 0; i < s.ns; ++i)
+    for (int64_t e = s.off[i]; e < s.off[i + 1]; ++e) {
+      etg[e] = i;
+      eid[e] = int(s.ids[e]);
+    }
+  std::vector<float> gt0(size_t(s.Nc > 0 ? s.Nc : 1), 0.0f);
+  for (int64_t c = 0; c < s.Nc; ++c) gt0[c] = float(s.Gt[c]);
 
   auto rom = new ptrom_rom();
   rom->ctx = ctx;
@@ -1130,7 +1192,9 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   const size_t bytes[] = {align256(phibar.size() * 4), align256(xbar0.size() * 4), align256(ent.size() * 4),
                           align256(off32.size() * 4), align256(size_t(s.Mr) * nd * 8),
                           align256(nd * 8), align256(nd * 8), align256(nd * 8),
-                          align256(size_t(nd) * ((M + 4) / 4 * 4) * 8)};
+                          align256(size_t(nd) * ((M + 4) / 4 * 4) * 8), align256(pt.size() * 8),
+                          align256(p0.size() * 8), align256(etg.size() * 4), align256(eid.size() * 4),
+                          align256(gt0.size() * 4)};
   constexpr int NB = sizeof(bytes) / sizeof(bytes[0]);
   size_t total = 0;
   for (size_t b : bytes) total += b;
@@ -1147,11 +1211,18 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.Phibar = (float *)ptrs[0]; d.xbar0 = (float *)ptrs[1]; d.ent = (float *)ptrs[2]; d.off = (int *)ptrs[3];
   d.A = (double *)ptrs[4]; d.xbar_prev = (double *)ptrs[5]; d.fbar = (double *)ptrs[6];
   d.fbar_prev = (double *)ptrs[7]; d.C = (double *)ptrs[8];
+  d.P = int(P); d.pt = (double *)ptrs[9]; d.p0 = (double *)ptrs[10]; d.etg = (int *)ptrs[11];
+  d.eid = (int *)ptrs[12]; d.gt0 = (float *)ptrs[13];
   hipError_t e = hipMemcpy(ptrs[0], phibar.data(), phibar.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[1], xbar0.data(), xbar0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[2], ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[3], off32.data(), off32.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[4], s.A, size_t(s.Mr) * nd * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[9], pt.data(), pt.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[10], p0.data(), p0.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[11], etg.data(), etg.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[12], eid.data(), eid.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[13], gt0.data(), gt0.size() * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(rom->buf);
     delete rom;
@@ -1200,7 +1271,7 @@ int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xha
   ptrom_ctx *ctx = rom->ctx;
   const RomDev &d = rom->d;
   if (d.M > kSmallM || d.Mr > kSmallMr) {
-    const BigLayout L = big_layout(d.M, d.Mr, d.nd, d.ns, d.nnz, gtq ? d.Nc : 0);
+    const BigLayout L = big_layout(d.M, d.Mr, d.nd, d.ns, d.nnz, d.Nc);
     const size_t bytes = L.total * sizeof(double);
     if (bytes > rom->max_dyn_lds_big)
       return ctx->fail(PTROM_EINVAL, "basis, sample set and lists too large for one workgroup's LDS");
