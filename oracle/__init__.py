@@ -54,6 +54,7 @@ class _Rom(ctypes.Structure):
         ("Phibar", _dp), ("xbar0", _dp), ("xqt0", _dp), ("Phit", _dp), ("Gt", _dp), ("A", _dp),
         ("off", _i64p), ("ids", _i64p),
         ("delta", ctypes.c_double), ("dt", ctypes.c_double),
+        ("ubar", _dp),
     ]
 
 
@@ -80,6 +81,8 @@ def lib():
         L.or_rk4.argtypes = [i64, _dp, _dp, dbl, dbl, i32]
         L.or_implicit.argtypes = [i64, _dp, _dp, dbl, dbl, i32, i32, dbl, i32, dbl, i32, i32,
                                   ctypes.POINTER(NewtonStats)]
+        L.or_implicit_forced.argtypes = [i64, _dp, _dp, dbl, _dp, dbl, i32, i32, dbl, i32, dbl, i32, i32,
+                                         ctypes.POINTER(NewtonStats)]
         L.or_rk4_adjoint.argtypes = [i64, _dp, _dp, dbl, dbl, i32, _dp, _dp, _dp, _dp, _dp]
         L.or_lstsq.argtypes = [i32, i32, _dp, _dp, _dp]
         L.or_rom_hyperpair.argtypes = [ctypes.POINTER(_Rom), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -211,16 +214,21 @@ BE, TRAPEZOID = 0, 1
 
 
 def implicit(xy, gamma, delta, dt, nsteps, scheme=BE, newton_tol=1e-12, max_newton=50,
-             gmres_tol=1e-14, gmres_restart=40, gmres_maxit=400):
+             gmres_tol=1e-14, gmres_restart=40, gmres_maxit=400, u=None):
     """k=1 implicit linear multistep steps (backward Euler or trapezoid) solved by
-    Newton-GMRES with the exact Jacobian product.  Returns (x, NewtonStats)."""
+    Newton-GMRES with the exact Jacobian product; ``u`` [2N] is an optional
+    background velocity (dx/dt = f(x) + u).  Returns (x, NewtonStats)."""
     n = _n(xy)
     x = np.array(xy, dtype=np.float64, copy=True)
     g, pg = _d(gamma)
+    pu = None
+    if u is not None:
+        ua, pu = _d(u)
+        assert ua.size == 2 * n
     st = NewtonStats()
-    lib().or_implicit(n, x.ctypes.data_as(_dp), pg, float(delta), float(dt), int(nsteps), int(scheme),
-                      float(newton_tol), int(max_newton), float(gmres_tol), int(gmres_restart),
-                      int(gmres_maxit), ctypes.byref(st))
+    lib().or_implicit_forced(n, x.ctypes.data_as(_dp), pg, float(delta), pu, float(dt), int(nsteps), int(scheme),
+                             float(newton_tol), int(max_newton), float(gmres_tol), int(gmres_restart),
+                             int(gmres_maxit), ctypes.byref(st))
     return x, st
 
 
@@ -292,6 +300,8 @@ class Rom:
         r.ids = i("ids", art["ids"] if len(art["ids"]) else np.zeros(1, np.int64))
         r.delta = float(art["delta"])
         r.dt = float(art["dt"])
+        ub = art.get("ubar")
+        r.ubar = d("ubar", np.asarray(ub, dtype=np.float64).reshape(nd)) if ub is not None else None
         self._r = r
 
     def hyperpair(self, xhat, xbar_prev, fbar_prev):

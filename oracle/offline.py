@@ -52,12 +52,13 @@ import oracle
 
 # ----------------------------------------------------------------- Stage 1
 
-def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap):
-    """Columns x^1..x^nsnap of the trapezoid FOM (scheme of the online residual)."""
+def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap, u=None):
+    """Columns x^1..x^nsnap of the trapezoid FOM (scheme of the online
+    residual); ``u`` [2N] an optional background velocity (inflow)."""
     S = np.empty((xy0.size, nsnap))
     x = np.array(xy0, dtype=np.float64)
     for t in range(nsnap):
-        x, st = oracle.implicit(x, gamma, delta, dt, 1, scheme=oracle.TRAPEZOID)
+        x, st = oracle.implicit(x, gamma, delta, dt, 1, scheme=oracle.TRAPEZOID, u=u)
         assert st.nonconverged_steps == 0
         S[:, t] = x
     return S
@@ -252,13 +253,18 @@ def sampled_rows(sample, n):
     return np.concatenate([s, n + s])
 
 
-def rom_artifacts(sample, tree, pc, xy0, Phi, gamma, delta, dt, A=None):
+def rom_artifacts(sample, tree, pc, xy0, Phi, gamma, delta, dt, A=None, u=None):
+    """Online artifacts; with a background velocity ``u`` [2N] its sampled
+    rows become ``ubar``."""
     n = gamma.size
     rows = sampled_rows(sample, n)
     xqt0, Phit, Gt, off, ids, keys = cluster_artifacts(tree, sample, pc, xy0, Phi, gamma)
-    return dict(M=Phi.shape[1], Mr=(A.shape[0] if A is not None else rows.size), sample=np.asarray(sample),
-                Phibar=Phi[rows].copy(), xbar0=np.asarray(xy0)[rows].copy(), xqt0=xqt0, Phit=Phit, Gt=Gt,
-                off=off, ids=ids, A=A, delta=float(delta), dt=float(dt), keys=keys)
+    art = dict(M=Phi.shape[1], Mr=(A.shape[0] if A is not None else rows.size), sample=np.asarray(sample),
+               Phibar=Phi[rows].copy(), xbar0=np.asarray(xy0)[rows].copy(), xqt0=xqt0, Phit=Phit, Gt=Gt,
+               off=off, ids=ids, A=A, delta=float(delta), dt=float(dt), keys=keys)
+    if u is not None:
+        art["ubar"] = np.asarray(u, dtype=np.float64)[rows].copy()
+    return art
 
 
 # ----------------------------------------------------------------- Stage 3
@@ -352,21 +358,23 @@ def reassign_circulation(members, gamma_mu):
     return np.array([float(np.sum(g[np.asarray(m, dtype=np.int64)])) for m in members])
 
 
-def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, jac_mode=0):
+def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100, jac_mode=0, u=None):
     """Stages 1-4 over several training parameters.  ``clouds`` share x^0 and
     delta and differ in Gamma (the parameter).  Snapshots of every training
     point form one snapshot matrix (Stage 1 over the sampled parametric
     points); the clustering weights are the mean |Gamma| over the training
     points; Tier II runs at every training point with its reassigned Gamma~
-    and its residual snapshots are pooled (Stage 3)."""
+    and its residual snapshots are pooled (Stage 3).  ``u`` [2N] is a
+    background velocity shared by every parameter (the mushroom cloud's
+    inflow), or None."""
     x0 = np.asarray(clouds[0].xy, dtype=np.float64)
     d = float(clouds[0].delta)
     n = x0.size // 2
-    S = np.hstack([trapezoid_snapshots(x0, np.asarray(c.gamma, float), d, dt, nsnap) for c in clouds])
+    S = np.hstack([trapezoid_snapshots(x0, np.asarray(c.gamma, float), d, dt, nsnap, u=u) for c in clouds])
     Phi, sigma = pod(S, M)
     tree = QuadTree(weighted_points(Phi, sigma), depth)
     wgt = np.mean([np.abs(np.asarray(c.gamma, float)) for c in clouds], axis=0)
-    full = rom_artifacts(np.arange(n), tree, pc, x0, Phi, wgt, d, dt)
+    full = rom_artifacts(np.arange(n), tree, pc, x0, Phi, wgt, d, dt, u=u)
     mem_full = surrogate_members(tree, full["keys"])
     R, t2 = [], []
     for c in clouds:
@@ -379,7 +387,7 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
     Phi_r = U[:, :Mr].copy()
     sample = greedy_sample(Phi_r, ns)
     A = gappy_operator(Phi_r, sample)
-    art = rom_artifacts(sample, tree, pc, x0, Phi, wgt, d, dt, A=A)
+    art = rom_artifacts(sample, tree, pc, x0, Phi, wgt, d, dt, A=A, u=u)
     art["members"] = surrogate_members(tree, art["keys"])
     return art, dict(S=S, Phi=Phi, sigma=sigma, tree=tree, Phi_r=Phi_r, sigma_r=sr[:Mr].copy(), tier2=t2,
                      weights=wgt)

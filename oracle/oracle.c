@@ -364,10 +364,13 @@ typedef struct {
 } or_newton_stats;
 
 /* scheme 0 = backward Euler, 1 = trapezoid.  Newton stops when
- * |r(xi)| <= newton_tol |r(x_prev)|. */
-int or_implicit(int64_t n, double *xy, const double *gam, double delta, double dt, int nsteps,
-                int scheme, double newton_tol, int max_newton, double gmres_tol, int gmres_restart,
-                int gmres_maxit, or_newton_stats *st) {
+ * |r(xi)| <= newton_tol |r(x_prev)|.  u [2n] (may be NULL) is a background
+ * velocity added to every body's right-hand side, dx_i/dt = f_i(x) + u_i:
+ * the inflow of the mushroom-cloud experiment (parametric results).  It does
+ * not depend on x, so the Jacobian is unchanged. */
+int or_implicit_forced(int64_t n, double *xy, const double *gam, double delta, const double *u, double dt,
+                       int nsteps, int scheme, double newton_tol, int max_newton, double gmres_tol,
+                       int gmres_restart, int gmres_maxit, or_newton_stats *st) {
   const int64_t m = 2 * n;
   const double beta0 = (scheme == 0) ? 1.0 : 0.5, beta1 = (scheme == 0) ? 0.0 : 0.5;
   double *xprev = (double *)malloc(sizeof(double) * m), *fprev = (double *)malloc(sizeof(double) * m);
@@ -377,10 +380,14 @@ int or_implicit(int64_t n, double *xy, const double *gam, double delta, double d
   for (int step = 0; step < nsteps; ++step) {
     memcpy(xprev, xy, sizeof(double) * m);
     or_velocity(n, xprev, gam, delta, fprev);
+    if (u)
+      for (int64_t q = 0; q < m; ++q) fprev[q] += u[q];
     double r0 = -1.0, rn = 0.0;
     int it = 0;
     for (;; ++it) {
       or_velocity(n, xy, gam, delta, f);
+      if (u)
+        for (int64_t q = 0; q < m; ++q) f[q] += u[q];
       for (int64_t q = 0; q < m; ++q)
         r[q] = xy[q] - xprev[q] - dt * (beta0 * f[q] + beta1 * fprev[q]);
       rn = sqrt(dot(m, r, r));
@@ -402,6 +409,13 @@ int or_implicit(int64_t n, double *xy, const double *gam, double delta, double d
   }
   free(xprev); free(fprev); free(f); free(r); free(d); free(tmp);
   return st->nonconverged_steps ? 1 : 0;
+}
+
+int or_implicit(int64_t n, double *xy, const double *gam, double delta, double dt, int nsteps,
+                int scheme, double newton_tol, int max_newton, double gmres_tol, int gmres_restart,
+                int gmres_maxit, or_newton_stats *st) {
+  return or_implicit_forced(n, xy, gam, delta, NULL, dt, nsteps, scheme, newton_tol, max_newton, gmres_tol,
+                            gmres_restart, gmres_maxit, st);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -493,11 +507,13 @@ typedef struct {
   const double *Phibar, *xbar0, *xqt0, *Phit, *Gt, *A;
   const int64_t *off, *ids;
   double delta, dt;
+  const double *ubar; /* [nd] background velocity at the sampled rows, or NULL */
 } or_rom;
 
 /* One HyperPair evaluation at generalized coordinates xhat (source clustering
  * with the Biot-Savart kernel of the governing equations).
- * Outputs: xbar[nd] (sampled positions), fbar[nd] (sampled velocities),
+ * Outputs: xbar[nd] (sampled positions), fbar[nd] (sampled velocities, with
+ * the background velocity ubar when there is one),
  * rbar[nd] (trapezoid residual rows), C[nd][M] (residual Jacobian times Phi). */
 static void rom_hyperpair(const or_rom *R, const double *xhat, const double *xbar_prev,
                           const double *fbar_prev, double *xbar, double *fbar, double *rbar,
@@ -544,6 +560,10 @@ static void rom_hyperpair(const or_rom *R, const double *xhat, const double *xba
           E[q] += g * (h[0] * px + h[1] * py);
           E[M + q] += g * (h[2] * px + h[3] * py);
         }
+    }
+    if (R->ubar) {
+      fx += R->ubar[i];
+      fy += R->ubar[ns + i];
     }
     fbar[i] = fx;
     fbar[ns + i] = fy;

@@ -109,6 +109,25 @@ def vortex_pair(mu, n=500, half=52.93, delta=0.2121):
     return Cloud(_soa(s, s.copy()), g, float(delta), dict(kind="vortex_pair", mu=tuple(float(m) for m in mu)))
 
 
+def mushroom_cloud(mu, n=500, half=37.43, y0=-10.0, delta=0.15):
+    """Mushroom-cloud parametric study: n bodies on the line y = y0 from
+    x = -half to x = half, Gamma = 0.01 except the end bodies, which carry
+    mu = (Gamma_1, Gamma_N) of opposite signs; core delta (the initial
+    spacing).  The inflow is ``mushroom_inflow(n)``."""
+    g = np.full(n, 0.01)
+    g[0], g[-1] = float(mu[0]), float(mu[1])
+    return Cloud(_soa(np.linspace(-half, half, n), np.full(n, float(y0))), g, float(delta),
+                 dict(kind="mushroom_cloud", mu=tuple(float(m) for m in mu)))
+
+
+def mushroom_inflow(n, amp=5.0, radius=1.125, base=0.5):
+    """Background velocity of the mushroom cloud, SoA [2n]: zero along x and
+    a semicircle profile amp * sqrt(radius^2 - s^2) + base along y, with s
+    running linearly from -1 to 1 over the bodies."""
+    s = np.linspace(-1.0, 1.0, n)
+    return np.concatenate([np.zeros(n), amp * np.sqrt(radius * radius - s * s) + base])
+
+
 def latin_hypercube(k, lo, hi, seed):
     """k points of a Latin hypercube in the box [lo, hi]^2 (one per row and
     column stratum, uniform inside its cell)."""

@@ -289,3 +289,83 @@ def test_parametric_training_small():
             S = ex["S"][:, :steps]
             err = np.linalg.norm(rec - S) / np.linalg.norm(S - x0[:, None])
             assert err < 0.05, err
+
+
+# ---------------------------------------------------------------- background velocity (inflow)
+
+@pytest.mark.parametrize("scheme", [oracle.BE, oracle.TRAPEZOID])
+def test_uniform_background_velocity_translates_the_fom(scheme):
+    # The kernel sees only differences of positions, so a velocity U common
+    # to every body carries the unforced solution along: x_U(t) = x(t) + U t.
+    cl = W.gaussian_patch(40, seed=7, delta=0.05)
+    g = cl.gamma * 40
+    U = np.concatenate([np.full(40, 0.7), np.full(40, -0.3)])
+    dt, k = 2e-3, 15
+    x0, st0 = oracle.implicit(cl.xy, g, cl.delta, dt, k, scheme=scheme)
+    assert st0.nonconverged_steps == 0
+    xu, st = oracle.implicit(cl.xy, g, cl.delta, dt, k, scheme=scheme, u=U)
+    assert st.nonconverged_steps == 0
+    np.testing.assert_allclose(xu, x0 + U * dt * k, rtol=0, atol=1e-12)
+
+
+def test_background_velocity_alone_moves_bodies_linearly():
+    # Gamma = 0: dx/dt = u exactly, which both schemes integrate without error.
+    n = 30
+    xy = W.uniform_disk(n, seed=2)[1]
+    u = W.mushroom_inflow(n)
+    for scheme in (oracle.BE, oracle.TRAPEZOID):
+        x, _ = oracle.implicit(xy, np.zeros(n), 0.1, 5e-3, 40, scheme=scheme, u=u)
+        np.testing.assert_allclose(x, xy + u * 0.2, rtol=0, atol=1e-13)
+
+
+def test_mushroom_inflow_profile():
+    u = W.mushroom_inflow(5)
+    np.testing.assert_array_equal(u[:5], 0.0)
+    # s = -1, -0.5, 0, 0.5, 1: 5 sqrt(1.125^2 - s^2) + 0.5
+    want = [5 * np.sqrt(1.265625 - s * s) + 0.5 for s in (-1.0, -0.5, 0.0, 0.5, 1.0)]
+    np.testing.assert_allclose(u[5:], want, rtol=1e-15)
+    np.testing.assert_allclose(u[7], 6.125, rtol=1e-15)
+
+
+def test_full_rank_lspg_reproduces_forced_fom():
+    # The full-rank reproduction pin with a non-uniform background velocity:
+    # a dropped or mis-signed inflow term in HyperPair's residual rows breaks
+    # the zero-residual reproduction of the forced trapezoid FOM.
+    n = 48
+    cl = W.gaussian_patch(n, seed=3, delta=0.05)
+    g = cl.gamma * n
+    u = 0.2 * W.mushroom_inflow(n)
+    dt, T = 2e-3, 6
+    S = off.trapezoid_snapshots(cl.xy, g, cl.delta, dt, T, u=u)
+    Phi, sig = off.pod(S, T, x0=cl.xy)
+    tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+    art = off.rom_artifacts(np.arange(n), tree, np.inf, cl.xy, Phi, g, cl.delta, dt, u=u)
+    out = oracle.Rom(art, jac_mode=1).run(T, tol=1e-13, max_iter=30)
+    assert out["status"] == 0
+    rec = cl.xy[:, None] + Phi @ out["hist"].T
+    np.testing.assert_allclose(rec, S, rtol=0, atol=1e-9)
+    # the same basis without the inflow in HyperPair misses the forced states
+    art0 = dict(art)
+    del art0["ubar"]
+    out0 = oracle.Rom(art0, jac_mode=1).run(T, tol=1e-13, max_iter=30)
+    rec0 = cl.xy[:, None] + Phi @ out0["hist"].T
+    assert np.abs(rec0 - S).max() > 1e-4
+
+
+def test_hyperpair_velocity_includes_the_background(small_problem):
+    cl, S, Phi, sig, tree = small_problem
+    g = cl.gamma
+    n = g.size
+    u = W.mushroom_inflow(n)
+    sample = np.array([1, 5, 9])
+    a0 = off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, g, cl.delta, 1e-3)
+    a1 = off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, g, cl.delta, 1e-3, u=u)
+    xh = np.linspace(-0.1, 0.2, Phi.shape[1])
+    z = np.zeros(6)
+    xb0, fb0, rb0, C0 = oracle.Rom(a0).hyperpair(xh, z, z)
+    xb1, fb1, rb1, C1 = oracle.Rom(a1).hyperpair(xh, z, z)
+    rows = np.concatenate([sample, n + sample])
+    np.testing.assert_array_equal(xb1, xb0)
+    np.testing.assert_allclose(fb1, fb0 + u[rows], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(rb1, rb0 - 0.5e-3 * u[rows], rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(C1, C0)
