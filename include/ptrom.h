@@ -163,6 +163,14 @@ int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, flo
                    float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
                    ptrom_newton_stats *stats, ptrom_stream stream);
 
+/* Same with a background velocity uinf [2N] (device, SoA; may be NULL) added
+ * to every body's right-hand side, dx_i/dt = f_i(x) + uinf_i: the inflow
+ * condition of the mushroom-cloud parametric experiment.  It enters the
+ * residual as - dt (beta0 + beta1) uinf; the Jacobian is unchanged. */
+int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
+                          const float *uinf, float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
+                          ptrom_newton_stats *stats, ptrom_stream stream);
+
 /* ------------------------------------------------------------------------
  * Batched parametric instances: nb independent systems in one persistent
  * launch per velocity evaluation.
@@ -223,11 +231,15 @@ typedef struct {
   double alpha;         /* Gauss-Newton step length (the paper uses 1) */
   int32_t max_iter;     /* Gauss-Newton iterations per step (the paper caps at 100) */
   int32_t pad;
+  const double *ubar;   /* [nd] background velocity at the sampled rows (the
+                           mushroom cloud's inflow), or NULL for none; it is
+                           part of the sampled velocity fbar and so of the
+                           trapezoid residual rows */
 } ptrom_rom_desc;
 
 /* Copy the artifacts to the device (surrogate and sampled rows as FP32 for
  * the gather, A as FP64 for the least-squares solve).  Requires
- * 1 <= M <= 96, M <= Mr <= 256, 1 <= ns <= 2^20, ids in [0, Nc); the exact
+ * 1 <= M <= 112, M <= Mr <= 256, 1 <= ns <= 2^20, ids in [0, Nc); the exact
  * Jacobian needs M <= 32 and Mr <= 64.  Bases beyond 32 / 64 take a blocked
  * path whose per-query arrays must fit one workgroup's LDS (EINVAL from the
  * run calls otherwise). */

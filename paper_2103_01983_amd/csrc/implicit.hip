@@ -22,12 +22,12 @@ __global__ void add_kernel(int64_t m, float *__restrict__ out, const float *__re
   if (q < m) out[q] = a[q] + b[q];
 }
 
-// r = D - dt (b0 f + b1 fp)
+// r = D - dt (b0 f + b1 fp) - dt (b0 + b1) u, u (background velocity) may be null
 __global__ void residual_kernel(int64_t m, float *__restrict__ r, const float *__restrict__ D,
                                 const float *__restrict__ f, const float *__restrict__ fp, float dtb0,
-                                float dtb1) {
+                                float dtb1, const float *__restrict__ u, float dtu) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < m) r[q] = D[q] - (dtb0 * f[q] + dtb1 * fp[q]);
+  if (q < m) r[q] = D[q] - (dtb0 * f[q] + dtb1 * fp[q] + (u ? dtu * u[q] : 0.0f));
 }
 
 constexpr int kDotParts = 64;
@@ -205,9 +205,10 @@ struct Solver {
 
 }  // namespace
 
-extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
-                              float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
-                              ptrom_newton_stats *stats, ptrom_stream stream) {
+extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
+                                     const float *uinf, float dt, int nsteps, int scheme,
+                                     const ptrom_newton_opts *opts, ptrom_newton_stats *stats,
+                                     ptrom_stream stream) {
   if (!ctx) return PTROM_EINVAL;
   ctx->err.clear();
   if (n < 1 || n > kMaxN) return ctx->fail(PTROM_EINVAL, "n must be in [1, 2^30]");
@@ -259,7 +260,8 @@ extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float 
         e = launch_pair(OP_VEL, vcfg, ctx->num_cus, n, xi, gamma, nullptr, delta, f, nullptr, pws, pwsf, st);
         if (e != hipSuccess) return ctx->hip_fail(e, "velocity");
       }
-      hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dt * b0, dt * b1);
+      hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dt * b0, dt * b1, uinf,
+                         dt * (b0 + b1));
       if (int rc = S.norm(r, &rn)) return rc;
       if (r0 < 0.0) r0 = rn;
       if (rn <= o.newton_tol * r0 || r0 == 0.0) break;
@@ -282,4 +284,10 @@ extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float 
   PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
   if (stats) *stats = stl;
   return stl.nonconverged_steps ? PTROM_ENOCONV : PTROM_OK;
+}
+
+extern "C" int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
+                              float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
+                              ptrom_newton_stats *stats, ptrom_stream stream) {
+  return ptrom_implicit_forced(ctx, n, xy, gamma, delta, nullptr, dt, nsteps, scheme, opts, stats, stream);
 }

@@ -42,7 +42,7 @@ namespace {
 // ones (paper Jacobian) the blocked path, up to kMaxM / kMaxMr.
 constexpr int kSmallM = 32;
 constexpr int kSmallMr = 64;
-constexpr int kMaxM = 96;
+constexpr int kMaxM = 112;
 constexpr int kMaxMr = 256;
 constexpr int kRunThreads = 512;  // 8 waves: up to 256 VGPRs per lane
 constexpr double kInv2PiD = 0.15915494309189533576888376337251;
@@ -60,6 +60,7 @@ struct RomDev {
   // mode-major pt[m][p] and reference positions p0[p], both FP64; per entry
   // its target (etg) and surrogate (eid); gt0 the trained Gamma~
   int P;
+  const double *ubar;  // [nd] background velocity at the sampled rows (zeros without inflow)
   const double *pt, *p0;
   const int *etg, *eid;
   const float *gt0;
@@ -277,7 +278,8 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
       entry_terms<EXACT>(v, d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
     }
   }
-  const double Fx = gsum(a.fx, G) * kInv2PiD, Fy = gsum(a.fy, G) * kInv2PiD;
+  const double Fx = gsum(a.fx, G) * kInv2PiD + (valid ? d.ubar[t] : 0.0);
+  const double Fy = gsum(a.fy, G) * kInv2PiD + (valid ? d.ubar[ns + t] : 0.0);
   const double hdt = 0.5 * (double)d.dt;
   if (valid && gl == 0) {
     double tx, ty;
@@ -473,7 +475,7 @@ __global__ void __launch_bounds__(kRunThreads)
         // per-target sums (one thread per target for short lists, else
         // groups of G lanes), residual rows and the 2x2 blocks
         auto finish = [&](int t, float s0, float s1, float s2, float s3, float s4) {
-          const double Fx = s0 * kInv2PiD, Fy = s1 * kInv2PiD;
+          const double Fx = s0 * kInv2PiD + d.ubar[t], Fy = s1 * kInv2PiD + d.ubar[ns + t];
           fbar[t] = Fx;
           fbar[ns + t] = Fy;
           Cp[(size_t)t * ldc + M] = (xcur[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
@@ -675,11 +677,12 @@ __global__ void __launch_bounds__(kRunThreads)
 
 // ----------------------------------------------------------- larger bases
 
-// Bases with M > 32 or M_r > 64 (paper Jacobian; M <= 96, M_r <= 256).  One
-// workgroup per query;
-// per Gauss-Newton iteration:
-//   gather    one thread per list entry (rows streamed from memory) into
-//             per-entry terms in LDS, per-target sums, then [C | rbar] in LDS;
+// Bases with M > 32 or M_r > 64 (paper Jacobian; M <= 112, M_r <= 256).  One
+// workgroup per query; per Gauss-Newton iteration:
+//   gather    the sampled-row and surrogate positions at xhat in FP64 (one
+//             thread per coordinate over a mode-major basis), then each
+//             target's list by a group of 8 lanes: velocity, residual rows
+//             rbar and the 2x2 blocks; C = (I - dt/2 B) Phibar in FP32;
 //   normal    N' = G'^T G' with G' = A [C | rbar] accumulated over 16-row
 //   matrix    blocks of A: the block is staged in LDS, G'_blk = A_blk [C |
 //             rbar] and N' += G'_blk^T G'_blk run on the FP64 matrix cores,
@@ -689,10 +692,15 @@ __global__ void __launch_bounds__(kRunThreads)
 //             (a non-positive pivot leaves its direction out), the row and
 //             column panels and the rank-16 trailing update run on the FP64
 //             matrix cores; then x = N^-1 g with g = G^T b.
-// LDS: region 1 holds [C | rbar] and then N; region 2 holds the per-entry
-// terms during the gather, the A / G' row blocks during the product and the
-// panels during the inversion.
-constexpr int kMaxTiles = 4;   // lower-triangle tiles of N' per wave (M + 1 <= 112: 28 tiles)
+// C enters only the step direction, never the residual, so its FP32 rounding
+// leaves the Gauss-Newton fixed point where it is.
+// LDS: region 1 holds C and rbar and then N; region 2 holds the positions
+// during the gather, the A / G' row blocks during the product and the panels
+// during the inversion; the tail holds the previous-step rows, this query's
+// Gamma~ and the entries' surrogate ids.
+constexpr int kMaxTiles = 5;  // lower-triangle tiles of N' per wave
+static_assert(((kMaxM + 16) / 16) * ((kMaxM + 16) / 16 + 1) / 2 <= kMaxTiles * (kRunThreads / 64),
+              "every lower-triangle tile of N' needs an owner");
 
 struct BigLayout {
   size_t r1, r2, total;  // doubles
@@ -703,21 +711,21 @@ __host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, i
   const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16, Mp = (M + 15) / 16 * 16;
   BigLayout L;
   const size_t tab = (size_t)Mp * (Mp + 1);  // padded tableau, odd row stride
-  L.r1 = (size_t)nd * M1 > tab ? (size_t)nd * M1 : tab;
-  const size_t gather = 3 * (size_t)ns + nd + 2 * (size_t)Nc + (5 * (size_t)nnz + 1) / 2;
+  const size_t crb = ((size_t)nd * M + 1) / 2 + nd;  // FP32 C and FP64 rbar
+  L.r1 = crb > tab ? crb : tab;
+  const size_t gather = 3 * (size_t)ns + nd + 2 * (size_t)Nc;
   const size_t blocks = 16 * (size_t)nd + 16 * (size_t)M1p;
   const size_t inv = 2 * 16 * (size_t)Mp + 256 + Mp;  // row / column panels, block inverse, g
   L.r2 = gather > blocks ? gather : blocks;
   L.r2 = L.r2 > inv ? L.r2 : inv;
-  L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)Nc + 1) / 2;
+  L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)Nc + 1) / 2 + ((size_t)nnz + 1) / 2;
   return L;
 }
 
 __global__ void __launch_bounds__(kRunThreads)
     rom_run_large_kernel(RomDev d, int nsteps, const float *__restrict__ gtq, double *__restrict__ xhat,
                          double *__restrict__ hist, int *__restrict__ iters) {
-  __shared__ double xh[kMaxM], xs[kMaxM];
-  __shared__ float xf[kMaxM];
+  __shared__ double xh[kMaxM + 32], xs[kMaxM];  // xh is zero beyond M
   __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
@@ -727,9 +735,10 @@ __global__ void __launch_bounds__(kRunThreads)
   const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, d.Nc);
   double *R1 = dyn, *R2 = dyn + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
-  double *Cp = R1, *T = R1;                      // [C | rbar] (nd x M1), then N (Mp x Mp, stride ldT)
+  // region 1: C (nd x M, FP32) and rbar (nd, FP64), then N (Mp x Mp, stride ldT)
+  float *Cf = reinterpret_cast<float *>(R1);
+  double *rres = R1 + ((size_t)nd * M + 1) / 2, *T = R1;
   double *bt = R2, *pos = R2 + 3 * ns;           // gather phase: pos[0, nd) are the sampled rows
-  float *ct = reinterpret_cast<float *>(pos + d.P);
   double *Ab = R2, *Gb = R2 + 16 * (size_t)nd;   // product phase
   const int Mp = (M + 15) / 16 * 16, ldT = Mp + 1;
   double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp, *gb = Pinv + 256;  // inversion
@@ -737,14 +746,13 @@ __global__ void __launch_bounds__(kRunThreads)
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
   if (iters) iters += (size_t)blockIdx.x * nsteps;
   float *gt = reinterpret_cast<float *>(xbar_prev + nd);  // this query's Gamma~ per surrogate
+  int *eid = reinterpret_cast<int *>(xbar_prev + nd + (d.Nc + 1) / 2);  // surrogate of each entry
   {
     const float *src = gtq ? gtq + (size_t)blockIdx.x * d.Nc : d.gt0;
     for (int t = tid; t < d.Nc; t += kRunThreads) gt[t] = src[t];
+    for (int e = tid; e < nnz; e += kRunThreads) eid[e] = d.eid[e];
   }
-  if (tid < M) {
-    xh[tid] = xhat[tid];
-    xf[tid] = (float)xhat[tid];
-  }
+  for (int m = tid; m < kMaxM + 32; m += kRunThreads) xh[m] = m < M ? xhat[m] : 0.0;
   __syncthreads();
 
   // positions at xhat in FP64: the sampled rows (p < nd) and the surrogates
@@ -760,45 +768,40 @@ __global__ void __launch_bounds__(kRunThreads)
         for (int u = 0; u < kB; ++u) v[u] = m0 + u < M ? col[(size_t)(m0 + u) * d.P] : 0.0;
 #pragma unroll
         for (int u = 0; u < kB; u += 2) {
-          x0 = fma(v[u], m0 + u < M ? xh[m0 + u] : 0.0, x0);
-          x1 = fma(v[u + 1], m0 + u + 1 < M ? xh[m0 + u + 1] : 0.0, x1);
+          x0 = fma(v[u], xh[m0 + u], x0);
+          x1 = fma(v[u + 1], xh[m0 + u + 1], x1);
         }
       }
       pos[p] = x0 + x1;
     }
   };
 
-  // HyperPair of the paper: per-entry terms from the separations (taken in
-  // FP64, evaluated in FP32), per-target sums by groups of 8 lanes.  With
-  // res == false only fbar_out and the sampled rows (xbar_out) are kept.
+  // HyperPair of the paper: each target's list is taken by a group of 8
+  // lanes; the separations are formed in FP64 and the pair terms evaluated
+  // in FP32, summed in FP64.  With res == false only fbar_out and the
+  // sampled rows (xbar_out) are kept.
   auto hyperpair = [&](bool res, double *xbar_out, double *fbar_out) {
     positions(d.P);
-    __syncthreads();
-    for (int e = tid; e < nnz; e += kRunThreads) {
-      const int t = d.etg[e], c = d.eid[e];
-      const float rx = (float)(pos[t] - pos[nd + 2 * c]);
-      const float ry = (float)(pos[ns + t] - pos[nd + 2 * c + 1]);
-      const float qq = fmaf(rx, rx, fmaf(ry, ry, d.d2));
-      const float r = qq > 0.f ? 1.0f / qq : 0.f;  // zero separation adds nothing
-      const float g = gt[c] * r, g2 = g * r;
-      const float a2 = (rx + rx) * ry, dd = fmaf(ry, ry, -rx * rx);
-      ct[e] = -ry * g;
-      ct[nnz + e] = rx * g;
-      ct[2 * nnz + e] = g2 * a2;
-      ct[3 * nnz + e] = g2 * (dd - d.d2);
-      ct[4 * nnz + e] = g2 * (dd + d.d2);
-    }
     __syncthreads();
     for (int t0 = 0; t0 < ns; t0 += kRunThreads / 8) {
       const int t = t0 + (tid >> 3), part = tid & 7;
       if (t < ns) {  // whole groups of 8 lanes are in or out
+        const double tx = pos[t], ty = pos[ns + t];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-        for (int e = d.off[t] + part; e < d.off[t + 1]; e += 8) {
-          s0 += ct[e];
-          s1 += ct[nnz + e];
-          s2 += ct[2 * nnz + e];
-          s3 += ct[3 * nnz + e];
-          s4 += ct[4 * nnz + e];
+        const int e1 = d.off[t + 1];
+        for (int e = d.off[t] + part; e < e1; e += 8) {
+          const int c = eid[e];
+          const float rx = (float)(tx - pos[nd + 2 * c]);
+          const float ry = (float)(ty - pos[nd + 2 * c + 1]);
+          const float qq = fmaf(rx, rx, fmaf(ry, ry, d.d2));
+          const float r = qq > 0.f ? 1.0f / qq : 0.f;  // zero separation adds nothing
+          const float g = gt[c] * r, g2 = g * r;
+          const float a2 = (rx + rx) * ry, dd = fmaf(ry, ry, -rx * rx);
+          s0 += -ry * g;
+          s1 += rx * g;
+          s2 += g2 * a2;
+          s3 += g2 * (dd - d.d2);
+          s4 += g2 * (dd + d.d2);
         }
         s0 = sum8(s0);
         s1 = sum8(s1);
@@ -806,12 +809,12 @@ __global__ void __launch_bounds__(kRunThreads)
         s3 = sum8(s3);
         s4 = sum8(s4);
         if (part == 0) {
-          const double Fx = s0 * kInv2PiD, Fy = s1 * kInv2PiD;
+          const double Fx = s0 * kInv2PiD + d.ubar[t], Fy = s1 * kInv2PiD + d.ubar[ns + t];
           fbar_out[t] = Fx;
           fbar_out[ns + t] = Fy;
           if (res) {
-            Cp[(size_t)t * M1 + M] = (pos[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
-            Cp[(size_t)(ns + t) * M1 + M] = (pos[ns + t] - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+            rres[t] = (tx - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+            rres[ns + t] = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
             bt[3 * t] = s2 * kInv2PiD;
             bt[3 * t + 1] = s3 * kInv2PiD;
             bt[3 * t + 2] = s4 * kInv2PiD;
@@ -837,7 +840,7 @@ __global__ void __launch_bounds__(kRunThreads)
         const int t = row < ns ? row : row - ns;
         const double px = d.pt[(size_t)m * d.P + t], py = d.pt[(size_t)m * d.P + ns + t];
         const double B00 = bt[3 * t], B01 = bt[3 * t + 1], B10 = bt[3 * t + 2];
-        Cp[(size_t)row * M1 + m] = row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py);
+        Cf[(size_t)row * M + m] = (float)(row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py));
       }
       // N' = G'^T G' over 16-row blocks of A (the gather's LDS is free now)
       dbl4 acc[kMaxTiles];
@@ -853,7 +856,10 @@ __global__ void __launch_bounds__(kRunThreads)
         for (int tj = wave; tj < tcn; tj += nwaves) {
           const int j0 = tj * 16;
           const dbl4 g = mfma_tile(nd, lane, [&](int i, int q) { return Ab[(size_t)i * nd + q]; },
-                                   [&](int q, int j) { return j0 + j < M1 ? Cp[(size_t)q * M1 + j0 + j] : 0.0; });
+                                   [&](int q, int j) {
+                                     const int c = j0 + j;
+                                     return c < M ? (double)Cf[(size_t)q * M + c] : (c == M ? rres[q] : 0.0);
+                                   });
 #pragma unroll
           for (int r = 0; r < 4; ++r) Gb[(4 * r + (lane >> 4)) * M1p + j0 + (lane & 15)] = g[r];
         }
@@ -870,7 +876,7 @@ __global__ void __launch_bounds__(kRunThreads)
           }
         }
       }
-      __syncthreads();  // [C | rbar] is dead: the tableau takes region 1
+      __syncthreads();  // C and rbar are dead: N takes region 1
       // N = G^T G into the padded tableau T (Mp x Mp, row stride ldT; the
       // padding is the identity), g = G^T b into gb
       for (int t = tid; t < Mp * Mp; t += kRunThreads) {
@@ -990,10 +996,7 @@ __global__ void __launch_bounds__(kRunThreads)
         if (part == 0) xs[o] = sx;
       }
       __syncthreads();
-      if (tid < M) {
-        xh[tid] -= d.alpha * xs[tid];
-        xf[tid] = (float)xh[tid];
-      }
+      if (tid < M) xh[tid] -= d.alpha * xs[tid];
       if (tid == 0) {
         const double gn = s_gn;
         if (k == 1) s_g1 = gn;
@@ -1066,7 +1069,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   if (!desc || !out) return ctx->fail(PTROM_EINVAL, "NULL argument");
   const ptrom_rom_desc &s = *desc;
   if (s.M < 1 || s.M > kMaxM || s.Mr < s.M || s.Mr > kMaxMr || s.ns < 1 || s.ns > (1 << 20))
-    return ctx->fail(PTROM_EINVAL, "need 1 <= M <= 96, M <= Mr <= 256, 1 <= ns <= 2^20");
+    return ctx->fail(PTROM_EINVAL, "need 1 <= M <= 112, M <= Mr <= 256, 1 <= ns <= 2^20");
   if (s.jac_mode == PTROM_JAC_EXACT && (s.M > kSmallM || s.Mr > kSmallMr))
     return ctx->fail(PTROM_EINVAL, "the exact Jacobian needs M <= 32 and Mr <= 64");
   const int nd = 2 * s.ns;
@@ -1128,6 +1131,9 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       etg[e] = i;
       eid[e] = int(s.ids[e]);
     }
+  std::vector<double> ubar(nd, 0.0);
+  if (s.ubar)
+    for (int q = 0; q < nd; ++q) ubar[q] = s.ubar[q];
   std::vector<float> gt0(size_t(s.Nc > 0 ? s.Nc : 1), 0.0f);
   for (int64_t c = 0; c < s.Nc; ++c) gt0[c] = float(s.Gt[c]);
 
@@ -1194,7 +1200,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
                           align256(nd * 8), align256(nd * 8), align256(nd * 8),
                           align256(size_t(nd) * ((M + 4) / 4 * 4) * 8), align256(pt.size() * 8),
                           align256(p0.size() * 8), align256(etg.size() * 4), align256(eid.size() * 4),
-                          align256(gt0.size() * 4)};
+                          align256(gt0.size() * 4), align256(ubar.size() * 8)};
   constexpr int NB = sizeof(bytes) / sizeof(bytes[0]);
   size_t total = 0;
   for (size_t b : bytes) total += b;
@@ -1212,7 +1218,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.A = (double *)ptrs[4]; d.xbar_prev = (double *)ptrs[5]; d.fbar = (double *)ptrs[6];
   d.fbar_prev = (double *)ptrs[7]; d.C = (double *)ptrs[8];
   d.P = int(P); d.pt = (double *)ptrs[9]; d.p0 = (double *)ptrs[10]; d.etg = (int *)ptrs[11];
-  d.eid = (int *)ptrs[12]; d.gt0 = (float *)ptrs[13];
+  d.eid = (int *)ptrs[12]; d.gt0 = (float *)ptrs[13]; d.ubar = (double *)ptrs[14];
   hipError_t e = hipMemcpy(ptrs[0], phibar.data(), phibar.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[1], xbar0.data(), xbar0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[2], ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
@@ -1223,6 +1229,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   if (e == hipSuccess) e = hipMemcpy(ptrs[11], etg.data(), etg.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[12], eid.data(), eid.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[13], gt0.data(), gt0.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[14], ubar.data(), ubar.size() * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(rom->buf);
     delete rom;

@@ -117,25 +117,44 @@ def run(n, case=1, depth=16, device=None):
                 report=info["report"])
 
 
-def vortex_pair_study(n=500, M=85, Mr=110, ns=60, pc=1.0, tol=1e-4, depth=16, gamma_max=255.0, t_f=5.0, dt=0.01,
-                      ntrain=4, grid=6, seed=2103, newton_tol=2e-5, device=None):
-    """Parametric vortex pair: offline training at ntrain Latin-hypercube
-    points, then grid x grid queries in one batched launch; accuracy of every
-    query against its trapezoid FOM.  The FP32 FOM's Newton tolerance sits
-    just above the rounding floor of states of magnitude ~50."""
+# The two parametric experiments of the paper's results (vortex pair and
+# mushroom cloud): N = 500 bodies, mu = (Gamma_1, Gamma_N), 4 Latin-hypercube
+# training points, a 6 x 6 query grid, and the paper's hyper-parameters.
+PARAMETRIC = {
+    "vortex_pair": dict(lo=(0.25 * 255.0, 0.25 * 255.0), hi=(255.0, 255.0), dt=0.01, t_f=5.0,
+                        M=85, Mr=110, ns=60, inflow=False),
+    "mushroom_cloud": dict(lo=(-220.0, 0.5 * 220.0), hi=(-0.5 * 220.0, 220.0), dt=0.005, t_f=5.0,
+                           M=110, Mr=185, ns=75, inflow=True),
+}
+
+
+def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0, tol=1e-4, depth=16, ntrain=4,
+                     grid=6, seed=2103, newton_tol=2e-5, device=None):
+    """Parametric experiment: offline training at ntrain Latin-hypercube
+    points, then grid x grid queries (Gamma~ reassigned on the device) in one
+    batched launch; accuracy of every query against its trapezoid FOM.  The
+    FP32 FOM's Newton tolerance sits just above the rounding floor of states
+    of magnitude ~50."""
+    cfg = PARAMETRIC[case]
+    M = cfg["M"] if M is None else M
+    Mr = cfg["Mr"] if Mr is None else Mr
+    ns = cfg["ns"] if ns is None else ns
+    dt, t_f = cfg["dt"], cfg["t_f"]
+    make = W.vortex_pair if case == "vortex_pair" else W.mushroom_cloud
     dev = torch.device("cuda", 0) if device is None else device
     steps = int(round(t_f / dt))
-    lo, hi = 0.25 * gamma_max, gamma_max
+    lo, hi = np.asarray(cfg["lo"]), np.asarray(cfg["hi"])
     mus_train = W.latin_hypercube(ntrain, lo, hi, seed)
     mus_q = W.parameter_grid(grid, lo, hi)
-    clouds = [W.vortex_pair(m, n=n) for m in mus_train]
+    clouds = [make(m, n=n) for m in mus_train]
+    u = W.mushroom_inflow(n) if cfg["inflow"] else None
     t0 = time.perf_counter()
     art, info = offline.train_parametric(clouds, dt=dt, nsnap=steps, M=M, Mr=Mr, ns=ns, depth=depth, pc=pc, tol=tol,
-                                         max_iter=100, device=dev, newton_tol=newton_tol)
+                                         max_iter=100, device=dev, newton_tol=newton_tol, u=u)
     t_off = time.perf_counter() - t0
     rom = native.Rom(art, tol=tol, max_iter=100)
     nq = len(mus_q)
-    G = torch.tensor(np.stack([np.asarray(W.vortex_pair(m, n=n).gamma, np.float32) for m in mus_q]), device=dev)
+    G = torch.tensor(np.stack([np.asarray(make(m, n=n).gamma, np.float32) for m in mus_q]), device=dev)
     gt = rom.reassign(G)
     xq = torch.zeros((nq, M), dtype=torch.float64, device=dev)
     hq = torch.empty((nq, steps, M), dtype=torch.float64, device=dev)
@@ -159,16 +178,18 @@ def vortex_pair_study(n=500, M=85, Mr=110, ns=60, pc=1.0, tol=1e-4, depth=16, ga
     xy0 = np.asarray(clouds[0].xy, np.float32).astype(np.float64)
     length = float(np.hypot(xy0[n - 1] - xy0[0], xy0[2 * n - 1] - xy0[n]))
     delta = float(clouds[0].delta)
+    ud = None if u is None else torch.tensor(np.asarray(u, np.float32), device=dev)
     maes, aes, t_fom = [], [], []
     for q, m in enumerate(mus_q):
-        cl = W.vortex_pair(m, n=n)
+        cl = make(m, n=n)
         g = torch.tensor(np.asarray(cl.gamma, np.float32), device=dev)
         x = torch.tensor(xy0, dtype=torch.float32, device=dev)
         traj_d = torch.empty((steps, 2 * n), dtype=torch.float32, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for t in range(steps):
-            native.implicit(x, g, delta, dt, 1, scheme=native.TRAPEZOID, newton_tol=newton_tol, gmres_tol=1e-4)
+            native.implicit(x, g, delta, dt, 1, scheme=native.TRAPEZOID, newton_tol=newton_tol, gmres_tol=1e-4,
+                            uinf=ud)
             traj_d[t].copy_(x)
         torch.cuda.synchronize()
         t_fom.append(time.perf_counter() - t0)
@@ -182,9 +203,9 @@ def vortex_pair_study(n=500, M=85, Mr=110, ns=60, pc=1.0, tol=1e-4, depth=16, ga
             hs.append(abs((h3 - h1) / h1))
         aes.append(float(np.mean(hs)))
     it = iq.cpu().numpy()
-    return dict(study="vortex_pair_parametric", N=n, M=M, Mr=Mr, ns=ns, pc=pc, tol=tol, steps=steps, dt=dt,
-                gamma_max=gamma_max, train_mu=mus_train.tolist(), queries=nq, Nc=int(np.asarray(art["Gt"]).size),
-                nnz=int(np.asarray(art["ids"]).size), offline_seconds=t_off,
+    return dict(study=case + "_parametric", N=n, M=M, Mr=Mr, ns=ns, pc=pc, tol=tol, steps=steps, dt=dt,
+                mu_lo=lo.tolist(), mu_hi=hi.tolist(), train_mu=mus_train.tolist(), queries=nq,
+                Nc=int(np.asarray(art["Gt"]).size), nnz=int(np.asarray(art["ids"]).size), offline_seconds=t_off,
                 online_batched_seconds=t_batch, online_one_query_seconds=t_one,
                 batched_queries_per_one_query_time=nq * t_one / t_batch,
                 fom_seconds_per_query=float(np.mean(t_fom)), speedup_SF_per_query=float(np.mean(t_fom)) / (t_batch / nq),
@@ -194,17 +215,22 @@ def vortex_pair_study(n=500, M=85, Mr=110, ns=60, pc=1.0, tol=1e-4, depth=16, ga
                 mae_d_per_query=maes, report=info["report"])
 
 
+def vortex_pair_study(**kw):
+    """The vortex-pair parametric experiment (see ``parametric_study``)."""
+    return parametric_study("vortex_pair", **kw)
+
+
 def main(argv=None):
     p = argparse.ArgumentParser()
-    p.add_argument("--study", default="single_vortex", choices=["single_vortex", "vortex_pair"])
+    p.add_argument("--study", default="single_vortex", choices=["single_vortex"] + sorted(PARAMETRIC))
     p.add_argument("--n", type=int, nargs="+", default=[500])
     p.add_argument("--case", type=int, default=1)
-    p.add_argument("--basis", type=int, nargs=3, default=[85, 110, 60], metavar=("M", "MR", "NS"),
-                   help="vortex pair: M, M_r, n_s (the paper's 85, 110, 60)")
+    p.add_argument("--basis", type=int, nargs=3, default=None, metavar=("M", "MR", "NS"),
+                   help="parametric studies: M, M_r, n_s (default: the paper's)")
     a = p.parse_args(argv)
-    if a.study == "vortex_pair":
-        M, Mr, ns = a.basis
-        print(json.dumps(vortex_pair_study(M=M, Mr=Mr, ns=ns)), flush=True)
+    if a.study in PARAMETRIC:
+        M, Mr, ns = a.basis if a.basis else (None, None, None)
+        print(json.dumps(parametric_study(a.study, M=M, Mr=Mr, ns=ns)), flush=True)
         return 0
     for n in a.n:
         print(json.dumps(run(n, a.case)), flush=True)

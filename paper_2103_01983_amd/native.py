@@ -45,7 +45,7 @@ class RomDesc(ctypes.Structure):
                 ("Phibar", _vp), ("xbar0", _vp), ("xqt0", _vp), ("Phit", _vp), ("Gt", _vp),
                 ("off", _vp), ("ids", _vp), ("A", _vp),
                 ("delta", _f64), ("dt", _f64), ("tol", _f64), ("alpha", _f64),
-                ("max_iter", _i32), ("pad", _i32)]
+                ("max_iter", _i32), ("pad", _i32), ("ubar", _vp)]
 
 
 # name -> (restype, argtypes); the full exported surface of ptrom.h
@@ -65,6 +65,8 @@ SIGNATURES = {
     "ptrom_rk4_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f64, _f64, ctypes.c_int, _vp]),
     "ptrom_implicit": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _f32, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _vp]),
+    "ptrom_implicit_forced": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _f32, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonStats), _vp]),
     "ptrom_velocity_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptrom_rk4_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _f32, ctypes.c_int,
                                          ctypes.c_int, _vp]),
@@ -292,15 +294,18 @@ def rk4_f64(xy, gamma, delta, dt, nsteps):
 
 
 def implicit(xy, gamma, delta, dt, nsteps, scheme=BACKWARD_EULER, newton_tol=1e-6, max_newton=20,
-             gmres_restart=20, gmres_maxit=60, gmres_tol=1e-3):
-    """In place on xy; returns NewtonStats.  Synchronises the stream."""
+             gmres_restart=20, gmres_maxit=60, gmres_tol=1e-3, uinf=None):
+    """In place on xy; returns NewtonStats.  Synchronises the stream.
+    ``uinf`` [2N] (device FP32) is an optional background velocity."""
     n = _n(xy)
     c = context(xy.device)
     o = NewtonOpts(float(newton_tol), int(max_newton), int(gmres_restart), int(gmres_maxit), 0, float(gmres_tol))
     st = NewtonStats()
-    _check(c, lib().ptrom_implicit(c, n, _ptr(xy, torch.float32, 2 * n, "xy"), _ptr(gamma, torch.float32, n, "gamma"),
-                                   float(delta), float(dt), int(nsteps), int(scheme), ctypes.byref(o),
-                                   ctypes.byref(st), _stream(xy)), "ptrom_implicit", warn_ok=True)
+    pu = None if uinf is None else _ptr(uinf, torch.float32, 2 * n, "uinf")
+    _check(c, lib().ptrom_implicit_forced(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
+                                          _ptr(gamma, torch.float32, n, "gamma"), float(delta), pu, float(dt),
+                                          int(nsteps), int(scheme), ctypes.byref(o), ctypes.byref(st), _stream(xy)),
+           "ptrom_implicit_forced", warn_ok=True)
     return st
 
 
@@ -401,12 +406,15 @@ class Rom:
         ns = off.size - 1
         A = np.asarray(art["A"], dtype=np.float64)
         self.M, self.ns, self.Mr = int(art["M"]), ns, int(A.shape[0])
+        if art.get("ubar") is not None and np.asarray(art["ubar"]).size != 2 * ns:
+            raise ValueError("ubar must hold the 2 ns sampled rows")
         Nc = int(np.asarray(art["Gt"]).size)
         ids = np.asarray(art["ids"], dtype=np.int64)
         desc = RomDesc(self.M, self.Mr, ns, int(jac_mode), Nc, int(ids.size),
                        d(art["Phibar"]), d(art["xbar0"]), d(np.asarray(art["xqt0"]).reshape(-1)),
                        d(np.asarray(art["Phit"]).reshape(-1)), d(art["Gt"]), i(off), i(ids if ids.size else [0]),
-                       d(A), float(art["delta"]), float(art["dt"]), float(tol), float(alpha), int(max_iter), 0)
+                       d(A), float(art["delta"]), float(art["dt"]), float(tol), float(alpha), int(max_iter), 0,
+                       d(art["ubar"]) if art.get("ubar") is not None else None)
         h = _vp()
         _check(c, lib().ptrom_rom_create(c, ctypes.byref(desc), ctypes.byref(h)), "ptrom_rom_create")
         self._h = h

@@ -23,13 +23,14 @@ import torch
 from . import native
 
 
-def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap, newton_tol=1e-6):
-    """Device FP64 [nsnap, 2N]: states x^1..x^nsnap of the trapezoid FOM."""
+def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap, newton_tol=1e-6, uinf=None):
+    """Device FP64 [nsnap, 2N]: states x^1..x^nsnap of the trapezoid FOM;
+    ``uinf`` (device FP32 [2N]) an optional background velocity."""
     x = xy0.clone()
     S = torch.empty((nsnap, xy0.numel()), dtype=torch.float64, device=xy0.device)
     for t in range(nsnap):
         st = native.implicit(x, gamma, delta, dt, 1, scheme=native.TRAPEZOID, newton_tol=newton_tol,
-                             gmres_tol=1e-4)
+                             gmres_tol=1e-4, uinf=uinf)
         if st.nonconverged_steps:
             raise RuntimeError("trapezoid snapshot %d did not converge" % t)
         S[t].copy_(x)
@@ -76,14 +77,20 @@ def sample_rows(sample, n):
     return np.concatenate([s, n + s])
 
 
-def artifacts(sample, wpts, xy0, Phi_h, gamma, depth, pc, delta, dt, A, criterion=native.NEIGHBOR, theta=0.0):
+def artifacts(sample, wpts, xy0, Phi_h, gamma, depth, pc, delta, dt, A, criterion=native.NEIGHBOR, theta=0.0,
+              u=None):
+    """Online artifacts; a background velocity ``u`` [2N] contributes its
+    sampled rows as ``ubar``."""
     n = gamma.size
     cl = native.cluster_build(wpts, xy0, Phi_h, gamma, depth, pc, sample, criterion, theta)
     rows = sample_rows(sample, n)
-    return dict(M=Phi_h.shape[1], Mr=A.shape[0], sample=np.asarray(sample), Phibar=Phi_h[rows].copy(),
-                xbar0=np.asarray(xy0)[rows].copy(), xqt0=cl["xqt0"], Phit=cl["Phit"], Gt=cl["Gt"],
-                off=cl["off"], ids=cl["ids"], keys=cl["keys"], A=A, delta=float(delta), dt=float(dt),
-                mem_off=cl["mem_off"], mem_ids=cl["mem_ids"], n=int(n))
+    art = dict(M=Phi_h.shape[1], Mr=A.shape[0], sample=np.asarray(sample), Phibar=Phi_h[rows].copy(),
+               xbar0=np.asarray(xy0)[rows].copy(), xqt0=cl["xqt0"], Phit=cl["Phit"], Gt=cl["Gt"],
+               off=cl["off"], ids=cl["ids"], keys=cl["keys"], A=A, delta=float(delta), dt=float(dt),
+               mem_off=cl["mem_off"], mem_ids=cl["mem_ids"], n=int(n))
+    if u is not None:
+        art["ubar"] = np.asarray(u, dtype=np.float64)[rows].copy()
+    return art
 
 
 def reassign_host(art, gamma_mu):
@@ -241,12 +248,14 @@ def mae_distance(xA, xB, n, length):
 
 
 def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100,
-                     jac_mode=native.JAC_PAPER, device=None, criterion=native.NEIGHBOR, theta=0.0, newton_tol=1e-6):
+                     jac_mode=native.JAC_PAPER, device=None, criterion=native.NEIGHBOR, theta=0.0, newton_tol=1e-6,
+                     u=None):
     """Stages 1-4 over several training parameters on one GPU.  ``clouds``
     share x^0 and delta and differ in Gamma.  One POD of the snapshots of all
     training points; clustering weights = mean |Gamma| over the training
     points; Tier II at every training point with its reassigned Gamma~; the
-    residual snapshots of all training points form Phi_r.  Returns
+    residual snapshots of all training points form Phi_r.  ``u`` [2N] is a
+    background velocity common to all parameters (inflow), or None.  Returns
     (artifacts with membership, info)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
     t = {}
@@ -256,8 +265,10 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
     d = float(clouds[0].delta)
 
     t0 = time.perf_counter()
+    u_h = None if u is None else np.asarray(u, np.float32).astype(np.float64)
+    u_d = None if u is None else torch.tensor(u_h, dtype=torch.float32, device=dev)
     S = torch.cat([trapezoid_snapshots(x0, torch.tensor(np.asarray(c.gamma, np.float32), device=dev), d, dt, nsnap,
-                                       newton_tol=newton_tol) for c in clouds])
+                                       newton_tol=newton_tol, uinf=u_d) for c in clouds])
     torch.cuda.synchronize()
     t["stage1_s"] = time.perf_counter() - t0
 
@@ -269,7 +280,8 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
     t["stage2_s"] = time.perf_counter() - t0
 
     t0 = time.perf_counter()
-    full = artifacts(np.arange(n), wpts, xy0_h, Phi_h, wgt, depth, pc, d, dt, np.zeros((M, 2 * n)), criterion, theta)
+    full = artifacts(np.arange(n), wpts, xy0_h, Phi_h, wgt, depth, pc, d, dt, np.zeros((M, 2 * n)), criterion, theta,
+                     u=u_h)
     R, hists, its = [], [], []
     for c in clouds:
         a = dict(full)
@@ -284,7 +296,7 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
     Phi_r = np.ascontiguousarray(Phir_d.cpu().numpy().T)
     sample = greedy_sample(Phi_r, ns)
     A = np.linalg.pinv(Phi_r[sample_rows(sample, n)])
-    art = artifacts(sample, wpts, xy0_h, Phi_h, wgt, depth, pc, d, dt, A, criterion, theta)
+    art = artifacts(sample, wpts, xy0_h, Phi_h, wgt, depth, pc, d, dt, A, criterion, theta, u=u_h)
     t["stage34_s"] = time.perf_counter() - t0
     info = dict(Phi=Phi_h, sigma=sigma, sigma_r=sig_r, Phi_r=Phi_r, S=S.cpu().numpy(), wpts=wpts, weights=wgt,
                 tier2_hist=hists, tier2_iters=its, report=dict(t, nc=int(art["Gt"].size), nnz=int(art["ids"].size),

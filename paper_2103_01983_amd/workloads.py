@@ -130,7 +130,8 @@ def mushroom_inflow(n, amp=5.0, radius=1.125, base=0.5):
 
 def latin_hypercube(k, lo, hi, seed):
     """k points of a Latin hypercube in the box [lo, hi]^2 (one per row and
-    column stratum, uniform inside its cell)."""
+    column stratum, uniform inside its cell); lo and hi may be
+    per-dimension pairs."""
     rng = np.random.default_rng(seed)
     pts = np.empty((k, 2))
     for dim in range(2):
@@ -139,9 +140,11 @@ def latin_hypercube(k, lo, hi, seed):
 
 
 def parameter_grid(m, lo, hi):
-    """m x m grid of parameter points spanning [lo, hi]^2 (row-major)."""
-    g = np.linspace(lo, hi, m)
-    return np.array([(a, b) for a in g for b in g])
+    """m x m grid of parameter points spanning [lo, hi]^2 (row-major); lo and
+    hi may be per-dimension pairs."""
+    lo, hi = np.broadcast_to(lo, 2), np.broadcast_to(hi, 2)
+    ga, gb = np.linspace(lo[0], hi[0], m), np.linspace(lo[1], hi[1], m)
+    return np.array([(a, b) for a in ga for b in gb])
 
 
 def unit_vectors(n, k, seed):

@@ -191,27 +191,34 @@ def test_rom_run_shapes(dev, trained_shapes, shape, mode):
     assert rel(h, o["hist"]) <= 1e-5
 
 
+LARGE = [(48, 96, 48), (85, 110, 60), (110, 185, 75)]
+
+
 @pytest.fixture(scope="module")
 def large_shapes():
-    """Bases beyond 32 (the blocked path): M = 48 / M_r = 96 / n_s = 48 and
-    the paper's vortex-pair sizes M = 85 / M_r = 110 / n_s = 60, with random
-    orthonormal Phi and Phi_r and the training clustering and sampling."""
+    """Bases beyond 32 (the blocked path): M = 48 / M_r = 96 / n_s = 48, the
+    paper's vortex-pair sizes M = 85 / M_r = 110 / n_s = 60 and its
+    mushroom-cloud sizes M = 110 / M_r = 185 / n_s = 75 (with the inflow as a
+    background velocity), with random orthonormal Phi and Phi_r and the
+    training clustering and sampling."""
     out = {}
     cl = W.counter_rotating_patches(640, seed=43, delta=0.02)
     n = cl.n
     rng = np.random.default_rng(44)
-    for M, Mr, ns in [(48, 96, 48), (85, 110, 60)]:
+    for M, Mr, ns in LARGE:
         Phi = np.linalg.qr(rng.standard_normal((2 * n, M)))[0]
         sig = np.sort(rng.uniform(1.0, 10.0, M))[::-1]
         tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
         sample = np.sort(rng.choice(n, ns, replace=False))
         Phi_r = np.linalg.qr(rng.standard_normal((2 * n, Mr)))[0]
         A = off.gappy_operator(Phi_r, sample)
-        out[(M, Mr, ns)] = rounded(off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A))
+        u = 0.1 * W.mushroom_inflow(n) if M > 96 else None
+        out[(M, Mr, ns)] = rounded(off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A,
+                                                     u=u))
     return out
 
 
-@pytest.mark.parametrize("shape", [(48, 96, 48), (85, 110, 60)])
+@pytest.mark.parametrize("shape", LARGE)
 def test_large_hyperpair_parity(dev, large_shapes, shape):
     art = large_shapes[shape]
     M = shape[0]
@@ -228,7 +235,7 @@ def test_large_hyperpair_parity(dev, large_shapes, shape):
     assert rel(gC.cpu().numpy() - art["Phibar"], C - art["Phibar"]) <= 1e-5
 
 
-@pytest.mark.parametrize("shape", [(48, 96, 48), (85, 110, 60)])
+@pytest.mark.parametrize("shape", LARGE)
 def test_large_run_fixed_iterations(dev, large_shapes, shape):
     art = large_shapes[shape]
     M = shape[0]
@@ -266,3 +273,48 @@ def test_large_batched_queries(dev, large_shapes):
 def test_large_exact_jacobian_rejected(dev, large_shapes):
     with pytest.raises(native.PtromError):
         native.Rom(large_shapes[(48, 96, 48)], jac_mode=native.JAC_EXACT)
+
+
+def test_large_inflow_enters_the_residual(dev, large_shapes):
+    # The same artifacts without their background velocity give a different
+    # trajectory, which the GPU also follows.
+    art = large_shapes[(110, 185, 75)]
+    assert "ubar" in art
+    art0 = dict(art)
+    del art0["ubar"]
+    steps, K, M = 4, 3, 110
+    hs = []
+    for a in (art, art0):
+        rom = native.Rom(a, tol=0.0, max_iter=K)
+        xh = torch.zeros(M, dtype=torch.float64, device=dev)
+        hist = torch.empty(steps * M, dtype=torch.float64, device=dev)
+        rom.run(steps, xh, hist, None)
+        torch.cuda.synchronize()
+        hs.append(hist.cpu().numpy().reshape(steps, M))
+    o0 = oracle.Rom(art0).run(steps, tol=0.0, max_iter=K)
+    assert rel(hs[1], o0["hist"]) <= 1e-5
+    assert rel(hs[0], hs[1]) > 1e-3
+
+
+@pytest.mark.parametrize("mode", [native.JAC_PAPER, native.JAC_EXACT])
+def test_small_path_inflow_parity(dev, trained, mode):
+    cl, art, ex = trained
+    a = dict(art)
+    nd = 2 * len(art["sample"])
+    rng = np.random.default_rng(12)
+    a["ubar"] = rng.uniform(0.5, 3.0, nd) * 1e-2
+    xh = rng.standard_normal(8) * 0.05
+    xp, fp = rng.standard_normal(nd) * 0.1 + a["xbar0"], rng.standard_normal(nd) * 0.1
+    xb, fb, rb, C = oracle.Rom(a, jac_mode=mode).hyperpair(xh, xp, fp)
+    t = lambda v: torch.tensor(v, dtype=torch.float64, device=dev)
+    gx, gf, gr, gC = native.Rom(a, jac_mode=mode).hyperpair(t(xh), t(xp), t(fp))
+    assert rel(gf.cpu().numpy(), fb) <= 1e-5
+    assert rel(gr.cpu().numpy(), rb) <= 1e-5
+    steps, K = 12, 3
+    o = oracle.Rom(a, jac_mode=mode).run(steps, tol=0.0, max_iter=K)
+    rom = native.Rom(a, tol=0.0, max_iter=K, jac_mode=mode)
+    x = torch.zeros(8, dtype=torch.float64, device=dev)
+    hist = torch.empty(steps * 8, dtype=torch.float64, device=dev)
+    rom.run(steps, x, hist, None)
+    torch.cuda.synchronize()
+    assert rel(hist.cpu().numpy().reshape(steps, 8), o["hist"]) <= 1e-5

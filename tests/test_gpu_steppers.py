@@ -71,6 +71,39 @@ def test_implicit_parity(dev, scheme):
     assert rel(xs - xy, o - xy) <= 1e-4
 
 
+@pytest.mark.parametrize("scheme", [native.BACKWARD_EULER, native.TRAPEZOID])
+def test_implicit_with_inflow_parity(dev, scheme):
+    # background velocity (the mushroom cloud's inflow profile) in the FOM
+    c = W.gaussian_patch(700, seed=41, delta=0.01)
+    xy, g = f32(c.xy), f32(c.gamma) * 50.0
+    u = f32(0.2 * W.mushroom_inflow(700))
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    ud = torch.tensor(u, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, 0.01, 5e-4, 5, scheme=scheme, newton_tol=1e-7, gmres_tol=1e-4, uinf=ud)
+    assert st.nonconverged_steps == 0
+    o, _ = oracle.implicit(xy, g, float(np.float32(0.01)), float(np.float32(5e-4)), 5, scheme=scheme, u=u)
+    xs = x.cpu().numpy()
+    assert rel(xs, o) <= 1e-5
+    assert rel(xs - xy, o - xy) <= 1e-4
+
+
+def test_implicit_uniform_inflow_translates(dev):
+    c = W.gaussian_patch(500, seed=42, delta=0.01)
+    xy, g = f32(c.xy), f32(c.gamma) * 50.0
+    U = np.concatenate([np.full(500, 0.25), np.full(500, -0.125)]).astype(np.float32)
+    dt, k = np.float32(5e-4), 6
+    xs = []
+    for uu in (None, torch.tensor(U, device=dev)):
+        x = torch.tensor(xy, dtype=torch.float32, device=dev)
+        st = native.implicit(x, torch.tensor(g, dtype=torch.float32, device=dev), 0.01, float(dt), k,
+                             scheme=native.TRAPEZOID, newton_tol=1e-7, gmres_tol=1e-4, uinf=uu)
+        assert st.nonconverged_steps == 0
+        xs.append(x.cpu().numpy().astype(np.float64))
+    shift = U.astype(np.float64) * float(dt) * k
+    assert np.abs(xs[1] - (xs[0] + shift)).max() <= 1e-5
+
+
 def test_backward_euler_full_size_residual(dev):
     # N = 65536 Gaussian patch, backward Euler dt 5e-4: after several steps the
     # state must satisfy x_n - x_{n-1} - dt f(x_n) = 0 on sampled rows, with f
