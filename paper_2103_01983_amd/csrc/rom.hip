@@ -353,18 +353,33 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // FP64 matrix-core instruction (16 x 16 x 4 per step): lane l supplies
 // X(l % 16, k0 + l / 16) and Y(k0 + l / 16, l % 16) and receives, in register
 // r, D(4 r + l / 16, l % 16) (tile-local indices).  xa / yb return 0 outside
-// the matrices.  The wave must be fully active.
+// the matrices.  Whole groups of four k-steps go to four independent
+// accumulators, so consecutive products do not wait on each other; the four
+// are added at the end.  The wave must be fully active.
 template <class FX, class FY>
 __device__ __forceinline__ dbl4 mfma_tile(int K, int lane, FX xa, FY yb, dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0}) {
   const int r = lane & 15, kq = lane >> 4;
-#pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 4) {
+  dbl4 c1 = dbl4{0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
+  int k0 = 0;
+  for (; k0 + 16 <= K; k0 += 16) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = xa(r, k0 + 4 * u + kq);
+      b[u] = yb(k0 + 4 * u + kq, r);
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], c3, 0, 0, 0);
+  }
+  for (; k0 < K; k0 += 4) {
     const int k = k0 + kq;
     const double a = k < K ? xa(r, k) : 0.0;
     const double b = k < K ? yb(k, r) : 0.0;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  return acc;
+  return (acc + c1) + (c2 + c3);
 }
 
 // Sum over aligned groups of 8 lanes (all lanes active); every lane of the
@@ -699,8 +714,16 @@ __global__ void __launch_bounds__(kRunThreads)
 // during the inversion; the tail holds the previous-step rows, this query's
 // Gamma~ and the entries' surrogate ids.
 constexpr int kMaxTiles = 5;  // lower-triangle tiles of N' per wave
+constexpr int kPf = 5;        // A elements per thread prefetched a block ahead (n_d <= 160)
 static_assert(((kMaxM + 16) / 16) * ((kMaxM + 16) / 16 + 1) / 2 <= kMaxTiles * (kRunThreads / 64),
               "every lower-triangle tile of N' needs an owner");
+
+// LDS row strides chosen so that the 16 lanes of a quarter-wave reading one
+// matrix-core operand column hit distinct banks: odd (in doubles) for the A
+// block, the pivot block and the tableau; an odd multiple of 16 floats for the
+// FP32 [C | rbar] rows (rows kq = 0..3 of one k-step then start 16 banks
+// apart).
+__host__ __device__ inline int c_stride(int M1p) { return (M1p / 16) % 2 ? M1p : M1p + 16; }
 
 struct BigLayout {
   size_t r1, r2, total;  // doubles
@@ -711,11 +734,12 @@ __host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, i
   const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16, Mp = (M + 15) / 16 * 16;
   BigLayout L;
   const size_t tab = (size_t)Mp * (Mp + 1);  // padded tableau, odd row stride
-  const size_t crb = ((size_t)nd * M + 1) / 2 + nd;  // FP32 C and FP64 rbar
+  const size_t ndp = (nd + 3) / 4 * 4, ldcf = c_stride(M1p);
+  const size_t crb = (ndp * ldcf + 1) / 2 + (ndp + 1) / 2;  // [C | rbar] in FP32 and rbar's low part
   L.r1 = crb > tab ? crb : tab;
   const size_t gather = 3 * (size_t)ns + nd + 2 * (size_t)Nc;
-  const size_t blocks = 16 * (size_t)nd + 16 * (size_t)M1p;
-  const size_t inv = 2 * 16 * (size_t)Mp + 256 + Mp;  // row / column panels, block inverse, g
+  const size_t blocks = 16 * (ndp + 1) + 16 * (size_t)M1p;
+  const size_t inv = 2 * 16 * (size_t)Mp + 16 * 17 + Mp;  // row / column panels, block inverse, g
   L.r2 = gather > blocks ? gather : blocks;
   L.r2 = L.r2 > inv ? L.r2 : inv;
   L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)Nc + 1) / 2 + ((size_t)nnz + 1) / 2;
@@ -736,12 +760,16 @@ __global__ void __launch_bounds__(kRunThreads)
   double *R1 = dyn, *R2 = dyn + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
   // region 1: C (nd x M, FP32) and rbar (nd, FP64), then N (Mp x Mp, stride ldT)
+  // [C | rbar | 0] as FP32 (ndp rows of stride ldcf, zero padded), rbar = hi (column M) +
+  // lo (Rlo) so that the residual keeps its FP64 value to 2^-48
+  const int ndp = (nd + 3) / 4 * 4, ldcf = c_stride(M1p), lda = ndp + 1;
   float *Cf = reinterpret_cast<float *>(R1);
-  double *rres = R1 + ((size_t)nd * M + 1) / 2, *T = R1;
+  float *Rlo = Cf + (size_t)ndp * ldcf;
+  double *T = R1;
   double *bt = R2, *pos = R2 + 3 * ns;           // gather phase: pos[0, nd) are the sampled rows
-  double *Ab = R2, *Gb = R2 + 16 * (size_t)nd;   // product phase
+  double *Ab = R2, *Gb = R2 + 16 * (size_t)lda;  // product phase (A block rows of stride lda)
   const int Mp = (M + 15) / 16 * 16, ldT = Mp + 1;
-  double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp, *gb = Pinv + 256;  // inversion
+  double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp, *gb = Pinv + 16 * 17;  // inversion
   xhat += (size_t)blockIdx.x * M;
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
   if (iters) iters += (size_t)blockIdx.x * nsteps;
@@ -813,8 +841,13 @@ __global__ void __launch_bounds__(kRunThreads)
           fbar_out[t] = Fx;
           fbar_out[ns + t] = Fy;
           if (res) {
-            rres[t] = (tx - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
-            rres[ns + t] = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+            const double r0 = (tx - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+            const double r1 = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+            const float h0 = (float)r0, h1 = (float)r1;
+            Cf[(size_t)t * ldcf + M] = h0;
+            Rlo[t] = (float)(r0 - (double)h0);
+            Cf[(size_t)(ns + t) * ldcf + M] = h1;
+            Rlo[ns + t] = (float)(r1 - (double)h1);
             bt[3 * t] = s2 * kInv2PiD;
             bt[3 * t + 1] = s3 * kInv2PiD;
             bt[3 * t + 2] = s4 * kInv2PiD;
@@ -840,28 +873,76 @@ __global__ void __launch_bounds__(kRunThreads)
         const int t = row < ns ? row : row - ns;
         const double px = d.pt[(size_t)m * d.P + t], py = d.pt[(size_t)m * d.P + ns + t];
         const double B00 = bt[3 * t], B01 = bt[3 * t + 1], B10 = bt[3 * t + 2];
-        Cf[(size_t)row * M + m] = (float)(row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py));
+        Cf[(size_t)row * ldcf + m] = (float)(row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py));
       }
+      // zero padding: columns past M, rows past nd (and their low parts)
+      for (int q = tid; q < nd * (M1p - M1); q += kRunThreads) {
+        const int row = q / (M1p - M1);
+        Cf[(size_t)row * ldcf + M1 + (q - row * (M1p - M1))] = 0.0f;
+      }
+      for (int q = tid; q < (ndp - nd) * ldcf; q += kRunThreads) Cf[(size_t)nd * ldcf + q] = 0.0f;
+      for (int q = nd + tid; q < ndp; q += kRunThreads) Rlo[q] = 0.0f;
       // N' = G'^T G' over 16-row blocks of A (the gather's LDS is free now)
       dbl4 acc[kMaxTiles];
 #pragma unroll
       for (int u = 0; u < kMaxTiles; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+      // A's 16-row blocks: the first kPf elements of each thread's share are
+      // fetched into registers one block ahead, so their loads run under the
+      // previous block's products
+      double pf[kPf];
+      auto fetch = [&](int rb) {
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+          const int t = tid + u * kRunThreads, r = t / ndp, q = t - r * ndp;
+          pf[u] = t < 16 * ndp && rb + r < Mr && q < nd ? d.A[(size_t)(rb + r) * nd + q] : 0.0;
+        }
+      };
+      fetch(0);
+      __syncthreads();  // C complete; the gather's terms in region 2 are dead
       for (int rb = 0; rb < Mr; rb += 16) {
-        __syncthreads();  // C complete / previous block consumed
-        for (int t = tid; t < 16 * nd; t += kRunThreads) {
-          const int r = t / nd, q = t - r * nd;
-          Ab[t] = rb + r < Mr ? d.A[(size_t)(rb + r) * nd + q] : 0.0;
+        // the previous block's G' has been read (barrier after its N' inputs)
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+          const int t = tid + u * kRunThreads;
+          if (t < 16 * ndp) Ab[t + t / ndp] = pf[u];  // row r at r * lda
+        }
+        for (int t = tid + kPf * kRunThreads; t < 16 * ndp; t += kRunThreads) {
+          const int r = t / ndp, q = t - r * ndp;
+          Ab[(size_t)r * lda + q] = rb + r < Mr && q < nd ? d.A[(size_t)(rb + r) * nd + q] : 0.0;
         }
         __syncthreads();
+        if (rb + 16 < Mr) fetch(rb + 16);
         for (int tj = wave; tj < tcn; tj += nwaves) {
-          const int j0 = tj * 16;
-          const dbl4 g = mfma_tile(nd, lane, [&](int i, int q) { return Ab[(size_t)i * nd + q]; },
-                                   [&](int q, int j) {
-                                     const int c = j0 + j;
-                                     return c < M ? (double)Cf[(size_t)q * M + c] : (c == M ? rres[q] : 0.0);
-                                   });
+          // G'_blk tile = A_blk [C | rbar] (K = ndp, no guards: both operands
+          // are zero padded); four k-steps' operands are loaded before their
+          // products issue
+          const int j0 = tj * 16, r = lane & 15, kq = lane >> 4;
+          const double *ap = Ab + (size_t)r * lda + kq;
+          const float *cp = Cf + (size_t)kq * ldcf + j0 + r;
+          const float *lp = Rlo + kq;
+          const bool rcol = j0 + r == M;
+          dbl4 g = dbl4{0.0, 0.0, 0.0, 0.0}, g1 = g, g2 = g, g3 = g;  // independent chains
+          int k0 = 0;
+          for (; k0 + 16 <= ndp; k0 += 16) {
+            double a[4], b[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Gb[(4 * r + (lane >> 4)) * M1p + j0 + (lane & 15)] = g[r];
+            for (int u = 0; u < 4; ++u) {
+              a[u] = ap[k0 + 4 * u];
+              b[u] = (double)cp[(size_t)(k0 + 4 * u) * ldcf] + (rcol ? (double)lp[k0 + 4 * u] : 0.0);
+            }
+            g = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], g, 0, 0, 0);
+            g1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], g1, 0, 0, 0);
+            g2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], g2, 0, 0, 0);
+            g3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], g3, 0, 0, 0);
+          }
+          for (; k0 < ndp; k0 += 4) {
+            const double a = ap[k0];
+            const double b = (double)cp[(size_t)k0 * ldcf] + (rcol ? (double)lp[k0] : 0.0);
+            g = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, g, 0, 0, 0);
+          }
+          g = (g + g1) + (g2 + g3);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Gb[(4 * q + kq) * M1p + j0 + r] = g[q];
         }
         __syncthreads();
 #pragma unroll
@@ -942,14 +1023,14 @@ __global__ void __launch_bounds__(kRunThreads)
           }
           if (lane < 16)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) Pinv[i * 16 + lane] = a[i];
+            for (int i = 0; i < 16; ++i) Pinv[i * 17 + lane] = a[i];
         }
         __syncthreads();
         // row panel R = P^-1 T_K, (16 x Mp; the K block is not used)
         for (int tj = wave; tj < nb; tj += nwaves) {
           if (tj == kb) continue;
           const int j0 = tj * 16;
-          const dbl4 r4 = mfma_tile(16, lane, [&](int i, int q) { return Pinv[i * 16 + q]; },
+          const dbl4 r4 = mfma_tile(16, lane, [&](int i, int q) { return Pinv[i * 17 + q]; },
                                     [&](int q, int j) { return T[(size_t)(k0 + q) * ldT + j0 + j]; });
 #pragma unroll
           for (int r = 0; r < 4; ++r) Rp[(4 * r + (lane >> 4)) * Mp + j0 + (lane & 15)] = r4[r];
@@ -963,7 +1044,7 @@ __global__ void __launch_bounds__(kRunThreads)
           const int i0 = ti * 16, j0 = tj * 16;
           if (tj == kb) {
             const dbl4 c4 = mfma_tile(16, lane, [&](int i, int q) { return T[(size_t)(i0 + i) * ldT + k0 + q]; },
-                                      [&](int q, int j) { return Pinv[q * 16 + j]; });
+                                      [&](int q, int j) { return Pinv[q * 17 + j]; });
 #pragma unroll
             for (int r = 0; r < 4; ++r) Cpn[(i0 + 4 * r + (lane >> 4)) * 16 + (lane & 15)] = -c4[r];
           } else {
@@ -981,7 +1062,7 @@ __global__ void __launch_bounds__(kRunThreads)
         for (int t = tid; t < 16 * Mp; t += kRunThreads) {
           const int r = t / Mp, c = t - r * Mp;
           if (c < k0 || c >= k0 + 16) T[(size_t)(k0 + r) * ldT + c] = Rp[r * Mp + c];
-          else T[(size_t)(k0 + r) * ldT + c] = Pinv[r * 16 + (c - k0)];
+          else T[(size_t)(k0 + r) * ldT + c] = Pinv[r * 17 + (c - k0)];
           const int i = t >> 4, q = t & 15;  // column panel: row i, column k0 + q
           if (i < k0 || i >= k0 + 16) T[(size_t)i * ldT + k0 + q] = Cpn[i * 16 + q];
         }

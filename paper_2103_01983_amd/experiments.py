@@ -149,9 +149,11 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
     clouds = [make(m, n=n) for m in mus_train]
     u = W.mushroom_inflow(n) if cfg["inflow"] else None
     t0 = time.perf_counter()
+    log = lambda msg: print("[%s] %s" % (case, msg), file=sys.stderr, flush=True)
     art, info = offline.train_parametric(clouds, dt=dt, nsnap=steps, M=M, Mr=Mr, ns=ns, depth=depth, pc=pc, tol=tol,
-                                         max_iter=100, device=dev, newton_tol=newton_tol, u=u)
+                                         max_iter=100, device=dev, newton_tol=newton_tol, u=u, log=log)
     t_off = time.perf_counter() - t0
+    log("offline done in %.1f s: Nc = %d, nnz = %d" % (t_off, np.asarray(art["Gt"]).size, np.asarray(art["ids"]).size))
     rom = native.Rom(art, tol=tol, max_iter=100)
     nq = len(mus_q)
     G = torch.tensor(np.stack([np.asarray(make(m, n=n).gamma, np.float32) for m in mus_q]), device=dev)
@@ -172,6 +174,7 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
     rom.run_batched(gt[:1], steps, x1)
     torch.cuda.synchronize()
     t_one = time.perf_counter() - t0
+    log("online: %d queries in %.3f s, one query %.3f s" % (nq, t_batch, t_one))
 
     # trapezoid FOM of every query (timed per query) and the QoIs
     Phi = info["Phi"]
@@ -202,6 +205,7 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
             h3 = float(native.hamiltonian(torch.tensor(rec[t], dtype=torch.float32, device=dev), g, delta).item())
             hs.append(abs((h3 - h1) / h1))
         aes.append(float(np.mean(hs)))
+        log("query %d: FOM %.2f s, MAE_D %.3e" % (q, t_fom[-1], maes[-1]))
     it = iq.cpu().numpy()
     return dict(study=case + "_parametric", N=n, M=M, Mr=Mr, ns=ns, pc=pc, tol=tol, steps=steps, dt=dt,
                 mu_lo=lo.tolist(), mu_hi=hi.tolist(), train_mu=mus_train.tolist(), queries=nq,

@@ -249,14 +249,16 @@ def mae_distance(xA, xB, n, length):
 
 def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, max_iter=100,
                      jac_mode=native.JAC_PAPER, device=None, criterion=native.NEIGHBOR, theta=0.0, newton_tol=1e-6,
-                     u=None):
+                     u=None, log=None):
     """Stages 1-4 over several training parameters on one GPU.  ``clouds``
     share x^0 and delta and differ in Gamma.  One POD of the snapshots of all
     training points; clustering weights = mean |Gamma| over the training
     points; Tier II at every training point with its reassigned Gamma~; the
     residual snapshots of all training points form Phi_r.  ``u`` [2N] is a
-    background velocity common to all parameters (inflow), or None.  Returns
+    background velocity common to all parameters (inflow), or None.  ``log``
+    (a callable taking a string) receives a line after each stage.  Returns
     (artifacts with membership, info)."""
+    log = log or (lambda msg: None)
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
     t = {}
     n = clouds[0].n
@@ -267,8 +269,12 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
     t0 = time.perf_counter()
     u_h = None if u is None else np.asarray(u, np.float32).astype(np.float64)
     u_d = None if u is None else torch.tensor(u_h, dtype=torch.float32, device=dev)
-    S = torch.cat([trapezoid_snapshots(x0, torch.tensor(np.asarray(c.gamma, np.float32), device=dev), d, dt, nsnap,
-                                       newton_tol=newton_tol, uinf=u_d) for c in clouds])
+    snaps = []
+    for k, c in enumerate(clouds):
+        snaps.append(trapezoid_snapshots(x0, torch.tensor(np.asarray(c.gamma, np.float32), device=dev), d, dt, nsnap,
+                                         newton_tol=newton_tol, uinf=u_d))
+        log("stage 1: snapshots of training point %d done" % k)
+    S = torch.cat(snaps)
     torch.cuda.synchronize()
     t["stage1_s"] = time.perf_counter() - t0
 
@@ -290,6 +296,7 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
         R.append(r)
         hists.append(h)
         its.append(i)
+        log("stage 3: tier II of training point %d done" % len(R))
     t["stage3_tier2_s"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     Phir_d, sig_r = pod(torch.cat(R), Mr)
