@@ -1000,30 +1000,36 @@ __global__ void __launch_bounds__(kRunThreads)
       for (int kb = 0; kb < nb; ++kb) {
         const int k0 = kb * 16;
         if (wave == 0) {
-          double a[16];
+          // lane (g, j) = 16 g + j holds column j of rows 4 g .. 4 g + 3; per
+          // pivot k, row k reaches every lane and column k every row group by
+          // lane permutes, and all 64 lanes update their four elements
+          const int j = lane & 15, g = lane >> 4;
+          double a[4];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) a[i] = lane < 16 ? T[(size_t)(k0 + i) * ldT + k0 + lane] : 0.0;
+          for (int r = 0; r < 4; ++r) a[r] = T[(size_t)(k0 + 4 * g + r) * ldT + k0 + j];
 #pragma unroll
           for (int k = 0; k < 16; ++k) {
-            const double piv = lane_d(a[k], k);
+            const int kg = k >> 2, kr = k & 3;
+            const double piv = lane_d(a[kr], 16 * kg + k);
             double ip = 0.0;
             if (piv > 0.0) {
               ip = __builtin_amdgcn_rcp(piv);
               ip = fma(ip, fma(-piv, ip, 1.0), ip);
               ip = fma(ip, fma(-piv, ip, 1.0), ip);
             }
-            const double rj = a[k];
+            const double rk = __shfl(a[kr], 16 * kg + j);  // a_kj
+            double ck[4];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-              if (i == k) continue;
-              const double ci = lane_d(a[i], k);
-              a[i] = lane == k ? -a[i] * ip : fma(-ci * ip, rj, a[i]);
+            for (int r = 0; r < 4; ++r) ck[r] = __shfl(a[r], 16 * g + k);  // a_ik, i = 4 g + r
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const bool row = 4 * g + r == k, col = j == k;
+              const double gen = fma(-ck[r] * ip, rk, a[r]);
+              a[r] = row ? (col ? ip : rk * ip) : (col ? -ck[r] * ip : gen);
             }
-            a[k] = lane == k ? ip : rj * ip;
           }
-          if (lane < 16)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) Pinv[i * 17 + lane] = a[i];
+          for (int r = 0; r < 4; ++r) Pinv[(4 * g + r) * 17 + j] = a[r];
         }
         __syncthreads();
         // row panel R = P^-1 T_K, (16 x Mp; the K block is not used)

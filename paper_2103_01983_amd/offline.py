@@ -38,23 +38,36 @@ def trapezoid_snapshots(xy0, gamma, delta, dt, nsnap, newton_tol=1e-6, uinf=None
 
 
 def pod(S, M, center=None):
-    """POD of the rows of S (device FP64 [k, nd]) by the method of snapshots.
-    Returns (Phi as device FP64 [M, nd] rows = modes, sigma [M] host); each
-    mode's sign makes its largest-magnitude entry positive."""
+    """POD of the rows of S (device FP64 [k, nd]): with fewer snapshots than
+    rows (k <= nd) by the method of snapshots (eigenvectors of the k x k Gram
+    S S^T, modes = S^T v / sigma, re-orthonormalised by CholeskyQR2); with
+    more, from the eigenvectors of the nd x nd Gram S^T S, which are the modes
+    themselves.  Returns (Phi as device FP64 [M, nd] rows = modes, sigma [M]
+    host); each mode's sign makes its largest-magnitude entry positive."""
     X = S if center is None else (S - center[None, :]).contiguous()
-    G = native.gram_f64(X).cpu().numpy()
-    w, V = np.linalg.eigh(G)
-    order = np.argsort(w)[::-1][:M]
-    sig = np.sqrt(np.maximum(w[order], 0.0))
-    if np.any(sig <= 0):
-        raise RuntimeError("snapshot matrix has rank < M")
-    T = torch.tensor(np.ascontiguousarray(V[:, order] / sig[None, :]), dtype=torch.float64, device=S.device)
-    Phi = native.combine_f64(X, T)
-    for _ in range(2):  # CholeskyQR2
-        G2 = native.gram_f64(Phi).cpu().numpy()
-        R = np.linalg.cholesky(G2).T
-        Rinv = torch.tensor(np.ascontiguousarray(np.linalg.inv(R)), dtype=torch.float64, device=S.device)
-        Phi = native.combine_f64(Phi, Rinv)
+    k, nd = X.shape
+    if k > nd:
+        G = native.gram_f64(X.t().contiguous()).cpu().numpy()
+        w, V = np.linalg.eigh(G)
+        order = np.argsort(w)[::-1][:M]
+        sig = np.sqrt(np.maximum(w[order], 0.0))
+        if np.any(sig <= 0):
+            raise RuntimeError("snapshot matrix has rank < M")
+        Phi = torch.tensor(np.ascontiguousarray(V[:, order].T), dtype=torch.float64, device=S.device)
+    else:
+        G = native.gram_f64(X).cpu().numpy()
+        w, V = np.linalg.eigh(G)
+        order = np.argsort(w)[::-1][:M]
+        sig = np.sqrt(np.maximum(w[order], 0.0))
+        if np.any(sig <= 0):
+            raise RuntimeError("snapshot matrix has rank < M")
+        T = torch.tensor(np.ascontiguousarray(V[:, order] / sig[None, :]), dtype=torch.float64, device=S.device)
+        Phi = native.combine_f64(X, T)
+        for _ in range(2):  # CholeskyQR2
+            G2 = native.gram_f64(Phi).cpu().numpy()
+            R = np.linalg.cholesky(G2).T
+            Rinv = torch.tensor(np.ascontiguousarray(np.linalg.inv(R)), dtype=torch.float64, device=S.device)
+            Phi = native.combine_f64(Phi, Rinv)
     # sign convention: each mode's entry of largest magnitude is positive
     # (lowest row on ties), which fixes W_phi and so the clustering
     P = Phi.cpu().numpy()
@@ -101,7 +114,7 @@ def reassign_host(art, gamma_mu):
     return np.array([g[ids[off[c]:off[c + 1]]].sum() for c in range(off.size - 1)])
 
 
-def tier2(art, nsteps, tol, max_iter, alpha=1.0, jac_mode=native.JAC_PAPER, device=None, record=True):
+def tier2(art, nsteps, tol, max_iter, alpha=1.0, jac_mode=native.JAC_PAPER, device=None, record=True, log=None):
     """Tier-II LSPG (no hyper-reduction) on the GPU gather: every body is a
     target, the weighting is the identity.  Same iteration as the online loop:
     HyperPair -> C, rbar -> d = argmin |C d - (-rbar)| -> xhat += alpha d, with the
@@ -144,6 +157,8 @@ def tier2(art, nsteps, tol, max_iter, alpha=1.0, jac_mode=native.JAC_PAPER, devi
                 break
         hist[step] = xh
         iters[step] = k - 1
+        if log and (step + 1) % 250 == 0:
+            log("tier II: step %d of %d" % (step + 1, nsteps))
         xbar_prev = tdev(xbar0 + Phibar @ xh)
         fbar_prev = fb.clone()
     rom.close()
@@ -292,13 +307,14 @@ def train_parametric(clouds, dt, nsnap, M, Mr, ns, depth=6, pc=1.0, tol=1e-4, ma
     for c in clouds:
         a = dict(full)
         a["Gt"] = reassign_host(full, np.asarray(c.gamma, np.float32).astype(np.float64))
-        r, h, i = tier2(a, nsnap, tol, max_iter, jac_mode=jac_mode, device=dev)
+        r, h, i = tier2(a, nsnap, tol, max_iter, jac_mode=jac_mode, device=dev, log=log)
         R.append(r)
         hists.append(h)
         its.append(i)
         log("stage 3: tier II of training point %d done" % len(R))
     t["stage3_tier2_s"] = time.perf_counter() - t0
     t0 = time.perf_counter()
+    log("stage 3: POD of %d residual snapshots" % sum(int(r.shape[0]) for r in R))
     Phir_d, sig_r = pod(torch.cat(R), Mr)
     Phi_r = np.ascontiguousarray(Phir_d.cpu().numpy().T)
     sample = greedy_sample(Phi_r, ns)
