@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(kRunThreads)
 // Gamma~ and the entries' surrogate ids.
 constexpr int kMaxTiles = 5;  // lower-triangle tiles of N' per wave
 constexpr int kPf = 5;        // A elements per thread prefetched a block ahead (n_d <= 160)
-static_assert(((kMaxM + 16) / 16) * ((kMaxM + 16) / 16 + 1) / 2 <= kMaxTiles * (kRunThreads / 64),
+static_assert(((kMaxM + 17) / 16) * ((kMaxM + 17) / 16 + 1) / 2 <= kMaxTiles * (kRunThreads / 64),
               "every lower-triangle tile of N' needs an owner");
 
 // LDS row strides chosen so that the 16 lanes of a quarter-wave reading one
@@ -731,15 +731,15 @@ struct BigLayout {
 
 __host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, int64_t nnz, int Nc) {
   (void)Mr;
-  const int M1 = M + 1, M1p = (M1 + 15) / 16 * 16, Mp = (M + 15) / 16 * 16;
+  const int M1p = (M + 2 + 15) / 16 * 16, Mp = (M + 15) / 16 * 16;
   BigLayout L;
   const size_t tab = (size_t)Mp * (Mp + 1);  // padded tableau, odd row stride
   const size_t ndp = (nd + 3) / 4 * 4, ldcf = c_stride(M1p);
-  const size_t crb = (ndp * ldcf + 1) / 2 + (ndp + 1) / 2;  // [C | rbar] in FP32 and rbar's low part
+  const size_t crb = (ndp * ldcf + 1) / 2;  // [C | rbar_hi | rbar_lo] in FP32
   L.r1 = crb > tab ? crb : tab;
   const size_t gather = 3 * (size_t)ns + nd + 2 * (size_t)Nc;
   const size_t blocks = 16 * (ndp + 1) + 16 * (size_t)M1p;
-  const size_t inv = 2 * 16 * (size_t)Mp + 16 * 17 + Mp;  // row / column panels, block inverse, g
+  const size_t inv = 2 * 16 * (size_t)Mp + 16 * 17 + 2 * (size_t)Mp;  // row / column panels, block inverse, g
   L.r2 = gather > blocks ? gather : blocks;
   L.r2 = L.r2 > inv ? L.r2 : inv;
   L.total = L.r1 + L.r2 + 3 * (size_t)nd + ((size_t)Nc + 1) / 2 + ((size_t)nnz + 1) / 2;
@@ -753,23 +753,26 @@ __global__ void __launch_bounds__(kRunThreads)
   __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
-  const int M = d.M, Mr = d.Mr, nd = d.nd, ns = d.ns, M1 = M + 1, M1p = (M1 + 15) / 16 * 16;
+  // columns of [C | rbar]: M of C, rbar's FP32 high part (M) and low part
+  // (M + 1), zeros up to M1p
+  const int M = d.M, Mr = d.Mr, nd = d.nd, ns = d.ns, M1p = (M + 2 + 15) / 16 * 16;
   const int nnz = (int)d.nnz;
   const double hdt = 0.5 * (double)d.dt;
   const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, d.Nc);
   double *R1 = dyn, *R2 = dyn + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
   // region 1: C (nd x M, FP32) and rbar (nd, FP64), then N (Mp x Mp, stride ldT)
-  // [C | rbar | 0] as FP32 (ndp rows of stride ldcf, zero padded), rbar = hi (column M) +
-  // lo (Rlo) so that the residual keeps its FP64 value to 2^-48
+  // [C | rbar_hi | rbar_lo | 0] as FP32 (ndp rows of stride ldcf, zero
+  // padded): the two parts of rbar keep its FP64 value to 2^-48, and A times
+  // their sum is the sum of the two product columns
   const int ndp = (nd + 3) / 4 * 4, ldcf = c_stride(M1p), lda = ndp + 1;
   float *Cf = reinterpret_cast<float *>(R1);
-  float *Rlo = Cf + (size_t)ndp * ldcf;
   double *T = R1;
   double *bt = R2, *pos = R2 + 3 * ns;           // gather phase: pos[0, nd) are the sampled rows
   double *Ab = R2, *Gb = R2 + 16 * (size_t)lda;  // product phase (A block rows of stride lda)
   const int Mp = (M + 15) / 16 * 16, ldT = Mp + 1;
-  double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp, *gb = Pinv + 16 * 17;  // inversion
+  double *Rp = R2, *Cpn = R2 + 16 * (size_t)Mp, *Pinv = Cpn + 16 * (size_t)Mp;  // inversion
+  double *gb = Pinv + 16 * 17, *gb2 = gb + Mp;  // g from rbar's high and low parts
   xhat += (size_t)blockIdx.x * M;
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
   if (iters) iters += (size_t)blockIdx.x * nsteps;
@@ -845,9 +848,9 @@ __global__ void __launch_bounds__(kRunThreads)
             const double r1 = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
             const float h0 = (float)r0, h1 = (float)r1;
             Cf[(size_t)t * ldcf + M] = h0;
-            Rlo[t] = (float)(r0 - (double)h0);
+            Cf[(size_t)t * ldcf + M + 1] = (float)(r0 - (double)h0);
             Cf[(size_t)(ns + t) * ldcf + M] = h1;
-            Rlo[ns + t] = (float)(r1 - (double)h1);
+            Cf[(size_t)(ns + t) * ldcf + M + 1] = (float)(r1 - (double)h1);
             bt[3 * t] = s2 * kInv2PiD;
             bt[3 * t + 1] = s3 * kInv2PiD;
             bt[3 * t + 2] = s4 * kInv2PiD;
@@ -876,12 +879,11 @@ __global__ void __launch_bounds__(kRunThreads)
         Cf[(size_t)row * ldcf + m] = (float)(row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py));
       }
       // zero padding: columns past M, rows past nd (and their low parts)
-      for (int q = tid; q < nd * (M1p - M1); q += kRunThreads) {
-        const int row = q / (M1p - M1);
-        Cf[(size_t)row * ldcf + M1 + (q - row * (M1p - M1))] = 0.0f;
+      for (int q = tid; q < nd * (M1p - M - 2); q += kRunThreads) {
+        const int row = q / (M1p - M - 2);
+        Cf[(size_t)row * ldcf + M + 2 + (q - row * (M1p - M - 2))] = 0.0f;
       }
       for (int q = tid; q < (ndp - nd) * ldcf; q += kRunThreads) Cf[(size_t)nd * ldcf + q] = 0.0f;
-      for (int q = nd + tid; q < ndp; q += kRunThreads) Rlo[q] = 0.0f;
       // N' = G'^T G' over 16-row blocks of A (the gather's LDS is free now)
       dbl4 acc[kMaxTiles];
 #pragma unroll
@@ -919,8 +921,6 @@ __global__ void __launch_bounds__(kRunThreads)
           const int j0 = tj * 16, r = lane & 15, kq = lane >> 4;
           const double *ap = Ab + (size_t)r * lda + kq;
           const float *cp = Cf + (size_t)kq * ldcf + j0 + r;
-          const float *lp = Rlo + kq;
-          const bool rcol = j0 + r == M;
           dbl4 g = dbl4{0.0, 0.0, 0.0, 0.0}, g1 = g, g2 = g, g3 = g;  // independent chains
           int k0 = 0;
           for (; k0 + 16 <= ndp; k0 += 16) {
@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(kRunThreads)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               a[u] = ap[k0 + 4 * u];
-              b[u] = (double)cp[(size_t)(k0 + 4 * u) * ldcf] + (rcol ? (double)lp[k0 + 4 * u] : 0.0);
+              b[u] = (double)cp[(size_t)(k0 + 4 * u) * ldcf];
             }
             g = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], g, 0, 0, 0);
             g1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], g1, 0, 0, 0);
@@ -937,7 +937,7 @@ __global__ void __launch_bounds__(kRunThreads)
           }
           for (; k0 < ndp; k0 += 4) {
             const double a = ap[k0];
-            const double b = (double)cp[(size_t)k0 * ldcf] + (rcol ? (double)lp[k0] : 0.0);
+            const double b = (double)cp[(size_t)k0 * ldcf];
             g = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, g, 0, 0, 0);
           }
           g = (g + g1) + (g2 + g3);
@@ -979,7 +979,9 @@ __global__ void __launch_bounds__(kRunThreads)
               T[(size_t)row * ldT + col] = v;
               T[(size_t)col * ldT + row] = v;
             } else if (row == M && col < M) {
-              gb[col] = v;  // g = G^T b
+              gb[col] = v;  // g = G^T b, b from rbar_hi
+            } else if (row == M + 1 && col < M) {
+              gb2[col] = v;  // and from rbar_lo
             }
           }
         }
@@ -987,7 +989,10 @@ __global__ void __launch_bounds__(kRunThreads)
       __syncthreads();
       if (wave == 0) {
         double sq = 0.0;
-        for (int i = lane; i < M; i += 64) sq += gb[i] * gb[i];
+        for (int i = lane; i < M; i += 64) {
+          gb[i] += gb2[i];
+          sq += gb[i] * gb[i];
+        }
         const double gn = sqrt(wsumd(sq));
         if (lane == 0) s_gn = gn;
       }
