@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,rom)")
+    p.add_argument("--gather-ns", default="16,256,2048,16384",
+                   help="sample-set sizes of the HyperPair gather sweep (rom form)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (HBM counter calibration)")
     return p.parse_args()
@@ -157,7 +159,8 @@ def main():
 
     if not args.no_forms:
         only = set(s for s in args.only.split(",") if s)
-        out["forms"] = run_forms(native, W, dev, only, pairs / (vel_ms * 1e-3))
+        out["forms"] = run_forms(native, W, dev, only, pairs / (vel_ms * 1e-3),
+                                 tuple(int(v) for v in args.gather_ns.split(",") if v))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cl, f, native, x0, g, d)
@@ -240,7 +243,7 @@ def traffic_for(op, cfg):
     return ent.get("bytes_per_launch")
 
 
-def run_forms(native, W, dev, only, plain_pairs_per_s):
+def run_forms(native, W, dev, only, plain_pairs_per_s, gather_ns=(16, 256, 2048, 16384)):
     import torch
     forms = {"plain_velocity_pairs_per_s": plain_pairs_per_s}
     stream = torch.cuda.current_stream(dev)
@@ -307,13 +310,13 @@ def run_forms(native, W, dev, only, plain_pairs_per_s):
     if not only or "rom" in only:
         log("form: rom")
         try:
-            forms["rom"] = rom_form(native, W, dev, timed)
+            forms["rom"] = rom_form(native, W, dev, timed, gather_ns)
         except Exception as e:  # reported, not fatal to the headline line
             forms["rom"] = {"error": repr(e)}
     return forms
 
 
-def rom_form(native, W, dev, timed):
+def rom_form(native, W, dev, timed, gather_ns=(16, 256, 2048, 16384)):
     import torch
     from paper_2103_01983_amd import offline
     c3 = W.CONFIGS["c3_ptrom_pipeline"]
@@ -347,11 +350,11 @@ def rom_form(native, W, dev, timed):
     res["mae_d_time_avg"] = float(np.mean(mae))
     res["mae_d_final"] = float(mae[-1])
     res["final_rel_state_err"] = float(np.linalg.norm(xr[-1] - S[-1]) / np.linalg.norm(S[-1] - x0))
-    res["gather_sweep"] = gather_sweep(native, offline, info, cl, art, dev, timed)
+    res["gather_sweep"] = gather_sweep(native, offline, info, cl, art, dev, timed, gather_ns)
     return res
 
 
-def gather_sweep(native, offline, info, cl, art, dev, timed):
+def gather_sweep(native, offline, info, cl, art, dev, timed, sizes=(16, 256, 2048, 16384)):
     """HyperPair gather over growing sample sets (random bodies; same tree,
     basis and clustering): HBM bytes streamed per evaluation / time."""
     import torch
@@ -360,7 +363,7 @@ def gather_sweep(native, offline, info, cl, art, dev, timed):
     xy0 = np.asarray(cl.xy, np.float32).astype(np.float64)
     g = np.asarray(cl.gamma, np.float32).astype(np.float64)
     out = []
-    for ns in (16, 256, 2048, 16384):
+    for ns in sizes:
         sample = np.arange(n) if ns >= n else np.sort(rng.choice(n, ns, replace=False))
         A = np.zeros((art["M"], 2 * sample.size))
         a = offline.artifacts(sample, info["wpts"], xy0, info["Phi"], g, 6, 1.0, cl.delta, art["dt"], A)
