@@ -318,3 +318,94 @@ def test_small_path_inflow_parity(dev, trained, mode):
     rom.run(steps, x, hist, None)
     torch.cuda.synchronize()
     assert rel(hist.cpu().numpy().reshape(steps, 8), o["hist"]) <= 1e-5
+
+
+# ------------------------------------------------------------ edges of the blocked path
+
+EDGE = [(33, 33, 17), (20, 65, 40), (112, 120, 61)]
+
+
+@pytest.fixture(scope="module")
+def edge_shapes():
+    """Just past the small kernel (M = 33; M_r = 65 with M = 20), the largest
+    basis (M = 112) and odd n_s (n_d not a multiple of 4), plus a shape whose
+    arrays exceed one workgroup's LDS (M = 112, M_r = 256, n_s = 128)."""
+    out = {}
+    cl = W.counter_rotating_patches(640, seed=43, delta=0.02)
+    n = cl.n
+    rng = np.random.default_rng(45)
+    for M, Mr, ns in EDGE + [(112, 256, 128)]:
+        Phi = np.linalg.qr(rng.standard_normal((2 * n, M)))[0]
+        sig = np.sort(rng.uniform(1.0, 10.0, M))[::-1]
+        tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+        sample = np.sort(rng.choice(n, ns, replace=False))
+        Phi_r = np.linalg.qr(rng.standard_normal((2 * n, Mr)))[0]
+        A = off.gappy_operator(Phi_r, sample)
+        out[(M, Mr, ns)] = rounded(off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A))
+    return out
+
+
+def _hyperpair_check(dev, art, seed):
+    M, nd = int(art["M"]), 2 * (len(art["off"]) - 1)
+    rng = np.random.default_rng(seed)
+    xh = rng.standard_normal(M) * 0.02
+    xp, fp = rng.standard_normal(nd) * 0.1 + art["xbar0"], rng.standard_normal(nd) * 0.1
+    xb, fb, rb, C = oracle.Rom(art).hyperpair(xh, xp, fp)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    gx, gf, gr, gC = native.Rom(art).hyperpair(t(xh), t(xp), t(fp))
+    assert rel(gx.cpu().numpy(), xb) <= 1e-14
+    assert rel(gf.cpu().numpy(), fb) <= 1e-5
+    assert rel(gr.cpu().numpy(), rb) <= 1e-5
+    assert rel(gC.cpu().numpy() - art["Phibar"], C - art["Phibar"]) <= 1e-5
+
+
+def _run_check(dev, art, steps=6, K=3):
+    M = int(art["M"])
+    o = oracle.Rom(art).run(steps, tol=0.0, max_iter=K)
+    rom = native.Rom(art, tol=0.0, max_iter=K)
+    xh = torch.zeros(M, dtype=torch.float64, device=dev)
+    hist = torch.empty(steps * M, dtype=torch.float64, device=dev)
+    it = torch.empty(steps, dtype=torch.int32, device=dev)
+    rom.run(steps, xh, hist, it)
+    torch.cuda.synchronize()
+    assert np.all(it.cpu().numpy() == K)
+    h = hist.cpu().numpy().reshape(steps, M)
+    assert np.all(np.isfinite(h))
+    assert rel(h, o["hist"]) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", EDGE)
+def test_edge_shapes_parity(dev, edge_shapes, shape):
+    _hyperpair_check(dev, edge_shapes[shape], 7)
+    _run_check(dev, edge_shapes[shape])
+
+
+def test_largest_shape_over_lds_is_rejected(dev, edge_shapes):
+    # the gather entry point has no LDS limit; the online run refuses arrays
+    # that do not fit one workgroup
+    art = edge_shapes[(112, 256, 128)]
+    _hyperpair_check(dev, art, 8)
+    rom = native.Rom(art, tol=0.0, max_iter=2)
+    xh = torch.zeros(112, dtype=torch.float64, device=dev)
+    with pytest.raises(native.PtromError, match="LDS"):
+        rom.run(1, xh, None, None)
+
+
+def _drop_list(art, t):
+    """The artifacts with target t's interaction list emptied."""
+    a = dict(art)
+    off_, ids = np.asarray(art["off"]), np.asarray(art["ids"])
+    a["ids"] = np.concatenate([ids[:off_[t]], ids[off_[t + 1]:]])
+    a["off"] = np.concatenate([off_[:t + 1], off_[t + 1:] - (off_[t + 1] - off_[t])])
+    return a
+
+
+def test_empty_list_parity(dev, trained, large_shapes):
+    # a target whose list is empty feels no velocity and no 2 x 2 block; both
+    # kernels and the gather entry point take it like the oracle
+    cl, art_small, ex = trained
+    for art in (art_small, large_shapes[(48, 96, 48)]):
+        a = _drop_list(art, 1)
+        assert a["off"][1] == a["off"][2]
+        _hyperpair_check(dev, a, 9)
+        _run_check(dev, a)
