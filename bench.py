@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,rom)")
+    p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,rom,next)")
     p.add_argument("--gather-ns", default="16,256,2048,16384",
                    help="sample-set sizes of the HyperPair gather sweep (rom form)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -313,7 +313,80 @@ def run_forms(native, W, dev, only, plain_pairs_per_s, gather_ns=(16, 256, 2048,
             forms["rom"] = rom_form(native, W, dev, timed, gather_ns)
         except Exception as e:  # reported, not fatal to the headline line
             forms["rom"] = {"error": repr(e)}
+    if not only or "next" in only:
+        log("form: next")
+        try:
+            forms["next"] = next_rows(native, W, dev, timed)
+        except Exception as e:
+            forms["next"] = {"error": repr(e)}
     return forms
+
+
+# FLOP per pair of the stream-function term: separation (2), |r|^2 + delta^2
+# (2 FMA), log2 (1), Gamma log2 FMA (2)
+PSI_FLOP_PER_PAIR = 9
+
+
+def next_rows(native, W, dev, timed):
+    """The widened rows on their own workloads: the log-kernel stream
+    function over the C2 patch, the velocity at a 256 x 256 grid of field
+    points from the same bodies, and the C3 pipeline clustered by the
+    Barnes-Hut criterion instead of the neighbour overlap test."""
+    import torch
+    from paper_2103_01983_amd import offline
+    out = {}
+    c2 = W.CONFIGS["c2_gaussian_patch"]
+    cl = W.config_cloud("c2_gaussian_patch")
+    n = cl.n
+    x = torch.tensor(cl.xy, dtype=torch.float32, device=dev)
+    g = torch.tensor(cl.gamma, dtype=torch.float32, device=dev)
+    psi = torch.empty_like(g)
+    native.stream_function(x, g, c2["delta"], psi)
+    sec = timed(lambda: native.stream_function(x, g, c2["delta"], psi), reps=10)
+    pairs = float(n) * (n - 1)
+    out["stream_function"] = {"N": n, "launch_ms": sec * 1e3, "pairs_per_s": pairs / sec,
+                              "tflops": PSI_FLOP_PER_PAIR * pairs / sec / 1e12, "flop_per_pair": PSI_FLOP_PER_PAIR,
+                              "frac_of_157_3": PSI_FLOP_PER_PAIR * pairs / sec / 157.3e12}
+    side = 256
+    gx = np.linspace(-1.0, 1.0, side)
+    pts = np.concatenate([np.tile(gx, side), np.repeat(gx, side)])
+    P = torch.tensor(pts, dtype=torch.float32, device=dev)
+    fv = torch.empty_like(P)
+    native.velocity_points(P, x, g, c2["delta"], fv)
+    sec = timed(lambda: native.velocity_points(P, x, g, c2["delta"], fv), reps=10)
+    pp = float(side * side) * n
+    out["velocity_points"] = {"points": side * side, "N": n, "launch_ms": sec * 1e3, "pairs_per_s": pp / sec,
+                              "tflops": 12 * pp / sec / 1e12}
+    c3 = W.CONFIGS["c3_ptrom_pipeline"]
+    cl3 = W.config_cloud("c3_ptrom_pipeline")
+    for crit, theta in ((native.NEIGHBOR, 0.0), (native.BARNES_HUT, 0.5)):
+        t0 = time.perf_counter()
+        art, info = offline.train(cl3, dt=c3["dt"], nsnap=c3["snapshots"], M=c3["M"], Mr=c3["Mr"], ns=c3["ns"],
+                                  depth=c3["depth"], pc=c3["pc"], tol=c3["tol"], max_iter=c3["max_iter"], device=dev,
+                                  criterion=crit, theta=theta)
+        t_off = time.perf_counter() - t0
+        rom = native.Rom(art, tol=c3["tol"], max_iter=c3["max_iter"])
+        steps = c3["steps"]
+        xh = torch.zeros(art["M"], dtype=torch.float64, device=dev)
+        hist = torch.empty(steps * art["M"], dtype=torch.float64, device=dev)
+        it = torch.empty(steps, dtype=torch.int32, device=dev)
+        rom.run(2, xh, None, None)
+        xh.zero_()
+        sec = timed(lambda: rom.run(steps, xh, hist, it))
+        its = it.cpu().numpy()
+        Phi, S = info["Phi"], info["S"]
+        x0 = np.asarray(cl3.xy, np.float32).astype(np.float64)
+        m = cl3.n
+        length = float(np.hypot(x0[m - 1] - x0[0], x0[2 * m - 1] - x0[m]))
+        xr = x0[None, :] + hist.cpu().numpy().reshape(steps, -1) @ Phi.T
+        mae = [offline.mae_distance(xr[t], S[t], m, length) for t in range(min(steps, S.shape[0]))]
+        key = "c3_neighbor" if crit == native.NEIGHBOR else "c3_barnes_hut_theta_0_5"
+        out[key] = {"Nc": int(np.asarray(art["Gt"]).size), "nnz": int(np.asarray(art["ids"]).size),
+                    "tier2_nnz": info["report"].get("tier2_nnz"), "offline_seconds": t_off,
+                    "us_per_gn_iteration": 1e6 * sec / max(int(its.sum()), 1),
+                    "mean_gn_iterations": float(its.mean()), "mae_d_time_avg": float(np.mean(mae))}
+        rom.close()
+    return out
 
 
 def rom_form(native, W, dev, timed, gather_ns=(16, 256, 2048, 16384)):

@@ -137,7 +137,11 @@ extern "C" int ptrom_velocity_points(ptrom_ctx *ctx, int64_t nt, const float *p,
   if (int rc = check_common(ctx, n, delta)) return rc;
   if (nt < 1 || nt > kMaxN) return ctx->fail(PTROM_EINVAL, "nt must be in [1, 2^30]");
   if (!p || !xy || !gamma || !f) return ctx->fail(PTROM_EINVAL, "NULL array");
-  hipError_t e = launch_velocity_points(nt, p, n, xy, gamma, delta, f, (hipStream_t)stream);
+  const size_t wsf = points_ws_floats(ctx->num_cus, nt, n);
+  if (wsf)
+    if (int rc = ctx->reserve(wsf * sizeof(float))) return rc;
+  hipError_t e = launch_velocity_points(nt, p, n, xy, gamma, delta, f, static_cast<float *>(ctx->ws),
+                                        ctx->ws_bytes / sizeof(float), ctx->num_cus, (hipStream_t)stream);
   if (e != hipSuccess) return ctx->hip_fail(e, "points velocity launch");
   return PTROM_OK;
 }

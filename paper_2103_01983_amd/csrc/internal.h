@@ -61,8 +61,11 @@ hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64
                            float *ws, size_t ws_floats, hipStream_t stream);
 
 // velocity at nt arbitrary points p [2][nt] from all n bodies (no exclusion)
-hipError_t launch_velocity_points(int64_t nt, const float *p, int64_t n, const float *xy,
-                                  const float *gamma, float delta, float *out, hipStream_t stream);
+int points_splits(int num_cus, int64_t nt, int64_t n);
+size_t points_ws_floats(int num_cus, int64_t nt, int64_t n);
+hipError_t launch_velocity_points(int64_t nt, const float *p, int64_t n, const float *xy, const float *gamma,
+                                  float delta, float *out, float *ws, size_t ws_floats, int num_cus,
+                                  hipStream_t stream);
 
 hipError_t launch_velocity_f64(int64_t n, const double *xy, const double *gamma, double delta,
                                double *f, hipStream_t stream);

@@ -72,12 +72,19 @@ int nacc(int op) {
   }
 }
 
-// Velocity at arbitrary points: K = 2 points per lane, sources read at
-// wave-uniform addresses, 256-source tiles added with Kahan compensation.
+// Velocity at arbitrary points: kPtsK points per lane, sources read at
+// wave-uniform addresses (full tiles unrolled so the scalar loads batch),
+// 256-source tiles added with Kahan compensation.
+// blockIdx.y takes sources [y chunk, (y + 1) chunk); with several chunks
+// each writes its unscaled partial sums to out[(2 y + a) nt + t], added in
+// chunk order by reduce_kernel<OP_VEL>.
+constexpr int kPtsK = 4;  // field points per lane
+
 __global__ void __launch_bounds__(kBlock)
     points_velocity_kernel(int nt, const float *__restrict__ p, int n, const float *__restrict__ xy,
-                           const float *__restrict__ gam, float d2, float *__restrict__ out) {
-  constexpr int K = 2;
+                           const float *__restrict__ gam, float d2, int chunk, int partial,
+                           float *__restrict__ out) {
+  constexpr int K = kPtsK;
   float tg[K][2];
   const int t0 = blockIdx.x * (kBlock * K);
 #pragma unroll
@@ -88,13 +95,23 @@ __global__ void __launch_bounds__(kBlock)
     tg[k][1] = p[nt + tc];
   }
   float sum[K][2] = {}, cmp[K][2] = {};
-  for (int ts = 0; ts < n; ts += kTile) {
-    const int cnt = min(kTile, n - ts);
+  const int sb = blockIdx.y * chunk, se = min(n, sb + chunk);
+  for (int ts = sb; ts < se; ts += kTile) {
+    const int cnt = min(kTile, se - ts);
     float part[K][2] = {};
-    for (int jj = 0; jj < cnt; ++jj) {
-      const float s[3] = {xy[ts + jj], xy[n + ts + jj], gam[ts + jj]};
+    if (cnt == kTile) {
+#pragma unroll 4
+      for (int jj = 0; jj < kTile; ++jj) {
+        const float s[3] = {xy[ts + jj], xy[n + ts + jj], gam[ts + jj]};
 #pragma unroll
-      for (int k = 0; k < K; ++k) interact<OP_VEL, false>(tg[k], s, d2, part[k], false);
+        for (int k = 0; k < K; ++k) interact<OP_VEL, false>(tg[k], s, d2, part[k], false);
+      }
+    } else {
+      for (int jj = 0; jj < cnt; ++jj) {
+        const float s[3] = {xy[ts + jj], xy[n + ts + jj], gam[ts + jj]};
+#pragma unroll
+        for (int k = 0; k < K; ++k) interact<OP_VEL, false>(tg[k], s, d2, part[k], false);
+      }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -106,8 +123,13 @@ __global__ void __launch_bounds__(kBlock)
   for (int k = 0; k < K; ++k) {
     const int t = t0 + k * kBlock + threadIdx.x;
     if (t < nt) {
-      out[t] = (sum[k][0] - cmp[k][0]) * kInv2Pi;
-      out[nt + t] = (sum[k][1] - cmp[k][1]) * kInv2Pi;
+      if (partial) {
+        out[(size_t)(2 * blockIdx.y) * nt + t] = sum[k][0] - cmp[k][0];
+        out[(size_t)(2 * blockIdx.y + 1) * nt + t] = sum[k][1] - cmp[k][1];
+      } else {
+        out[t] = (sum[k][0] - cmp[k][0]) * kInv2Pi;
+        out[nt + t] = (sum[k][1] - cmp[k][1]) * kInv2Pi;
+      }
     }
   }
 }
@@ -261,10 +283,35 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, con
   return hipGetLastError();
 }
 
-hipError_t launch_velocity_points(int64_t nt, const float *p, int64_t n, const float *xy,
-                                  const float *gamma, float delta, float *out, hipStream_t stream) {
-  hipLaunchKernelGGL(points_velocity_kernel, dim3((unsigned)((nt + 2 * kBlock - 1) / (2 * kBlock))), dim3(kBlock),
-                     0, stream, int(nt), p, int(n), xy, gamma, delta * delta, out);
+// Source chunks for the field-point kernel: enough workgroups for 16 waves
+// per CU, whole 256-source tiles per chunk.
+int points_splits(int num_cus, int64_t nt, int64_t n) {
+  const int64_t blocks_x = (nt + kPtsK * kBlock - 1) / (kPtsK * kBlock);
+  const int64_t want_waves = int64_t(num_cus) * 16;
+  int64_t s = (want_waves + blocks_x * 4 - 1) / (blocks_x * 4);
+  const int64_t max_s = (n + kTile - 1) / kTile;
+  s = std::max<int64_t>(1, std::min(s, max_s));
+  const int64_t chunk = ((n + s - 1) / s + kTile - 1) / kTile * kTile;
+  return int((n + chunk - 1) / chunk);
+}
+
+size_t points_ws_floats(int num_cus, int64_t nt, int64_t n) {
+  const int s = points_splits(num_cus, nt, n);
+  return s > 1 ? size_t(s) * 2 * size_t(nt) : 0;
+}
+
+hipError_t launch_velocity_points(int64_t nt, const float *p, int64_t n, const float *xy, const float *gamma,
+                                  float delta, float *out, float *ws, size_t ws_floats, int num_cus,
+                                  hipStream_t stream) {
+  const int s = points_splits(num_cus, nt, n);
+  const int64_t chunk = ((n + s - 1) / s + kTile - 1) / kTile * kTile;
+  if (s > 1 && ws_floats < size_t(s) * 2 * size_t(nt)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((nt + kPtsK * kBlock - 1) / (kPtsK * kBlock)), s);
+  hipLaunchKernelGGL(points_velocity_kernel, grid, dim3(kBlock), 0, stream, int(nt), p, int(n), xy, gamma,
+                     delta * delta, int(chunk), s > 1 ? 1 : 0, s > 1 ? ws : out);
+  if (s == 1) return hipGetLastError();
+  hipLaunchKernelGGL(reduce_kernel<OP_VEL>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, int(nt), s, ws,
+                     out, nullptr);
   return hipGetLastError();
 }
 

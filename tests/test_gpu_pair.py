@@ -136,9 +136,28 @@ def test_stream_function_parity(dev, n, delta):
     assert abs(H - Ho) <= 1e-5 * abs(Ho)
 
 
-def test_velocity_points_parity(dev):
-    xy, g, d = cloud(3000, 77, "disk", 0.01)
+@pytest.mark.parametrize("n, nt", [(3000, 1000), (1025, 777), (256, 1)])
+def test_velocity_points_parity(dev, n, nt):
+    # source chunks split across workgroups (ragged last chunk, a single
+    # point, a single source tile)
+    xy, g, d = cloud(n, 77, "disk", 0.01)
     rng = np.random.default_rng(5)
-    pts = f32(np.concatenate([rng.uniform(-1.2, 1.2, 1000), rng.uniform(-1.2, 1.2, 1000)]))
+    pts = f32(np.concatenate([rng.uniform(-1.2, 1.2, nt), rng.uniform(-1.2, 1.2, nt)]))
     f = native.velocity_points(to_dev(pts, dev), to_dev(xy, dev), to_dev(g, dev), d).cpu().numpy()
     assert rel(f, oracle.velocity_points(pts, xy, g, float(d))) <= 1e-5
+
+
+def test_velocity_points_grid_full_size(dev):
+    # the 256 x 256 field grid over the N = 65536 Gaussian patch, checked on
+    # 512 sampled points
+    c = W.config_cloud("c2_gaussian_patch")
+    xy, g = f32(c.xy), f32(c.gamma)
+    side = 256
+    gx = np.linspace(-1.0, 1.0, side)
+    pts = f32(np.concatenate([np.tile(gx, side), np.repeat(gx, side)]))
+    f = native.velocity_points(to_dev(pts, dev), to_dev(xy, dev), to_dev(g, dev), c.delta).cpu().numpy()
+    idx = np.random.default_rng(6).choice(side * side, 512, replace=False)
+    sub = np.concatenate([pts[:side * side][idx], pts[side * side:][idx]])
+    want = oracle.velocity_points(sub, xy, g, float(np.float32(c.delta)))
+    got = np.concatenate([f[:side * side][idx], f[side * side:][idx]])
+    assert rel(got, want) <= 1e-5

@@ -112,3 +112,46 @@ def test_batched_rejects_oversized(dev):
     with pytest.raises(native.PtromError):
         rom.run_batched(gt, 2, xq)
     rom.close()
+
+
+@pytest.fixture(scope="module")
+def mushroom():
+    # a small mushroom cloud (opposite end circulations, inflow) trained by
+    # the oracle pipeline at two parameters
+    n = 64
+    mus = [(-50.0, 40.0), (-30.0, 60.0)]
+    clouds = [W.mushroom_cloud(m, n=n, half=4.8, delta=0.15) for m in mus]
+    u = W.mushroom_inflow(n)
+    art, ex = off.train_parametric(clouds, 0.005, 40, M=16, Mr=32, ns=24, depth=6, pc=1.0, tol=1e-6, u=u)
+    a = dict(art)
+    for k in ("Phibar", "xbar0", "xqt0", "Phit", "Gt"):
+        a[k] = f32(art[k])
+    a["delta"] = float(np.float32(art["delta"]))
+    a["dt"] = float(np.float32(art["dt"]))
+    mem = art["members"]
+    a["mem_off"] = np.concatenate([[0], np.cumsum([len(m) for m in mem])])
+    a["mem_ids"] = np.concatenate([np.asarray(m) for m in mem])
+    a["n"] = n
+    queries = np.array([(-50.0, 40.0), (-60.0, 30.0), (-35.0, 55.0)])
+    return a, ex, queries
+
+
+def test_batched_inflow_queries_match_oracle(dev, mushroom):
+    a, ex, queries = mushroom
+    assert "ubar" in a
+    M, steps, K = a["M"], 20, 3
+    rom = native.Rom(a, tol=0.0, max_iter=K)
+    G = np.stack([f32(W.mushroom_cloud(q, n=64, half=4.8, delta=0.15).gamma) for q in queries])
+    gt = rom.reassign(torch.tensor(G, dtype=torch.float32, device=dev))
+    nq = len(queries)
+    xq = torch.zeros((nq, M), dtype=torch.float64, device=dev)
+    hq = torch.empty((nq, steps, M), dtype=torch.float64, device=dev)
+    rom.run_batched(gt, steps, xq, hq, None)
+    torch.cuda.synchronize()
+    gth = gt.cpu().numpy().astype(np.float64)
+    for q in range(nq):
+        aq = dict(a)
+        aq["Gt"] = gth[q]
+        o = oracle.Rom(aq).run(steps, tol=0.0, max_iter=K)
+        assert rel(hq[q].cpu().numpy(), o["hist"]) <= 1e-5, q
+    rom.close()
