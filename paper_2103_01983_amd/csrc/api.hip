@@ -63,6 +63,7 @@ extern "C" void ptrom_destroy(ptrom_ctx *ctx) {
   for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
   delete ctx;
 }
 

@@ -87,6 +87,10 @@ __global__ void lincomb_kernel(int64_t m, float *__restrict__ out, const float *
 
 inline dim3 g1(int64_t m) { return dim3((unsigned)((m + 255) / 256)); }
 
+// Matrix-free GMRES for (I - c J(xi)) d = b.  The Gram-Schmidt coefficients
+// stay on the device (the projections read them there); the host takes one
+// copy per Arnoldi step (both coefficient sets and |w|^2, into pinned memory)
+// for the Hessenberg column, the Givens rotations and the convergence test.
 struct Solver {
   ptrom_ctx *ctx;
   hipStream_t st;
@@ -97,7 +101,9 @@ struct Solver {
   float *pws;
   size_t pwsf;
   float *xi, *tmp, *w, *V;
-  double *dev_dots, *host_dots, *dot_part;
+  double *dd;     // device: coefficients [restart + 1] twice and |w|^2, then y [restart]
+  double *hp;     // pinned host: the same layout
+  double *dot_part;
   int restart;
 
   // w = (I - c J(xi)) v
@@ -109,18 +115,23 @@ struct Solver {
     return PTROM_OK;
   }
 
-  int dots(const float *X, int nvec, const float *y, double *host) {
+  // dev[v] = X_v . y for v < nvec (stays on the device)
+  void dots(const float *X, int nvec, const float *y, double *dev) {
     hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotParts, nvec), dim3(256), 0, st, m, X, m, y, dot_part);
-    hipLaunchKernelGGL(dot_final_kernel, dim3(nvec), dim3(kDotParts), 0, st, dot_part, dev_dots);
-    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(host, dev_dots, sizeof(double) * nvec, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(dot_final_kernel, dim3(nvec), dim3(kDotParts), 0, st, dot_part, dev);
+  }
+
+  // host[0, count) = dev[0, count), then wait
+  int fetch(const double *dev, double *host, int count) {
+    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, st));
     PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
     return PTROM_OK;
   }
 
   int norm(const float *y, double *out) {
-    double h;
-    if (int rc = dots(y, 1, y, &h)) return rc;
-    *out = std::sqrt(h);
+    dots(y, 1, y, dd);
+    if (int rc = fetch(dd, hp, 1)) return rc;
+    *out = std::sqrt(hp[0]);
     return PTROM_OK;
   }
 
@@ -131,8 +142,9 @@ struct Solver {
     if (int rc = norm(b, &bn)) return rc;
     hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, d, b, 0.0f);
     if (bn == 0.0) return PTROM_OK;
-    std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
-    std::vector<double> h1(restart + 1), h2(restart + 1);
+    const int R = restart;
+    double *d1 = dd, *d2 = dd + (R + 1), *dy = dd + 2 * (R + 1) + 1, *hy = hp + 2 * (R + 1) + 1;
+    std::vector<double> H((R + 1) * R), cs(R), sn(R), g(R + 1), y(R);
     bool first = true;
     while (*used < maxit) {
       // V0 = residual / |residual|
@@ -153,34 +165,35 @@ struct Solver {
       g[0] = beta;
       int k = 0;
       bool done = false;
-      for (; k < restart && *used < maxit; ++k) {
+      for (; k < R && *used < maxit; ++k) {
         float *vk = V + (size_t)k * m;
         if (int rc = apply(vk, c, w)) return rc;
         ++*used;
-        // classical Gram-Schmidt, applied twice
-        if (int rc = dots(V, k + 1, w, h1.data())) return rc;
-        PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dev_dots, h1.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, dev_dots, -1.0f, w);
-        if (int rc = dots(V, k + 1, w, h2.data())) return rc;
-        PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dev_dots, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, dev_dots, -1.0f, w);
-        double hn;
-        if (int rc = norm(w, &hn)) return rc;
-        for (int i = 0; i <= k; ++i) H[i * restart + k] = h1[i] + h2[i];
-        H[(k + 1) * restart + k] = hn;
+        // classical Gram-Schmidt, applied twice, coefficients on the device
+        dots(V, k + 1, w, d1);
+        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d1, -1.0f, w);
+        dots(V, k + 1, w, d2);
+        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d2, -1.0f, w);
+        dots(w, 1, w, d2 + (k + 1));
+        // one copy covering d1 [0, k], d2 [0, k] and |w|^2 (d2 starts at R + 1)
+        if (int rc = fetch(dd, hp, R + k + 3)) return rc;
+        const double *h1 = hp, *h2 = hp + (R + 1);
+        const double hn = std::sqrt(h2[k + 1]);
+        for (int i = 0; i <= k; ++i) H[i * R + k] = h1[i] + h2[i];
+        H[(k + 1) * R + k] = hn;
         if (hn > 0.0)
           hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V + (size_t)(k + 1) * m, w, float(1.0 / hn));
         for (int i = 0; i < k; ++i) {
-          const double a = H[i * restart + k], bb = H[(i + 1) * restart + k];
-          H[i * restart + k] = cs[i] * a + sn[i] * bb;
-          H[(i + 1) * restart + k] = -sn[i] * a + cs[i] * bb;
+          const double a = H[i * R + k], bb = H[(i + 1) * R + k];
+          H[i * R + k] = cs[i] * a + sn[i] * bb;
+          H[(i + 1) * R + k] = -sn[i] * a + cs[i] * bb;
         }
-        const double a = H[k * restart + k], bb = H[(k + 1) * restart + k];
+        const double a = H[k * R + k], bb = H[(k + 1) * R + k];
         const double rr = std::sqrt(a * a + bb * bb);
         cs[k] = rr == 0.0 ? 1.0 : a / rr;
         sn[k] = rr == 0.0 ? 0.0 : bb / rr;
-        H[k * restart + k] = rr;
-        H[(k + 1) * restart + k] = 0.0;
+        H[k * R + k] = rr;
+        H[(k + 1) * R + k] = 0.0;
         g[k + 1] = -sn[k] * g[k];
         g[k] = cs[k] * g[k];
         if (std::fabs(g[k + 1]) <= rtol * bn || hn == 0.0) {
@@ -191,12 +204,14 @@ struct Solver {
       }
       for (int i = k - 1; i >= 0; --i) {
         double s = g[i];
-        for (int j = i + 1; j < k; ++j) s -= H[i * restart + j] * y[j];
-        y[i] = s / H[i * restart + i];
+        for (int j = i + 1; j < k; ++j) s -= H[i * R + j] * y[j];
+        y[i] = s / H[i * R + i];
       }
-      PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dev_dots, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k, V, m, dev_dots, 1.0f, d);
-      PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));  // dev_dots is reused next
+      // the pinned y is read by the copy before any later host write to it:
+      // every path to the next write passes a fetch (stream synchronisation)
+      std::copy(y.begin(), y.begin() + k, hy);
+      PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dy, hy, sizeof(double) * k, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k, V, m, dy, 1.0f, d);
       if (done) break;
     }
     return PTROM_OK;
@@ -229,7 +244,7 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
                                pair_ws_floats(OP_JVP, jcfg, ctx->num_cus, n));
   const int R = o.gmres_restart;
   const size_t vb = align256(m * sizeof(float));
-  const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (R + 2)) +
+  const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (3 * R + 4)) +
                       align256(sizeof(double) * (R + 2) * kDotParts) + 768;
   if (int rc = ctx->reserve(need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
@@ -238,12 +253,13 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   float *tmp = cv.take<float>(m), *d = cv.take<float>(m), *w = cv.take<float>(m);
   float *V = cv.take<float>(m * (R + 1));
   float *pws = cv.take<float>(pwsf ? pwsf : 1);
-  double *dd = cv.take<double>(R + 2);
+  double *dd = cv.take<double>(3 * R + 4);
   double *dpart = cv.take<double>(size_t(R + 2) * kDotParts);
   if (!w || !V || !pws || !dd || !dpart) return ctx->fail(PTROM_ENOMEM, "workspace carve");
-  std::vector<double> hd(R + 2);
+  double *hp = ctx->pinned_doubles(3 * R + 4);
+  if (!hp) return ctx->fail(PTROM_ENOMEM, "pinned host scratch");
   hipStream_t st = (hipStream_t)stream;
-  Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hd.data(), dpart, R};
+  Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hp, dpart, R};
 
   for (int step = 0; step < nsteps; ++step) {
     PTROM_CHECK_HIP(ctx, hipMemcpyAsync(xprev, xy, m * sizeof(float), hipMemcpyDeviceToDevice, st));

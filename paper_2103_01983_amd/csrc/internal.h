@@ -98,6 +98,21 @@ struct ptrom_ctx {
   hipStream_t capture_stream = nullptr;
   std::vector<GraphCacheEntry> graphs;
   std::shared_ptr<ptrom::BatchPlan> batch_plan;
+  double *pinned = nullptr;  // pinned host scratch for small device-to-host reads
+  size_t pinned_count = 0;
+
+  // at least count pinned doubles (kept until the context is destroyed)
+  double *pinned_doubles(size_t count) {
+    if (count <= pinned_count) return pinned;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_count = 0;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+    pinned = static_cast<double *>(p);
+    pinned_count = count;
+    return pinned;
+  }
 
   hipGraphExec_t find_graph(const std::string &key) const {
     for (auto &g : graphs)
