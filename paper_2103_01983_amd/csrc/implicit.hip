@@ -135,11 +135,10 @@ struct Solver {
     return PTROM_OK;
   }
 
-  // Solve (I - c J) d = b from d = 0 to relative tolerance rtol; returns matvecs in *used.
-  int gmres(const float *b, float *d, float c, double rtol, int maxit, int *used) {
+  // Solve (I - c J) d = b from d = 0 to relative tolerance rtol; returns
+  // matvecs in *used.  bn = |b| (the caller has it).
+  int gmres(const float *b, double bn, float *d, float c, double rtol, int maxit, int *used) {
     *used = 0;
-    double bn;
-    if (int rc = norm(b, &bn)) return rc;
     hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, d, b, 0.0f);
     if (bn == 0.0) return PTROM_OK;
     const int R = restart;
@@ -287,7 +286,7 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
       }
       hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, r, r, -1.0f);
       int used = 0;
-      if (int rc = S.gmres(r, d, dt * b0, o.gmres_tol, o.gmres_maxit, &used)) return rc;
+      if (int rc = S.gmres(r, rn, d, dt * b0, o.gmres_tol, o.gmres_maxit, &used)) return rc;
       stl.krylov_iters += used;
       hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, D, D, d);
     }
