@@ -259,12 +259,15 @@ int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const double *xbar_p
  * Gauss-Newton iterations (Algorithm "Gauss-Newton") of HyperPair + the FP64
  * least-squares step dxhat = -argmin |A C nu + A rbar|, solved through the
  * normal equations (AC)^T (AC) by Gauss-Jordan elimination with one
- * refinement on the true residual, xhat += alpha dxhat, until the relative
- * reduced gradient |(AC)^T A rbar| / (its first-iteration value) <= tol or
- * max_iter iterations.  A direction with a non-positive pivot is left out of
- * the step.  xhat_hist (device [nsteps][M]) and iters (device int32
- * [nsteps]) may be NULL.  Asynchronous; iteration caps are reported in iters
- * only. */
+ * refinement on the true residual (M <= 32, M_r <= 64), or for larger bases
+ * by blocked Gauss-Jordan inversion of the normal matrix (C held in FP32
+ * there; positions, separations and residual in FP64), xhat += alpha dxhat,
+ * until the relative reduced gradient |(AC)^T A rbar| / (its first-iteration
+ * value) <= tol or max_iter iterations.  A direction with a non-positive
+ * pivot is left out of the step.  xhat_hist (device [nsteps][M]) and iters
+ * (device int32 [nsteps]) may be NULL.  EINVAL when a larger basis's arrays
+ * do not fit one workgroup's LDS.  Asynchronous; iteration caps are reported
+ * in iters only. */
 int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, int32_t *iters,
                   ptrom_stream stream);
 
