@@ -70,6 +70,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()  # loaded (compiled if stale) before the GPU is touched
     import torch
     from paper_2103_01983_amd import native
     from paper_2103_01983_amd import workloads as W
@@ -479,10 +482,27 @@ def cpu_baseline(cl, f_gpu, native, x0, g, d):
         done += idx.size
         got = np.concatenate([f[idx], f[n + idx]])
         errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    # the same oracle on one core (the paper's setting), a smaller sample
+    prev = oracle.set_threads(1)
+    try:
+        idx = rng.choice(n, 2048, replace=False)
+        t = time.perf_counter()
+        oracle.velocity_at(xy32, g32, d32, idx)
+        one = idx.size * (n - 1) / (time.perf_counter() - t)
+    finally:
+        oracle.set_threads(prev)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": done * (n - 1) / sec, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
             "sample": "FP64 oracle velocity at %d random targets (batches of 8192) of the N=65536 Gaussian "
                       "patch, each against all sources" % done,
-            "seconds": sec, "gpu_rel_err_on_sample_max": max(errs)}
+            "seconds": sec, "gpu_rel_err_on_sample_max": max(errs),
+            "single_core_value": one, "single_core_sample": "2048 random targets, one thread",
+            "nproc": os.cpu_count(), "cpu_model": model}
 
 
 if __name__ == "__main__":

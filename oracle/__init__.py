@@ -86,6 +86,8 @@ def lib():
         L.or_rk4_adjoint.argtypes = [i64, _dp, _dp, dbl, dbl, i32, _dp, _dp, _dp, _dp, _dp]
         L.or_lstsq.argtypes = [i32, i32, _dp, _dp, _dp]
         L.or_rom_hyperpair.argtypes = [ctypes.POINTER(_Rom), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_set_threads.argtypes = [i32]
+        L.or_set_threads.restype = i32
         L.or_rom_run.argtypes = [ctypes.POINTER(_Rom), dbl, dbl, i32, i32, _dp, _dp, _i32p, _dp, i64, _i64p]
     return _lib
 
@@ -200,6 +202,11 @@ def velocity_points(points, xy, gamma, delta):
 # ---------------------------------------------------------------------------
 # time steppers
 # ---------------------------------------------------------------------------
+
+def set_threads(n):
+    """Thread count of the oracle's OpenMP loops; returns the previous one."""
+    return int(lib().or_set_threads(int(n)))
+
 
 def rk4(xy, gamma, delta, dt, nsteps):
     n = _n(xy)

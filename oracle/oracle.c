@@ -22,6 +22,7 @@
  *   self pair     : excluded by index (j != i), never by testing r == 0.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -712,4 +713,12 @@ int or_rom_run(const or_rom *R, double alpha, double tol, int max_iter, int nste
   free(xbar); free(fbar); free(rbar); free(C); free(xbar_prev); free(fbar_prev);
   free(G); free(b); free(d); free(gvec);
   return status;
+}
+
+/* Thread count of the OpenMP loops (for timing the oracle on one core);
+ * returns the previous maximum. */
+int or_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
 }

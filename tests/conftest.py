@@ -11,6 +11,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU oracle runs")
+    # load (and, if stale, compile) the C oracle before any test touches the
+    # GPU: no compiler child process is started from a GPU-initialised process
+    import oracle
+    oracle.lib()
 
 
 def gpu_available():
