@@ -86,8 +86,10 @@ __global__ void __launch_bounds__(kBlock)
   using T = Traits<OP>;
   constexpr int NA = T::NACC, NS = T::NSRC;
   constexpr int TB = kBlock * K;
-  __shared__ float4 s_a[64];
-  __shared__ float s_b[64];
+  // the 64 staged sources, stored twice in a row (entries l and l + 64 are the
+  // same source), so lane l reads entry l + t at step t with no wrap-around:
+  // one address per lane and constant offsets per step
+  __shared__ float4 s_src[128][2];
   __shared__ float racc_lds[kBlock / 64][NA][64];
   __shared__ float lds_diag[NS * kTile];
   __shared__ int item_s;
@@ -144,9 +146,13 @@ __global__ void __launch_bounds__(kBlock)
       if (tid < 64) {
         const int j = j0 + tid;
         const bool ok = j < n;
-        s_a[tid] = make_float4(ok ? xy[j] : kFar, ok ? xy[n + j] : kFar, ok ? gam[j] : 0.0f,
-                               (NS == 5 && ok) ? aux[j] : 0.0f);
-        s_b[tid] = (NS == 5 && ok) ? aux[n + j] : 0.0f;
+        const float4 a = make_float4(ok ? xy[j] : kFar, ok ? xy[n + j] : kFar, ok ? gam[j] : 0.0f,
+                                     (NS == 5 && ok) ? aux[j] : 0.0f);
+        const float4 b = make_float4((NS == 5 && ok) ? aux[n + j] : 0.0f, 0.0f, 0.0f, 0.0f);
+        s_src[tid][0] = a;
+        s_src[tid][1] = b;
+        s_src[tid + 64][0] = a;
+        s_src[tid + 64][1] = b;
       }
       __syncthreads();
       float part[K][NA], racc[NA];
@@ -156,11 +162,11 @@ __global__ void __launch_bounds__(kBlock)
         for (int a = 0; a < NA; ++a) part[k][a] = 0.0f;
 #pragma unroll
       for (int a = 0; a < NA; ++a) racc[a] = 0.0f;
-#pragma unroll 2
+      const float4(*src)[2] = s_src + lane;
+#pragma unroll 8
       for (int t = 0; t < 64; ++t) {
-        const int sidx = (lane + t) & 63;
-        const float4 A = s_a[sidx];
-        float s[5] = {A.x, A.y, A.z, A.w, s_b[sidx]};
+        const float4 A = src[t][0];
+        float s[5] = {A.x, A.y, A.z, A.w, NS == 5 ? src[t][1].x : 0.0f};
         float react[NA];
 #pragma unroll
         for (int a = 0; a < NA; ++a) react[a] = 0.0f;
