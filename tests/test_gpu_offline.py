@@ -59,6 +59,26 @@ def test_pod_matches_oracle_svd(dev):
         assert np.abs(Phi_g[:, m] - Phi_o[:, m]).max() <= err2 / sig_o[m] ** 2
 
 
+def test_pod_with_more_snapshots_than_rows(dev):
+    # k > nd takes the nd x nd Gram (the residual POD pools thousands of
+    # Gauss-Newton residuals of a few hundred rows)
+    rng = np.random.default_rng(22)
+    nd, k, r = 120, 900, 10
+    U = np.linalg.qr(rng.standard_normal((nd, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((k, r)))[0]
+    sig = 10.0 ** -np.arange(r) * 50
+    S = (U * sig) @ V.T
+    M = 6
+    Phi_o, sig_o = oo.pod(S, M)
+    Phi_g, sig_g = po.pod(torch.tensor(np.ascontiguousarray(S.T), device=dev), M)
+    Phi_g = Phi_g.cpu().numpy().T
+    err2 = 10 * k * EPS * sig_o[0] ** 2
+    np.testing.assert_allclose(sig_g ** 2, sig_o ** 2, rtol=0, atol=err2)
+    np.testing.assert_allclose(Phi_g.T @ Phi_g, np.eye(M), atol=1e-13)
+    for m in range(M):
+        assert np.abs(Phi_g[:, m] - Phi_o[:, m]).max() <= err2 / sig_o[m] ** 2
+
+
 def test_single_vortex_training_and_online_rom(dev):
     # Bases Case 1 at N = 100 (M = 13, tol = 0.1, pc = 0, M_r = n_s = 2M)
     cl = W.single_vortex(100)
