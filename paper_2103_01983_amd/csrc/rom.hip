@@ -788,7 +788,9 @@ __global__ void __launch_bounds__(kRunThreads)
 
   // positions at xhat in FP64: the sampled rows (p < nd) and the surrogates
   // (Algorithm "HyperPair" preamble), one thread per coordinate
-  auto positions = [&](int np) {
+  // With stash, the sampled rows' basis (Phibar) also goes to the first M
+  // columns of the FP32 [C | rbar] matrix, where C is then formed in place.
+  auto positions = [&](int np, bool stash) {
     constexpr int kB = 32;  // loads in flight per thread
     for (int p = tid; p < np; p += kRunThreads) {
       const double *col = d.pt + p;
@@ -802,6 +804,10 @@ __global__ void __launch_bounds__(kRunThreads)
           x0 = fma(v[u], xh[m0 + u], x0);
           x1 = fma(v[u + 1], xh[m0 + u + 1], x1);
         }
+        if (stash && p < nd)
+#pragma unroll
+          for (int u = 0; u < kB; ++u)
+            if (m0 + u < M) Cf[(size_t)p * ldcf + m0 + u] = (float)v[u];
       }
       pos[p] = x0 + x1;
     }
@@ -812,7 +818,7 @@ __global__ void __launch_bounds__(kRunThreads)
   // in FP32, summed in FP64.  With res == false only fbar_out and the
   // sampled rows (xbar_out) are kept.
   auto hyperpair = [&](bool res, double *xbar_out, double *fbar_out) {
-    positions(d.P);
+    positions(d.P, res);
     __syncthreads();
     for (int t0 = 0; t0 < ns; t0 += kRunThreads / 8) {
       const int t = t0 + (tid >> 3), part = tid & 7;
@@ -871,12 +877,14 @@ __global__ void __launch_bounds__(kRunThreads)
     for (;;) {
       hyperpair(true, nullptr, fbar);
       // C = Phibar - dt/2 B Phibar
-      for (int q = tid; q < nd * M; q += kRunThreads) {
-        const int m = q / nd, row = q - m * nd;
-        const int t = row < ns ? row : row - ns;
-        const double px = d.pt[(size_t)m * d.P + t], py = d.pt[(size_t)m * d.P + ns + t];
+      // (in place over the stashed Phibar: one thread per target and mode
+      // takes both of the target's rows)
+      for (int q = tid; q < ns * M; q += kRunThreads) {
+        const int t = q / M, m = q - t * M;
+        const double px = Cf[(size_t)t * ldcf + m], py = Cf[(size_t)(ns + t) * ldcf + m];
         const double B00 = bt[3 * t], B01 = bt[3 * t + 1], B10 = bt[3 * t + 2];
-        Cf[(size_t)row * ldcf + m] = (float)(row < ns ? px - hdt * (B00 * px + B01 * py) : py - hdt * (B10 * px - B00 * py));
+        Cf[(size_t)t * ldcf + m] = (float)(px - hdt * (B00 * px + B01 * py));
+        Cf[(size_t)(ns + t) * ldcf + m] = (float)(py - hdt * (B10 * px - B00 * py));
       }
       // zero padding: columns past M, rows past nd (and their low parts)
       for (int q = tid; q < nd * (M1p - M - 2); q += kRunThreads) {
@@ -1105,7 +1113,7 @@ __global__ void __launch_bounds__(kRunThreads)
     // previous-step terms: sampled rows at the accepted xhat, velocity of the
     // last HyperPair evaluation
     __syncthreads();  // the last solve's reads of region 2 are done
-    positions(nd);
+    positions(nd, false);
     __syncthreads();
     for (int q = tid; q < nd; q += kRunThreads) {
       xbar_prev[q] = pos[q];
