@@ -714,7 +714,7 @@ __global__ void __launch_bounds__(kRunThreads)
 // during the inversion; the tail holds the previous-step rows, this query's
 // Gamma~ and the entries' surrogate ids.
 constexpr int kMaxTiles = 5;  // lower-triangle tiles of N' per wave
-constexpr int kPf = 5;        // A elements per thread prefetched a block ahead (n_d <= 160)
+constexpr int kPf = 4;        // A elements per thread prefetched a block ahead (n_d <= 128; the rest is loaded in place)
 static_assert(((kMaxM + 17) / 16) * ((kMaxM + 17) / 16 + 1) / 2 <= kMaxTiles * (kRunThreads / 64),
               "every lower-triangle tile of N' needs an owner");
 
@@ -1004,11 +1004,19 @@ __global__ void __launch_bounds__(kRunThreads)
         const double gn = sqrt(wsumd(sq));
         if (lane == 0) s_gn = gn;
       }
-      // ---- blocked Gauss-Jordan inversion of T in place (16 x 16 blocks).
-      // For pivot block K: P = T_KK is inverted by one wave (columns in
-      // registers; a non-positive pivot leaves its direction out), then on
-      // the matrix cores R_J = P^-1 T_KJ, T_IJ -= T_IK R_J and
-      // T_IK <- -T_IK P^-1 (I, J != K), and T_KK <- P^-1.
+      // ---- blocked Gauss-Jordan inversion of T in place (16 x 16 blocks),
+      // on the lower block triangle only.  With the swept blocks S (those
+      // before K) and the unswept ones U, T holds [[N_SS^-1, N_SS^-1 N_SU],
+      // [-N_US N_SS^-1, N_UU - N_US N_SS^-1 N_SU]], so an upper block is the
+      // transpose of its mirror, negated when it joins S to U.  For pivot
+      // block K: P = T_KK is inverted by one wave (a non-positive pivot leaves
+      // its direction out); with P_J = T_KJ (J < K) and Q_I = T_IK (I > K) the
+      // panels R_J = P^-1 P_J and C_I = -Q_I P^-1 and the lower trailing
+      // blocks (I >= J, I, J != K)
+      //   I, J > K:   T_IJ += C_I Q_J^T
+      //   I > K > J:  T_IJ += C_I P_J
+      //   K > I >= J: T_IJ += P_I^T R_J
+      // run on the matrix cores; then T_KK = P^-1, T_KJ = R_J, T_IK = C_I.
       const int nb = Mp / 16;
       for (int kb = 0; kb < nb; ++kb) {
         const int k0 = kb * 16;
@@ -1045,45 +1053,55 @@ __global__ void __launch_bounds__(kRunThreads)
           for (int r = 0; r < 4; ++r) Pinv[(4 * g + r) * 17 + j] = a[r];
         }
         __syncthreads();
-        // row panel R = P^-1 T_K, (16 x Mp; the K block is not used)
-        for (int tj = wave; tj < nb; tj += nwaves) {
-          if (tj == kb) continue;
-          const int j0 = tj * 16;
-          const dbl4 r4 = mfma_tile(16, lane, [&](int i, int q) { return Pinv[i * 17 + q]; },
-                                    [&](int q, int j) { return T[(size_t)(k0 + q) * ldT + j0 + j]; });
+        // panels: R_J for J < K (into Rp, 16 x Mp) and C_I for I > K (into Cpn, Mp x 16)
+        for (int tb = wave; tb < nb - 1; tb += nwaves) {
+          const int bb = tb < kb ? tb : tb + 1, b0 = bb * 16;
+          if (bb < kb) {
+            const dbl4 r4 = mfma_tile(16, lane, [&](int i, int q) { return Pinv[i * 17 + q]; },
+                                      [&](int q, int j) { return T[(size_t)(k0 + q) * ldT + b0 + j]; });
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Rp[(4 * r + (lane >> 4)) * Mp + j0 + (lane & 15)] = r4[r];
-        }
-        __syncthreads();
-        // trailing update T_IJ -= T_IK R_J and the new column panel
-        // -T_IK P^-1 (kept aside until every trailing tile has read T_IK)
-        for (int tile = wave; tile < nb * nb; tile += nwaves) {
-          const int ti = tile / nb, tj = tile - ti * nb;
-          if (ti == kb) continue;
-          const int i0 = ti * 16, j0 = tj * 16;
-          if (tj == kb) {
-            const dbl4 c4 = mfma_tile(16, lane, [&](int i, int q) { return T[(size_t)(i0 + i) * ldT + k0 + q]; },
+            for (int r = 0; r < 4; ++r) Rp[(4 * r + (lane >> 4)) * Mp + b0 + (lane & 15)] = r4[r];
+          } else {
+            const dbl4 c4 = mfma_tile(16, lane, [&](int i, int q) { return T[(size_t)(b0 + i) * ldT + k0 + q]; },
                                       [&](int q, int j) { return Pinv[q * 17 + j]; });
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Cpn[(i0 + 4 * r + (lane >> 4)) * 16 + (lane & 15)] = -c4[r];
-          } else {
-            dbl4 t4;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t4[r] = T[(size_t)(i0 + 4 * r + (lane >> 4)) * ldT + j0 + (lane & 15)];
-            const dbl4 u4 = mfma_tile(16, lane, [&](int i, int q) { return -T[(size_t)(i0 + i) * ldT + k0 + q]; },
-                                      [&](int q, int j) { return Rp[q * Mp + j0 + j]; }, t4);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) T[(size_t)(i0 + 4 * r + (lane >> 4)) * ldT + j0 + (lane & 15)] = u4[r];
+            for (int r = 0; r < 4; ++r) Cpn[(b0 + 4 * r + (lane >> 4)) * 16 + (lane & 15)] = -c4[r];
           }
         }
         __syncthreads();
-        // write back the panels and the block inverse
+        // lower trailing blocks; they read row K and column K before the
+        // write-back below replaces them
+        const int nr = nb - 1, ntri = nr * (nr + 1) / 2;
+        for (int tile = wave; tile < ntri; tile += nwaves) {
+          int ti = 0;
+          while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+          const int tj = tile - ti * (ti + 1) / 2;
+          const int bi = ti < kb ? ti : ti + 1, bj = tj < kb ? tj : tj + 1;
+          const int i0 = bi * 16, j0 = bj * 16;
+          dbl4 t4;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) t4[r] = T[(size_t)(i0 + 4 * r + (lane >> 4)) * ldT + j0 + (lane & 15)];
+          dbl4 u4;
+          if (bj > kb)
+            u4 = mfma_tile(16, lane, [&](int i, int q) { return Cpn[(i0 + i) * 16 + q]; },
+                           [&](int q, int j) { return T[(size_t)(j0 + j) * ldT + k0 + q]; }, t4);
+          else if (bi > kb)
+            u4 = mfma_tile(16, lane, [&](int i, int q) { return Cpn[(i0 + i) * 16 + q]; },
+                           [&](int q, int j) { return T[(size_t)(k0 + q) * ldT + j0 + j]; }, t4);
+          else
+            u4 = mfma_tile(16, lane, [&](int i, int q) { return T[(size_t)(k0 + q) * ldT + i0 + i]; },
+                           [&](int q, int j) { return Rp[q * Mp + j0 + j]; }, t4);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) T[(size_t)(i0 + 4 * r + (lane >> 4)) * ldT + j0 + (lane & 15)] = u4[r];
+        }
+        __syncthreads();
+        // write back the lower parts of row K and column K and the block inverse
         for (int t = tid; t < 16 * Mp; t += kRunThreads) {
           const int r = t / Mp, c = t - r * Mp;
-          if (c < k0 || c >= k0 + 16) T[(size_t)(k0 + r) * ldT + c] = Rp[r * Mp + c];
-          else T[(size_t)(k0 + r) * ldT + c] = Pinv[r * 17 + (c - k0)];
+          if (c < k0) T[(size_t)(k0 + r) * ldT + c] = Rp[r * Mp + c];
+          else if (c < k0 + 16) T[(size_t)(k0 + r) * ldT + c] = Pinv[r * 17 + (c - k0)];
           const int i = t >> 4, q = t & 15;  // column panel: row i, column k0 + q
-          if (i < k0 || i >= k0 + 16) T[(size_t)i * ldT + k0 + q] = Cpn[i * 16 + q];
+          if (i >= k0 + 16) T[(size_t)i * ldT + k0 + q] = Cpn[i * 16 + q];
         }
         __syncthreads();
       }
@@ -1091,7 +1109,12 @@ __global__ void __launch_bounds__(kRunThreads)
       for (int o = tid >> 3; o < M; o += kRunThreads / 8) {
         const int part = tid & 7;
         double sx = 0.0;
-        for (int j = part; j < M; j += 8) sx = fma(T[(size_t)o * ldT + j], gb[j], sx);
+        for (int j = part; j < M; j += 8) {
+          // N^-1 is symmetric and only its lower block triangle (and the
+          // diagonal blocks) is held
+          const double tv = (j >> 4) <= (o >> 4) ? T[(size_t)o * ldT + j] : T[(size_t)j * ldT + o];
+          sx = fma(tv, gb[j], sx);
+        }
         sx = sum8(sx);
         if (part == 0) xs[o] = sx;
       }
