@@ -697,16 +697,18 @@ __global__ void __launch_bounds__(kRunThreads)
 //   gather    the sampled-row and surrogate positions at xhat in FP64 (one
 //             thread per coordinate over a mode-major basis), then each
 //             target's list by a group of 8 lanes: velocity, residual rows
-//             rbar and the 2x2 blocks; C = (I - dt/2 B) Phibar in FP32;
+//             rbar and the 2x2 blocks; C = (I - dt/2 B) Phibar in FP32,
+//             formed in place over a copy of Phibar left by the positions;
 //   normal    N' = G'^T G' with G' = A [C | rbar] accumulated over 16-row
 //   matrix    blocks of A: the block is staged in LDS, G'_blk = A_blk [C |
 //             rbar] and N' += G'_blk^T G'_blk run on the FP64 matrix cores,
 //             each wave keeping its (lower-triangle) tiles of N' in registers;
 //   solve     N = G^T G is inverted in place by blocked Gauss-Jordan over
-//             16 x 16 blocks: one wave inverts the pivot block in registers
-//             (a non-positive pivot leaves its direction out), the row and
-//             column panels and the rank-16 trailing update run on the FP64
-//             matrix cores; then x = N^-1 g with g = G^T b.
+//             16 x 16 blocks of its lower block triangle: one wave inverts
+//             the pivot block in registers (a non-positive pivot leaves its
+//             direction out), the row and column panels and the rank-16
+//             trailing update run on the FP64 matrix cores; then x = N^-1 g
+//             with g = G^T b.
 // C enters only the step direction, never the residual, so its FP32 rounding
 // leaves the Gauss-Newton fixed point where it is.
 // LDS: region 1 holds C and rbar and then N; region 2 holds the positions
@@ -761,10 +763,10 @@ __global__ void __launch_bounds__(kRunThreads)
   const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, d.Nc);
   double *R1 = dyn, *R2 = dyn + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
-  // region 1: C (nd x M, FP32) and rbar (nd, FP64), then N (Mp x Mp, stride ldT)
-  // [C | rbar_hi | rbar_lo | 0] as FP32 (ndp rows of stride ldcf, zero
-  // padded): the two parts of rbar keep its FP64 value to 2^-48, and A times
-  // their sum is the sum of the two product columns
+  // region 1: [C | rbar_hi | rbar_lo | 0] as FP32 (ndp rows of stride ldcf,
+  // zero padded; the two parts of rbar keep its FP64 value to 2^-48, and A
+  // times their sum is the sum of the two product columns), then N (Mp x Mp,
+  // stride ldT)
   const int ndp = (nd + 3) / 4 * 4, ldcf = c_stride(M1p), lda = ndp + 1;
   float *Cf = reinterpret_cast<float *>(R1);
   double *T = R1;
