@@ -139,7 +139,7 @@ int ptrom_rk4_f64(ptrom_ctx *ctx, int64_t n, double *xy, const double *gamma, do
 typedef struct {
   double newton_tol;  /* stop when |r(xi)| <= newton_tol * |r(x_prev)| (default 1e-6) */
   int32_t max_newton; /* Newton iterations per step (default 20) */
-  int32_t gmres_restart; /* Krylov basis size (default 20) */
+  int32_t gmres_restart; /* Krylov basis size, 1 to 200 (default 20) */
   int32_t gmres_maxit;   /* matvecs per Newton iteration (default 60) */
   int32_t pad;
   double gmres_tol;   /* relative residual of each Newton linear solve (default 1e-3) */

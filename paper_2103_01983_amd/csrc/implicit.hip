@@ -64,6 +64,88 @@ __global__ void __launch_bounds__(64)
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// out[v] = X_v . y for short vectors: one workgroup per vector, the whole
+// sum in a fixed order (strided FP64 partials, then a tree over the block).
+constexpr int64_t kShortDot = 16384;
+
+__global__ void __launch_bounds__(256)
+    dot_short_kernel(int64_t m, const float *__restrict__ X, int64_t ldx, const float *__restrict__ y,
+                     double *__restrict__ out) {
+  __shared__ double red[256];
+  const float *x = X + (size_t)blockIdx.x * ldx;
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += 256) s += (double)x[q] * (double)y[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+constexpr int kMaxRestart = 200;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One Arnoldi orthogonalisation for short vectors (m <= kFusedGS), in one
+// workgroup with w held in LDS: classical Gram-Schmidt against V_0 .. V_k
+// applied twice, the two coefficient sets to c1[0, k] and c2[0, k], |w|^2 to
+// c2[k + 1], and V_{k+1} = w / |w| when |w| > 0.  Dot products are FP64
+// (per-lane strided partials, then a butterfly over the wave); the update of
+// each element adds the projections in vector order.
+constexpr int kFusedGS = 8192;
+constexpr int kGSThreads = 1024;
+
+__global__ void __launch_bounds__(kGSThreads)
+    gs_fused_kernel(int m, int k, float *__restrict__ V, const float *__restrict__ w,
+                    double *__restrict__ c1, double *__restrict__ c2) {
+  constexpr int NW = kGSThreads / 64;
+  __shared__ float wl[kFusedGS];
+  __shared__ double cs[kMaxRestart + 1];
+  __shared__ double red[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int q = tid; q < m; q += kGSThreads) wl[q] = w[q];
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    double *cout = pass ? c2 : c1;
+    for (int v = wv; v <= k; v += NW) {
+      const float *x = V + (size_t)v * m;
+      double s = 0.0;
+      for (int q = lane; q < m; q += 64) s += (double)x[q] * (double)wl[q];
+      s = wave_sum(s);
+      if (lane == 0) {
+        cs[v] = s;
+        cout[v] = s;
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < m; q += kGSThreads) {
+      double s = 0.0;
+      for (int v = 0; v <= k; ++v) s += cs[v] * (double)V[(size_t)v * m + q];
+      wl[q] = (float)((double)wl[q] - s);
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+  for (int q = tid; q < m; q += kGSThreads) s += (double)wl[q] * (double)wl[q];
+  s = wave_sum(s);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  double nn = 0.0;
+  for (int i = 0; i < NW; ++i) nn += red[i];
+  if (tid == 0) c2[k + 1] = nn;
+  if (nn > 0.0) {
+    const float a = float(1.0 / sqrt(nn));
+    float *out = V + (size_t)(k + 1) * m;
+    for (int q = tid; q < m; q += kGSThreads) out[q] = a * wl[q];
+  }
+}
+
 // y -= sum_v c[v] X_v  (c on the device), or y = scale * y + sum_v c[v] X_v when accumulate.
 __global__ void multi_axpy_kernel(int64_t m, int nvec, const float *__restrict__ X, int64_t ldx,
                                   const double *__restrict__ c, float sign, float *__restrict__ y) {
@@ -117,6 +199,10 @@ struct Solver {
 
   // dev[v] = X_v . y for v < nvec (stays on the device)
   void dots(const float *X, int nvec, const float *y, double *dev) {
+    if (m <= kShortDot) {
+      hipLaunchKernelGGL(dot_short_kernel, dim3(nvec), dim3(256), 0, st, m, X, m, y, dev);
+      return;
+    }
     hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotParts, nvec), dim3(256), 0, st, m, X, m, y, dot_part);
     hipLaunchKernelGGL(dot_final_kernel, dim3(nvec), dim3(kDotParts), 0, st, dot_part, dev);
   }
@@ -169,18 +255,23 @@ struct Solver {
         if (int rc = apply(vk, c, w)) return rc;
         ++*used;
         // classical Gram-Schmidt, applied twice, coefficients on the device
-        dots(V, k + 1, w, d1);
-        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d1, -1.0f, w);
-        dots(V, k + 1, w, d2);
-        hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d2, -1.0f, w);
-        dots(w, 1, w, d2 + (k + 1));
+        const bool fused = m <= kFusedGS;
+        if (fused) {
+          hipLaunchKernelGGL(gs_fused_kernel, dim3(1), dim3(kGSThreads), 0, st, int(m), k, V, w, d1, d2);
+        } else {
+          dots(V, k + 1, w, d1);
+          hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d1, -1.0f, w);
+          dots(V, k + 1, w, d2);
+          hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d2, -1.0f, w);
+          dots(w, 1, w, d2 + (k + 1));
+        }
         // one copy covering d1 [0, k], d2 [0, k] and |w|^2 (d2 starts at R + 1)
         if (int rc = fetch(dd, hp, R + k + 3)) return rc;
         const double *h1 = hp, *h2 = hp + (R + 1);
         const double hn = std::sqrt(h2[k + 1]);
         for (int i = 0; i <= k; ++i) H[i * R + k] = h1[i] + h2[i];
         H[(k + 1) * R + k] = hn;
-        if (hn > 0.0)
+        if (hn > 0.0 && !fused)
           hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V + (size_t)(k + 1) * m, w, float(1.0 / hn));
         for (int i = 0; i < k; ++i) {
           const double a = H[i * R + k], bb = H[(i + 1) * R + k];
@@ -231,7 +322,7 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   if (scheme != PTROM_BACKWARD_EULER && scheme != PTROM_TRAPEZOID) return ctx->fail(PTROM_EINVAL, "bad scheme");
   ptrom_newton_opts o{1e-6, 20, 20, 60, 0, 1e-3};
   if (opts) o = *opts;
-  if (o.gmres_restart < 1 || o.gmres_restart > 200 || o.max_newton < 0 || o.gmres_maxit < 1)
+  if (o.gmres_restart < 1 || o.gmres_restart > kMaxRestart || o.max_newton < 0 || o.gmres_maxit < 1)
     return ctx->fail(PTROM_EINVAL, "bad Newton/GMRES options");
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
   ptrom_newton_stats stl{};

@@ -14,6 +14,8 @@
 // workspace and a second kernel adds them in chunk order, so results are
 // bitwise reproducible.  Self pairs are removed by index in the tiles that
 // overlap the workgroup's targets (needed for delta = 0).
+#include <algorithm>
+
 #include "pair_core.h"
 
 namespace ptrom {
@@ -229,16 +231,31 @@ PairCfg Tuning::get(int op, int64_t n) const {
   return c;
 }
 
-int pair_splits(int op, const PairCfg &cfg, int num_cus, int64_t n) {
-  (void)op;
+// Source chunks per launch.  Chunks are whole 256-source tiles unless that
+// leaves fewer than 4 waves per SIMD (small n): then they shrink to multiples
+// of kSubChunk sources, at most kMaxSubSplits of them, so that each lane's
+// source loop stays short and the launch's latency is a few microseconds.
+constexpr int kSubChunk = 32;
+constexpr int kMaxSubSplits = 64;
+
+int64_t pair_chunk(const PairCfg &cfg, int num_cus, int64_t n) {
   const int64_t blocks_x = (n + kBlock * cfg.k - 1) / (kBlock * cfg.k);
   const int64_t want_waves = int64_t(num_cus) * 4 * cfg.waves_per_simd;
   int64_t s = (want_waves + blocks_x * 4 - 1) / (blocks_x * 4);
-  const int64_t max_s = (n + kTile - 1) / kTile;
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  int64_t unit = kTile, max_s = tiles;
+  if (blocks_x * tiles * 4 < int64_t(num_cus) * 16) {
+    unit = kSubChunk;
+    max_s = std::min<int64_t>((n + kSubChunk - 1) / kSubChunk, kMaxSubSplits);
+  }
   if (s < 1) s = 1;
   if (s > max_s) s = max_s;
-  // chunk = whole tiles; recompute the number of chunks actually needed
-  int64_t chunk = ((n + s - 1) / s + kTile - 1) / kTile * kTile;
+  return ((n + s - 1) / s + unit - 1) / unit * unit;
+}
+
+int pair_splits(int op, const PairCfg &cfg, int num_cus, int64_t n) {
+  (void)op;
+  const int64_t chunk = pair_chunk(cfg, num_cus, n);
   return int((n + chunk - 1) / chunk);
 }
 
@@ -255,9 +272,8 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, con
     return launch_pair_sym(op, cfg.k, cfg.waves_per_simd, num_cus, n64, xy, gamma, aux, delta, out, out2, ws,
                            ws_floats, stream);
   const int n = int(n64);
-  int s = pair_splits(op, cfg, num_cus, n64);
-  int64_t chunk = ((n64 + s - 1) / s + kTile - 1) / kTile * kTile;
-  s = int((n64 + chunk - 1) / chunk);
+  const int64_t chunk = pair_chunk(cfg, num_cus, n64);
+  const int s = int((n64 + chunk - 1) / chunk);
   if (s > 1 && ws_floats < size_t(s) * nacc(op) * size_t(n)) return hipErrorInvalidValue;
   const dim3 grid((n + kBlock * cfg.k - 1) / (kBlock * cfg.k), s);
   const float d2 = delta * delta;

@@ -71,6 +71,24 @@ def test_implicit_parity(dev, scheme):
     assert rel(xs - xy, o - xy) <= 1e-4
 
 
+@pytest.mark.parametrize("n, restart, nsteps", [(700, 3, 3), (5000, 20, 2)])
+def test_implicit_gmres_paths_parity(dev, n, restart, nsteps):
+    # GMRES orthogonalisation paths: N = 700 with a 3-vector Krylov basis
+    # (the one-workgroup Gram-Schmidt, restarted many times), N = 5000 (the
+    # separate projection kernels over 10000-long vectors)
+    c = W.gaussian_patch(n, seed=43, delta=0.01)
+    xy, g = f32(c.xy), f32(c.gamma) * 50.0
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, 0.01, 5e-4, nsteps, scheme=native.BACKWARD_EULER, newton_tol=1e-7, gmres_tol=1e-4,
+                         gmres_restart=restart, gmres_maxit=300)
+    assert st.nonconverged_steps == 0
+    o, _ = oracle.implicit(xy, g, float(np.float32(0.01)), float(np.float32(5e-4)), nsteps)
+    xs = x.cpu().numpy()
+    assert rel(xs, o) <= 1e-5
+    assert rel(xs - xy, o - xy) <= 1e-4
+
+
 @pytest.mark.parametrize("scheme", [native.BACKWARD_EULER, native.TRAPEZOID])
 def test_implicit_with_inflow_parity(dev, scheme):
     # background velocity (the mushroom cloud's inflow profile) in the FOM
