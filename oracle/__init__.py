@@ -83,6 +83,8 @@ def lib():
                                   ctypes.POINTER(NewtonStats)]
         L.or_implicit_forced.argtypes = [i64, _dp, _dp, dbl, _dp, dbl, i32, i32, dbl, i32, dbl, i32, i32,
                                          ctypes.POINTER(NewtonStats)]
+        L.or_implicit_block.argtypes = [i64, _dp, _dp, dbl, _dp, dbl, i32, i32, dbl, i32, i32,
+                                        ctypes.POINTER(NewtonStats)]
         L.or_rk4_adjoint.argtypes = [i64, _dp, _dp, dbl, dbl, i32, _dp, _dp, _dp, _dp, _dp]
         L.or_lstsq.argtypes = [i32, i32, _dp, _dp, _dp]
         L.or_rom_hyperpair.argtypes = [ctypes.POINTER(_Rom), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -236,6 +238,25 @@ def implicit(xy, gamma, delta, dt, nsteps, scheme=BE, newton_tol=1e-12, max_newt
     lib().or_implicit_forced(n, x.ctypes.data_as(_dp), pg, float(delta), pu, float(dt), int(nsteps), int(scheme),
                              float(newton_tol), int(max_newton), float(gmres_tol), int(gmres_restart),
                              int(gmres_maxit), ctypes.byref(st))
+    return x, st
+
+
+def implicit_block(xy, gamma, delta, dt, nsteps, scheme=BE, newton_tol=1e-12, max_newton=100, jac_period=0,
+                   u=None):
+    """The paper's FOM solver: k=1 implicit steps by inexact Newton with the
+    block-diagonal kernel Jacobian (per-body 2x2 solves), evaluated at every
+    iterate (jac_period 0) or at the start of every jac_period-th step.
+    Returns (x, NewtonStats)."""
+    n = _n(xy)
+    x = np.array(xy, dtype=np.float64, copy=True)
+    g, pg = _d(gamma)
+    pu = None
+    if u is not None:
+        ua, pu = _d(u)
+        assert ua.size == 2 * n
+    st = NewtonStats()
+    lib().or_implicit_block(n, x.ctypes.data_as(_dp), pg, float(delta), pu, float(dt), int(nsteps), int(scheme),
+                            float(newton_tol), int(max_newton), int(jac_period), ctypes.byref(st))
     return x, st
 
 

@@ -275,6 +275,55 @@ def test_backward_euler_two_vortex_fixed_point():
     assert abs(complex(out[0] - out[1], out[2] - out[3]) - z) < 1e-12
 
 
+@pytest.mark.parametrize("delta", [0.0, 0.15])
+def test_block_newton_passive_tracer_is_exact_newton(delta):
+    # A passive tracer (Gamma_2 = 0) around a vortex: the vortex feels no
+    # velocity and the tracer's own 2x2 block is the only nonzero Jacobian
+    # block, so the block-diagonal inexact Newton is exact Newton (same
+    # iteration count: a transposed or sign-flipped block loses quadratic
+    # convergence) and the trapezoid step is the Cayley rotation about the
+    # vortex by 2 atan(dt Omega / 2).
+    xy, g = _two_vortex_state((0.9, 0.0), (0.1, -0.05), (0.4, 0.2))
+    dt, steps = 0.05, 20
+    ob, sb = oracle.implicit_block(xy, g, delta, dt, steps, scheme=oracle.TRAPEZOID)
+    oe, se = oracle.implicit(xy, g, delta, dt, steps, scheme=oracle.TRAPEZOID)
+    assert sb.nonconverged_steps == 0 and sb.newton_iters == se.newton_iters
+    assert ob[0] == xy[0] and ob[2] == xy[2]
+    z0 = complex(xy[1] - xy[0], xy[3] - xy[2])
+    om = _omega(g, abs(z0) ** 2, delta)
+    z = z0 * np.exp(1j * steps * 2 * math.atan(dt * om / 2))
+    assert abs(complex(ob[1] - ob[0], ob[3] - ob[2]) - z) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", [oracle.BE, oracle.TRAPEZOID])
+def test_block_newton_same_root_as_exact_newton(scheme):
+    # Both iterations drive the same residual to zero and differ only in the
+    # linear model, so they reach the same states, the block version in more
+    # (linearly convergent) iterations, for every Jacobian refresh period.
+    cl = W.gaussian_patch(64, seed=21, delta=0.05)
+    xy, g, d = cl.xy, cl.gamma * 64, cl.delta
+    oe, se = oracle.implicit(xy, g, d, 2.5e-3, 3, scheme)
+    for p in (0, 1, 2):
+        ob, sb = oracle.implicit_block(xy, g, d, 2.5e-3, 3, scheme, jac_period=p)
+        assert sb.nonconverged_steps == 0 and sb.newton_iters > se.newton_iters
+        assert np.linalg.norm(ob - oe) <= 1e-10 * np.linalg.norm(oe - xy)
+
+
+def test_block_newton_background_velocity_and_rest():
+    # a uniform background velocity U shifts the trajectory by U t exactly;
+    # with every Gamma = 0 the initial state is already the root
+    cl = W.gaussian_patch(48, seed=22, delta=0.05)
+    xy, g, d = cl.xy, cl.gamma * 48, cl.delta
+    U = np.concatenate([np.full(48, 0.3), np.full(48, -0.2)])
+    dt, k = 2e-3, 4
+    o0, _ = oracle.implicit_block(xy, g, d, dt, k, oracle.TRAPEZOID, jac_period=1)
+    o1, s1 = oracle.implicit_block(xy, g, d, dt, k, oracle.TRAPEZOID, jac_period=1, u=U)
+    assert s1.nonconverged_steps == 0
+    assert np.abs(o1 - (o0 + U * dt * k)).max() < 1e-12
+    o2, s2 = oracle.implicit_block(xy, 0.0 * g, d, dt, k, oracle.BE)
+    assert s2.newton_iters == 0 and np.array_equal(o2, xy)
+
+
 def test_implicit_schemes_order_against_rk4():
     cl = W.gaussian_patch(64, seed=21, delta=0.05)
     xy, g, d = cl.xy, cl.gamma * 64, cl.delta
