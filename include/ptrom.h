@@ -136,18 +136,29 @@ int ptrom_rk4(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float de
 int ptrom_rk4_f64(ptrom_ctx *ctx, int64_t n, double *xy, const double *gamma, double delta,
                   double dt, int nsteps, ptrom_stream stream);
 
+/* Linear model of each Newton correction (ptrom_newton_opts.linear_solver):
+ * GMRES = the exact Jacobian, applied through Jacobian-vector products and
+ * solved by restarted GMRES; BLOCK = the paper's inexact Jacobian, which
+ * keeps only each body's own 2x2 block df_i/dx_i (Section "Problem
+ * formulation", after eq. "linKstep"), solved body by body. */
+enum { PTROM_NEWTON_GMRES = 0, PTROM_NEWTON_BLOCK = 1 };
+
 typedef struct {
   double newton_tol;  /* stop when |r(xi)| <= newton_tol * |r(x_prev)| (default 1e-6) */
   int32_t max_newton; /* Newton iterations per step (default 20) */
-  int32_t gmres_restart; /* Krylov basis size, 1 to 200 (default 20) */
-  int32_t gmres_maxit;   /* matvecs per Newton iteration (default 60) */
+  int32_t gmres_restart; /* GMRES: Krylov basis size, 1 to 200 (default 20) */
+  int32_t gmres_maxit;   /* GMRES: matvecs per Newton iteration (default 60) */
+  int32_t linear_solver; /* PTROM_NEWTON_GMRES (default) or PTROM_NEWTON_BLOCK */
+  double gmres_tol;   /* GMRES: relative residual of each Newton linear solve (default 1e-3) */
+  int32_t jac_period; /* BLOCK: 0 = blocks evaluated at every Newton iterate; p >= 1 =
+                         evaluated at the first iterate (x_prev) of steps 0, p, 2p, ...
+                         of the call and kept in between (default 0) */
   int32_t pad;
-  double gmres_tol;   /* relative residual of each Newton linear solve (default 1e-3) */
 } ptrom_newton_opts;
 
 typedef struct {
   int32_t newton_iters; /* total over all steps */
-  int32_t krylov_iters; /* total Jacobian products */
+  int32_t krylov_iters; /* total Jacobian products (0 with PTROM_NEWTON_BLOCK) */
   int32_t nonconverged_steps;
   int32_t pad;
   double max_final_rel_residual; /* max over steps of |r_final| / |r_0| */
@@ -156,9 +167,12 @@ typedef struct {
 /* nsteps implicit steps (scheme = PTROM_BACKWARD_EULER or PTROM_TRAPEZOID) of
  * the k=1 linear multistep residual, each solved by Newton's method whose
  * linear systems (I - dt beta0 J) d = -r are solved matrix-free by restarted
- * GMRES over ptrom_jvp.  The unknown is the increment xi - x_prev.
- * opts may be NULL (defaults).  stats may be NULL.  SYNCHRONISES the stream
- * (host-side Krylov scalars).  Returns PTROM_ENOCONV if a step hit max_newton. */
+ * GMRES over ptrom_jvp, or, with linear_solver = PTROM_NEWTON_BLOCK, with J
+ * replaced by the per-body blocks of ptrom_block_jacobian (2x2 solves; a
+ * singular block gives non-finite output and PTROM_ENOCONV).  The unknown
+ * is the increment xi - x_prev.  opts may be NULL (defaults).  stats may be
+ * NULL.  SYNCHRONISES the stream (host-side Newton and Krylov scalars).
+ * Returns PTROM_ENOCONV if a step hit max_newton. */
 int ptrom_implicit(ptrom_ctx *ctx, int64_t n, float *xy, const float *gamma, float delta,
                    float dt, int nsteps, int scheme, const ptrom_newton_opts *opts,
                    ptrom_newton_stats *stats, ptrom_stream stream);

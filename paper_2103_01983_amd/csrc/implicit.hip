@@ -5,7 +5,10 @@
 // (I - dt beta0 J(xi)) d = -r solved by restarted GMRES whose matrix-vector
 // products are the Jacobian-product pair kernel.  Krylov vectors live in
 // HBM (FP32); dot products accumulate in FP64 on the device; the small
-// Hessenberg least-squares problem is solved on the host in FP64.
+// Hessenberg least-squares problem is solved on the host in FP64.  With
+// the paper's inexact Jacobian the Newton systems are instead the per-body
+// 2x2 blocks (I - dt beta0 B_i) d_i = -r_i of the block-Jacobian kernel.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -64,6 +67,22 @@ __global__ void __launch_bounds__(64)
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// The paper's inexact Newton correction: per body, solve
+// (I - c B_i) d_i = -r_i with B_i = [B0 B1; B2 B3] (layout [4][n]) by
+// Cramer's rule in FP64, and add d_i to the increment D.
+__global__ void block_solve_kernel(int64_t n, float *__restrict__ D, const float *__restrict__ r,
+                                   const float *__restrict__ B, float c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double cc = c;
+  const double a00 = 1.0 - cc * B[i], a01 = -cc * B[n + i];
+  const double a10 = -cc * B[2 * n + i], a11 = 1.0 - cc * B[3 * n + i];
+  const double det = a00 * a11 - a01 * a10;
+  const double bx = -(double)r[i], by = -(double)r[n + i];
+  D[i] = (float)((double)D[i] + (bx * a11 - a01 * by) / det);
+  D[n + i] = (float)((double)D[n + i] + (a00 * by - a10 * bx) / det);
+}
+
 // out[v] = X_v . y for short vectors: one workgroup per vector, the whole
 // sum in a fixed order (strided FP64 partials, then a tree over the block).
 constexpr int64_t kShortDot = 16384;
@@ -98,7 +117,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // c2[k + 1], and V_{k+1} = w / |w| when |w| > 0.  Dot products are FP64
 // (per-lane strided partials, then a butterfly over the wave); the update of
 // each element adds the projections in vector order.
-constexpr int kFusedGS = 8192;
+constexpr int kFusedGS = 12288;
 constexpr int kGSThreads = 1024;
 
 __global__ void __launch_bounds__(kGSThreads)
@@ -320,22 +339,26 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   if (!(delta >= 0.0f) || !(dt > 0.0f) || nsteps < 0) return ctx->fail(PTROM_EINVAL, "bad delta/dt/nsteps");
   if (!xy || !gamma) return ctx->fail(PTROM_EINVAL, "NULL array");
   if (scheme != PTROM_BACKWARD_EULER && scheme != PTROM_TRAPEZOID) return ctx->fail(PTROM_EINVAL, "bad scheme");
-  ptrom_newton_opts o{1e-6, 20, 20, 60, 0, 1e-3};
+  ptrom_newton_opts o{1e-6, 20, 20, 60, PTROM_NEWTON_GMRES, 1e-3, 0, 0};
   if (opts) o = *opts;
-  if (o.gmres_restart < 1 || o.gmres_restart > kMaxRestart || o.max_newton < 0 || o.gmres_maxit < 1)
+  if (o.gmres_restart < 1 || o.gmres_restart > kMaxRestart || o.max_newton < 0 || o.gmres_maxit < 1 ||
+      (o.linear_solver != PTROM_NEWTON_GMRES && o.linear_solver != PTROM_NEWTON_BLOCK) || o.jac_period < 0)
     return ctx->fail(PTROM_EINVAL, "bad Newton/GMRES options");
+  const bool block = o.linear_solver == PTROM_NEWTON_BLOCK;
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
   ptrom_newton_stats stl{};
   const int64_t m = 2 * n;
   const float b0 = scheme == PTROM_BACKWARD_EULER ? 1.0f : 0.5f;
   const float b1 = scheme == PTROM_BACKWARD_EULER ? 0.0f : 0.5f;
   const PairCfg vcfg = ctx->tune.get(OP_VEL, n), jcfg = ctx->tune.get(OP_JVP, n);
-  const size_t pwsf = std::max(pair_ws_floats(OP_VEL, vcfg, ctx->num_cus, n),
-                               pair_ws_floats(OP_JVP, jcfg, ctx->num_cus, n));
+  const PairCfg bcfg = ctx->tune.get(OP_BJAC, n);
+  const size_t pwsf = std::max({pair_ws_floats(OP_VEL, vcfg, ctx->num_cus, n),
+                                pair_ws_floats(OP_JVP, jcfg, ctx->num_cus, n),
+                                block ? pair_ws_floats(OP_BJAC, bcfg, ctx->num_cus, n) : size_t(0)});
   const int R = o.gmres_restart;
   const size_t vb = align256(m * sizeof(float));
   const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (3 * R + 4)) +
-                      align256(sizeof(double) * (R + 2) * kDotParts) + 768;
+                      align256(sizeof(double) * (R + 2) * kDotParts) + align256(4 * n * sizeof(float)) + 1024;
   if (int rc = ctx->reserve(need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
   float *xprev = cv.take<float>(m), *D = cv.take<float>(m), *xi = cv.take<float>(m);
@@ -345,7 +368,8 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   float *pws = cv.take<float>(pwsf ? pwsf : 1);
   double *dd = cv.take<double>(3 * R + 4);
   double *dpart = cv.take<double>(size_t(R + 2) * kDotParts);
-  if (!w || !V || !pws || !dd || !dpart) return ctx->fail(PTROM_ENOMEM, "workspace carve");
+  float *Bj = cv.take<float>(4 * n);
+  if (!w || !V || !pws || !dd || !dpart || !Bj) return ctx->fail(PTROM_ENOMEM, "workspace carve");
   double *hp = ctx->pinned_doubles(3 * R + 4);
   if (!hp) return ctx->fail(PTROM_ENOMEM, "pinned host scratch");
   hipStream_t st = (hipStream_t)stream;
@@ -374,6 +398,15 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
       if (it >= o.max_newton) {
         stl.nonconverged_steps++;
         break;
+      }
+      if (block) {
+        // blocks at xi = x_prev + D: every iterate, or the first iterate of every jac_period-th step
+        if (o.jac_period == 0 || (it == 0 && step % o.jac_period == 0)) {
+          e = launch_pair(OP_BJAC, bcfg, ctx->num_cus, n, xi, gamma, nullptr, delta, Bj, nullptr, pws, pwsf, st);
+          if (e != hipSuccess) return ctx->hip_fail(e, "block jacobian");
+        }
+        hipLaunchKernelGGL(block_solve_kernel, g1(n), dim3(256), 0, st, n, D, r, Bj, dt * b0);
+        continue;
       }
       hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, r, r, -1.0f);
       int used = 0;

@@ -75,6 +75,16 @@ def run(n, case=1, depth=16, device=None):
     st = native.implicit(x, g, 0.0, dt, steps, scheme=native.TRAPEZOID, newton_tol=1e-6, gmres_tol=1e-4)
     torch.cuda.synchronize()
     t_fom = time.perf_counter() - t0
+    # the same FOM with the paper's inexact Newton (block-diagonal Jacobian
+    # at every iterate, at most 100 iterations), timed and compared
+    xb = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stb = native.implicit(xb, g, 0.0, dt, steps, scheme=native.TRAPEZOID, newton_tol=1e-6, max_newton=100,
+                          linear_solver=native.NEWTON_BLOCK)
+    torch.cuda.synchronize()
+    t_fom_block = time.perf_counter() - t0
+    block_rel = float(torch.linalg.norm((xb - x).double()) / torch.linalg.norm((x - x0).double()))
 
     # offline training (snapshots recomputed inside, one per step)
     t0 = time.perf_counter()
@@ -111,7 +121,10 @@ def run(n, case=1, depth=16, device=None):
     return dict(study="single_vortex_reproductive", N=n, bases_case=case, tol=tol, M=M, Mr=Mr, ns=ns, pc=pc,
                 Nc=int(np.asarray(art["Gt"]).size), nnz=int(np.asarray(art["ids"]).size), steps=steps, dt=dt,
                 fom_seconds=t_fom, fom_newton_iters=st.newton_iters, fom_krylov_iters=st.krylov_iters,
-                ptrom_online_seconds=t_rom, speedup_SF=t_fom / t_rom, offline_seconds=t_off,
+                fom_block_seconds=t_fom_block, fom_block_newton_iters=stb.newton_iters,
+                fom_block_nonconverged_steps=stb.nonconverged_steps, fom_block_vs_gmres_final_rel=block_rel,
+                ptrom_online_seconds=t_rom, speedup_SF=t_fom / t_rom, speedup_SF_block=t_fom_block / t_rom,
+                offline_seconds=t_off,
                 mean_gn_iterations=float(it.mean()), max_gn_iterations=int(it.max()),
                 mae_d_time_avg=float(np.mean(mae)), ae_h_time_avg=float(np.mean(ae)),
                 report=info["report"])
@@ -183,6 +196,7 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
     delta = float(clouds[0].delta)
     ud = None if u is None else torch.tensor(np.asarray(u, np.float32), device=dev)
     maes, aes, t_fom = [], [], []
+    t_fom_block, block_mae, block_nonconv = [], [], 0
     for q, m in enumerate(mus_q):
         cl = make(m, n=n)
         g = torch.tensor(np.asarray(cl.gamma, np.float32), device=dev)
@@ -196,7 +210,21 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
             traj_d[t].copy_(x)
         torch.cuda.synchronize()
         t_fom.append(time.perf_counter() - t0)
+        # the paper's inexact Newton (block Jacobian at every iterate), same loop
+        xb = torch.tensor(xy0, dtype=torch.float32, device=dev)
+        trb_d = torch.empty((steps, 2 * n), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(steps):
+            sb = native.implicit(xb, g, delta, dt, 1, scheme=native.TRAPEZOID, newton_tol=newton_tol, max_newton=100,
+                                 uinf=ud, linear_solver=native.NEWTON_BLOCK)
+            block_nonconv += sb.nonconverged_steps
+            trb_d[t].copy_(xb)
+        torch.cuda.synchronize()
+        t_fom_block.append(time.perf_counter() - t0)
         traj = traj_d.double().cpu().numpy()
+        trb = trb_d.double().cpu().numpy()
+        block_mae.append(float(np.mean([offline.mae_distance(trb[t], traj[t], n, length) for t in range(steps)])))
         rec = xy0[None, :] + hq[q].cpu().numpy() @ Phi.T
         maes.append(float(np.mean([offline.mae_distance(rec[t], traj[t], n, length) for t in range(steps)])))
         hs = []
@@ -205,7 +233,7 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
             h3 = float(native.hamiltonian(torch.tensor(rec[t], dtype=torch.float32, device=dev), g, delta).item())
             hs.append(abs((h3 - h1) / h1))
         aes.append(float(np.mean(hs)))
-        log("query %d: FOM %.2f s, MAE_D %.3e" % (q, t_fom[-1], maes[-1]))
+        log("query %d: FOM %.2f s (block Newton %.2f s), MAE_D %.3e" % (q, t_fom[-1], t_fom_block[-1], maes[-1]))
     it = iq.cpu().numpy()
     return dict(study=case + "_parametric", N=n, M=M, Mr=Mr, ns=ns, pc=pc, tol=tol, steps=steps, dt=dt,
                 mu_lo=lo.tolist(), mu_hi=hi.tolist(), train_mu=mus_train.tolist(), queries=nq,
@@ -213,6 +241,9 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
                 online_batched_seconds=t_batch, online_one_query_seconds=t_one,
                 batched_queries_per_one_query_time=nq * t_one / t_batch,
                 fom_seconds_per_query=float(np.mean(t_fom)), speedup_SF_per_query=float(np.mean(t_fom)) / (t_batch / nq),
+                fom_block_seconds_per_query=float(np.mean(t_fom_block)),
+                speedup_SF_block_per_query=float(np.mean(t_fom_block)) / (t_batch / nq),
+                fom_block_vs_gmres_mae_d_max=float(np.max(block_mae)), fom_block_nonconverged_steps=block_nonconv,
                 mean_gn_iterations=float(it.mean()), max_gn_iterations=int(it.max()),
                 mae_d_time_avg_mean=float(np.mean(maes)), mae_d_time_avg_max=float(np.max(maes)),
                 ae_h_time_avg_mean=float(np.mean(aes)), ae_h_time_avg_max=float(np.max(aes)),

@@ -21,6 +21,7 @@ TUNING_PATH = os.path.join(PKG, "tuning_gfx950.txt")
 PTROM_OK, PTROM_ENOCONV = 0, 1
 BACKWARD_EULER, TRAPEZOID = 0, 1
 JAC_PAPER, JAC_EXACT = 0, 1
+NEWTON_GMRES, NEWTON_BLOCK = 0, 1
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -31,7 +32,8 @@ _f64 = ctypes.c_double
 
 class NewtonOpts(ctypes.Structure):
     _fields_ = [("newton_tol", _f64), ("max_newton", _i32), ("gmres_restart", _i32),
-                ("gmres_maxit", _i32), ("pad", _i32), ("gmres_tol", _f64)]
+                ("gmres_maxit", _i32), ("linear_solver", _i32), ("gmres_tol", _f64),
+                ("jac_period", _i32), ("pad", _i32)]
 
 
 class NewtonStats(ctypes.Structure):
@@ -294,12 +296,16 @@ def rk4_f64(xy, gamma, delta, dt, nsteps):
 
 
 def implicit(xy, gamma, delta, dt, nsteps, scheme=BACKWARD_EULER, newton_tol=1e-6, max_newton=20,
-             gmres_restart=20, gmres_maxit=60, gmres_tol=1e-3, uinf=None):
+             gmres_restart=20, gmres_maxit=60, gmres_tol=1e-3, uinf=None, linear_solver=NEWTON_GMRES,
+             jac_period=0):
     """In place on xy; returns NewtonStats.  Synchronises the stream.
-    ``uinf`` [2N] (device FP32) is an optional background velocity."""
+    ``uinf`` [2N] (device FP32) is an optional background velocity.
+    ``linear_solver`` NEWTON_GMRES (exact Jacobian products) or NEWTON_BLOCK
+    (the paper's per-body block Jacobian, refreshed per ``jac_period``)."""
     n = _n(xy)
     c = context(xy.device)
-    o = NewtonOpts(float(newton_tol), int(max_newton), int(gmres_restart), int(gmres_maxit), 0, float(gmres_tol))
+    o = NewtonOpts(float(newton_tol), int(max_newton), int(gmres_restart), int(gmres_maxit), int(linear_solver),
+                   float(gmres_tol), int(jac_period), 0)
     st = NewtonStats()
     pu = None if uinf is None else _ptr(uinf, torch.float32, 2 * n, "uinf")
     _check(c, lib().ptrom_implicit_forced(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),

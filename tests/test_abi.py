@@ -39,3 +39,31 @@ def test_no_device_create_fails_cleanly():
         return
     h = ctypes.c_void_p()
     assert native.lib().ptrom_create(ctypes.byref(h), 0) != 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # every public struct: size and field offsets as a C compiler lays them
+    # out from include/ptrom.h, against the binding's ctypes mirrors
+    import subprocess
+    mirrors = {"ptrom_newton_opts": native.NewtonOpts, "ptrom_newton_stats": native.NewtonStats,
+               "ptrom_rom_desc": native.RomDesc}
+    src = open(os.path.join(ROOT, "include", "ptrom.h")).read()
+    assert set(re.findall(r"\}\s*(ptrom_[a-z0-9_]+)\s*;", src)) == set(mirrors)
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ptrom.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -71,11 +71,11 @@ def test_implicit_parity(dev, scheme):
     assert rel(xs - xy, o - xy) <= 1e-4
 
 
-@pytest.mark.parametrize("n, restart, nsteps", [(700, 3, 3), (5000, 20, 2)])
+@pytest.mark.parametrize("n, restart, nsteps", [(700, 3, 3), (7000, 20, 1)])
 def test_implicit_gmres_paths_parity(dev, n, restart, nsteps):
     # GMRES orthogonalisation paths: N = 700 with a 3-vector Krylov basis
-    # (the one-workgroup Gram-Schmidt, restarted many times), N = 5000 (the
-    # separate projection kernels over 10000-long vectors)
+    # (the one-workgroup Gram-Schmidt, restarted many times), N = 7000 (the
+    # separate projection kernels over 14000-long vectors)
     c = W.gaussian_patch(n, seed=43, delta=0.01)
     xy, g = f32(c.xy), f32(c.gamma) * 50.0
     x = torch.tensor(xy, dtype=torch.float32, device=dev)
@@ -87,6 +87,36 @@ def test_implicit_gmres_paths_parity(dev, n, restart, nsteps):
     xs = x.cpu().numpy()
     assert rel(xs, o) <= 1e-5
     assert rel(xs - xy, o - xy) <= 1e-4
+
+
+@pytest.mark.parametrize("scheme, period", [(native.BACKWARD_EULER, 0), (native.TRAPEZOID, 0),
+                                            (native.TRAPEZOID, 1), (native.TRAPEZOID, 3)])
+def test_implicit_block_newton_parity(dev, scheme, period):
+    # the paper's inexact Newton (per-body block Jacobian, refreshed at every
+    # iterate or every `period` steps) against the oracle's; no GMRES runs
+    c = W.gaussian_patch(700, seed=41, delta=0.01)
+    xy, g = f32(c.xy), f32(c.gamma) * 50.0
+    u = f32(0.2 * W.mushroom_inflow(700)) if period == 3 else None
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    ud = None if u is None else torch.tensor(u, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, 0.01, 5e-4, 5, scheme=scheme, newton_tol=1e-6, max_newton=100, uinf=ud,
+                         linear_solver=native.NEWTON_BLOCK, jac_period=period)
+    assert st.nonconverged_steps == 0 and st.krylov_iters == 0 and st.newton_iters >= 5
+    o, _ = oracle.implicit_block(xy, g, float(np.float32(0.01)), float(np.float32(5e-4)), 5, scheme=scheme,
+                                 jac_period=period, u=u)
+    xs = x.cpu().numpy()
+    assert rel(xs, o) <= 1e-5
+    assert rel(xs - xy, o - xy) <= 1e-4
+
+
+def test_implicit_options_rejected(dev):
+    x = torch.zeros(20, dtype=torch.float32, device=dev)
+    g = torch.ones(10, dtype=torch.float32, device=dev)
+    for kw in (dict(linear_solver=2), dict(linear_solver=native.NEWTON_BLOCK, jac_period=-1),
+               dict(gmres_restart=201)):
+        with pytest.raises(native.PtromError):
+            native.implicit(x, g, 0.1, 1e-3, 1, **kw)
 
 
 @pytest.mark.parametrize("scheme", [native.BACKWARD_EULER, native.TRAPEZOID])
@@ -122,19 +152,22 @@ def test_implicit_uniform_inflow_translates(dev):
     assert np.abs(xs[1] - (xs[0] + shift)).max() <= 1e-5
 
 
-def test_backward_euler_full_size_residual(dev):
-    # N = 65536 Gaussian patch, backward Euler dt 5e-4: after several steps the
-    # state must satisfy x_n - x_{n-1} - dt f(x_n) = 0 on sampled rows, with f
-    # from the oracle.
+@pytest.mark.parametrize("solver", [native.NEWTON_GMRES, native.NEWTON_BLOCK])
+def test_backward_euler_full_size_residual(dev, solver):
+    # N = 65536 Gaussian patch, backward Euler dt 5e-4, exact-Jacobian GMRES
+    # or the paper's block Jacobian: after several steps the state must
+    # satisfy x_n - x_{n-1} - dt f(x_n) = 0 on sampled rows, with f from the
+    # oracle.
     cfg = W.CONFIGS["c2_gaussian_patch"]
     c = W.config_cloud("c2_gaussian_patch")
     n = c.n
     x = torch.tensor(c.xy, dtype=torch.float32, device=dev)
     gd = torch.tensor(c.gamma, dtype=torch.float32, device=dev)
-    st = native.implicit(x, gd, c.delta, cfg["dt"], 3)
+    kw = dict(linear_solver=solver, max_newton=100 if solver == native.NEWTON_BLOCK else 20)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], 3, **kw)
     assert st.nonconverged_steps == 0
     xprev = x.cpu().numpy().astype(np.float64)
-    st = native.implicit(x, gd, c.delta, cfg["dt"], 1)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], 1, **kw)
     assert st.nonconverged_steps == 0
     xn = x.cpu().numpy().astype(np.float64)
     idx = np.random.default_rng(1).choice(n, 128, replace=False)
