@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,rom,next)")
+    p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,implicit,rom,next)")
     p.add_argument("--gather-ns", default="16,256,2048,16384",
                    help="sample-set sizes of the HyperPair gather sweep (rom form)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +310,12 @@ def run_forms(native, W, dev, only, plain_pairs_per_s, gather_ns=(16, 256, 2048,
                             "note": "backward = recompute (velocity) + vector-Jacobian pair kernels"}
         del holder
 
+    if not only or "implicit" in only:
+        log("form: implicit")
+        try:
+            forms["implicit"] = implicit_form(native, W, dev)
+        except Exception as e:
+            forms["implicit"] = {"error": repr(e)}
     if not only or "rom" in only:
         log("form: rom")
         try:
@@ -323,6 +329,50 @@ def run_forms(native, W, dev, only, plain_pairs_per_s, gather_ns=(16, 256, 2048,
         except Exception as e:
             forms["next"] = {"error": repr(e)}
     return forms
+
+
+def implicit_form(native, W, dev):
+    """The implicit FOM with both Newton linear models: the N = 65536 patch
+    (50 backward-Euler steps, as in the timed step) and the vortex pair at the
+    paper's size (N = 500, trapezoid, dt = 0.01, end circulations 255)."""
+    import torch
+    out = {}
+    cases = []
+    cfg = W.CONFIGS["c2_gaussian_patch"]
+    cl = W.config_cloud("c2_gaussian_patch")
+    cases.append(("gaussian_patch_n65536_be", cl, float(cl.delta), float(cfg["dt"]), cfg["steps"],
+                  native.BACKWARD_EULER, 1e-6))
+    vp = W.vortex_pair((255.0, 255.0), n=500)
+    cases.append(("vortex_pair_n500_trapezoid", vp, float(vp.delta), 0.01, 100, native.TRAPEZOID, 2e-5))
+    for name, c, d, dt, steps, scheme, tol in cases:
+        n = c.n
+        x0 = torch.tensor(np.asarray(c.xy, np.float32), device=dev)
+        g = torch.tensor(np.asarray(c.gamma, np.float32), device=dev)
+        pairs = float(n) * (n - 1)
+        row, finals = {"N": n, "steps": steps, "dt": dt}, {}
+        for label, kw in (("gmres", dict(linear_solver=native.NEWTON_GMRES, gmres_tol=1e-3)),
+                          ("block", dict(linear_solver=native.NEWTON_BLOCK, max_newton=100))):
+            x = x0.clone()
+            native.implicit(x, g, d, dt, 2, scheme=scheme, newton_tol=tol, **kw)  # warm-up
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = native.implicit(x, g, d, dt, steps, scheme=scheme, newton_tol=tol, **kw)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            # pair evaluations: a velocity per step and per Newton iterate, plus
+            # a JVP per Krylov vector (GMRES) or a block Jacobian per iterate
+            evals = steps + st.newton_iters + (st.krylov_iters if label == "gmres" else st.newton_iters)
+            row[label] = {"seconds": sec, "ms_per_step": 1e3 * sec / steps,
+                          "newton_iters_per_step": st.newton_iters / steps,
+                          "krylov_iters_per_step": st.krylov_iters / steps,
+                          "nonconverged_steps": st.nonconverged_steps,
+                          "pairs_per_s": evals * pairs / sec}
+            finals[label] = x
+        disp = torch.linalg.norm((finals["gmres"] - x0).double())
+        row["block_vs_gmres_final_rel"] = float(torch.linalg.norm((finals["block"] - finals["gmres"]).double()) / disp)
+        out[name] = row
+    return out
 
 
 # FLOP per pair of the stream-function term: separation (2), |r|^2 + delta^2

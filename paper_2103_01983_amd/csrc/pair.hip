@@ -46,7 +46,12 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Adds the per-chunk partials in chunk order (compensated) and stores.
+// Adds the per-chunk partials in chunk order (compensated) and stores.  The
+// partials are loaded kRedBatch chunks at a time, all loads issued before the
+// additions, so a small launch waits on a few memory round trips rather than
+// one per chunk; the order of the additions is the chunk order.
+constexpr int kRedBatch = 8;
+
 template <int OP>
 __global__ void __launch_bounds__(256)
     reduce_kernel(int n, int nsplit, const float *__restrict__ ws, float *__restrict__ out,
@@ -54,13 +59,26 @@ __global__ void __launch_bounds__(256)
   constexpr int NA = Traits<OP>::NACC;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  float s[NA], c[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) s[a] = c[a] = 0.0f;
+  for (int p0 = 0; p0 < nsplit; p0 += kRedBatch) {
+    const int cnt = min(kRedBatch, nsplit - p0);
+    float t[kRedBatch][NA];
+#pragma unroll
+    for (int u = 0; u < kRedBatch; ++u)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) t[u][a] = u < cnt ? ws[(size_t)((p0 + u) * NA + a) * n + i] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kRedBatch; ++u)
+      if (u < cnt) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) kahan_add(s[a], c[a], t[u][a]);
+      }
+  }
   float v[NA];
 #pragma unroll
-  for (int a = 0; a < NA; ++a) {
-    float s = 0.0f, c = 0.0f;
-    for (int p = 0; p < nsplit; ++p) kahan_add(s, c, ws[(size_t)(p * NA + a) * n + i]);
-    v[a] = s - c;
-  }
+  for (int a = 0; a < NA; ++a) v[a] = s[a] - c[a];
   store_final<OP>(n, i, v, out, out2);
 }
 
