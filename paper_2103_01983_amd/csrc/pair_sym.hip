@@ -4,7 +4,8 @@
 // body j receives from body i is the term body i receives from j with
 // Gamma_j replaced by Gamma_i and the sign flipped (velocity: u(-r) = -u(r);
 // Jacobian product: H(-r) = H(r) and v_j - v_i = -(v_i - v_j); adjoint:
-// q_ji = -q_ij).  The body index range is cut into blocks of 256*K; block
+// q_ji = -q_ij).  The self blocks of the Jacobian are symmetric instead:
+// H(-r) = H(r), so body j's block gains Gamma_i H(r) with the same sign.  The body index range is cut into blocks of 256*K; block
 // pairs (I, J) with J > I are evaluated once, each interaction adding the
 // forward term to the target (registers) and the reaction term to the
 // source; diagonal blocks (I, I) use the ordinary one-sided tile.
@@ -53,6 +54,20 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
     acc[1] = fmaf(gj, wx, acc[1]);
     react[0] = fmaf(gi, wy, react[0]);
     react[1] = fmaf(-gi, wx, react[1]);
+  } else if constexpr (OP == OP_BJAC) {
+    // entries 0..2 of q^-2 [2 rx ry, ry^2 - rx^2 - d^2; ry^2 - rx^2 + d^2, -2 rx ry]
+    // (Gamma r) r as in the one-sided kernel, which keeps Gamma / q^2 finite
+    // wherever that one is
+    const float h0 = (dx + dx) * dy;
+    const float m = fmaf(dy, dy, -dx * dx);
+    const float h1 = m - d2, h2 = m + d2;
+    const float gj = (s[2] * r) * r, gi = (t[4] * r) * r;
+    acc[0] = fmaf(gj, h0, acc[0]);
+    acc[1] = fmaf(gj, h1, acc[1]);
+    acc[2] = fmaf(gj, h2, acc[2]);
+    react[0] = fmaf(gi, h0, react[0]);
+    react[1] = fmaf(gi, h1, react[1]);
+    react[2] = fmaf(gi, h2, react[2]);
   } else {
     const float qx = fmaf(s[2], t[2], -t[4] * s[3]);
     const float qy = fmaf(s[2], t[3], -t[4] * s[4]);
@@ -277,7 +292,7 @@ hipError_t launch_sym_op(int k, int n, const float *xy, const float *gam, const 
 size_t pair_sym_ws_floats(int op, int k, int64_t n) {
   const int64_t tb = kBlock * int64_t(k);
   const int64_t nb = (n + tb - 1) / tb;
-  const int na = op == OP_VJP ? 3 : 2;
+  const int na = (op == OP_VJP || op == OP_BJAC) ? 3 : 2;
   return size_t(2 * nb * na * n + 64);
 }
 
@@ -292,6 +307,7 @@ hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64
     case OP_VEL: return launch_sym_op<OP_VEL>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     case OP_JVP: return launch_sym_op<OP_JVP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     case OP_VJP: return launch_sym_op<OP_VJP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
+    case OP_BJAC: return launch_sym_op<OP_BJAC>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -26,7 +26,7 @@ def vctx(request, dev):
     fd, path = tempfile.mkstemp(suffix=".txt")
     with os.fdopen(fd, "w") as fh:
         for op in ("velocity", "jvp", "vjp", "block_jacobian"):
-            fh.write("%s 16 %d %d %d %d\n" % (op, st, k, w, sym if op != "block_jacobian" else 0))
+            fh.write("%s 16 %d %d %d %d\n" % (op, st, k, w, sym))
     h = native.make_context(0, path)
     os.unlink(path)
     yield h
