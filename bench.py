@@ -39,7 +39,7 @@ FLOP_PER_PAIR = {"velocity": 12, "jvp": 23, "vjp": 31, "block_jacobian": 22}
 # the shared distance/reciprocal terms once, the forward and reaction
 # accumulations, and the per-step lane rotation of the reaction accumulators
 SYM_FLOP_PER_UNORDERED_PAIR = {"velocity": 19, "jvp": 30, "vjp": 41}
-PAIR_SOURCES = ("pair_core.h", "pair.hip", "pair_sym.hip")
+PAIR_SOURCES = ("pair_core.h", "pair_sym_core.h", "pair.hip", "pair_sym.hip")
 OP_ID = {"velocity": 0, "block_jacobian": 1, "jvp": 2, "vjp": 3, "stream_function": 4}
 
 

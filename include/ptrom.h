@@ -191,6 +191,10 @@ int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const float *gam
  *   offsets (host) [nb+1]: instance b owns bodies offsets[b]..offsets[b+1]-1;
  *   xy: instance b's SoA block [x..., y...] occupies xy[2*offsets[b] .. 2*offsets[b+1]);
  *   gamma[offsets[nb]]; delta (host) [nb] per-instance cores.
+ * Every unordered pair of an instance is evaluated once (blocks of 512
+ * bodies); EINVAL when the instances hold more than 2^24 block pairs in
+ * total (one instance of about 2.9 million bodies).  The workspace holds one
+ * slot per block and body: 8 * sum_b ceil(N_b / 512) * N_b bytes.
  * ---------------------------------------------------------------------- */
 int ptrom_velocity_batched(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float *xy,
                            const float *gamma, const float *delta, float *f, ptrom_stream stream);

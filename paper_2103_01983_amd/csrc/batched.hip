@@ -1,80 +1,117 @@
 // Many independent parametric instances (own N_b, own core delta_b) in one
-// persistent launch per velocity evaluation.  The host cuts every instance
-// into work items (instance, block of 512 targets, chunk of 4096 sources),
-// sorts them by pair count (largest first) and uploads the list once per
-// instance set; every workgroup then pops items from a device counter until
-// the list is exhausted, so large and small instances share the chip without
-// a tail.  Items write compensated partial sums per source chunk; a second
-// kernel adds each body's chunks in chunk order (bitwise reproducible).
+// persistent launch per velocity evaluation, every unordered pair of an
+// instance evaluated once.  The host cuts every instance into blocks of 512
+// bodies and lists its block pairs (instance, I, J), J >= I, sorted by pair
+// count (largest first), once per instance set; every workgroup then pops
+// items from a device counter until the list is exhausted, so large and
+// small instances share the chip without a tail.  Off-diagonal items run
+// the each-pair-once sweep (forward sums to the targets, rotated reactions
+// to the sources); diagonal items the one-sided tile.  Instance b keeps one
+// slot per block, P_b[slot][2][N_b]: a body of block B receives forward
+// sums in slots J >= B and reactions in slots I < B, each written once.  A
+// second kernel adds each body's slots in a fixed order (bitwise
+// reproducible).
 #include <algorithm>
 #include <cstring>
 #include <memory>
 #include <numeric>
 
-#include "pair_core.h"
+#include "pair_sym_core.h"
 
 namespace ptrom {
 namespace {
 
-constexpr int kBatchK = 2;                      // targets per lane
-constexpr int kBatchTargets = kBlock * kBatchK;  // targets per item
-constexpr int kChunk = 16 * kTile;              // sources per item
+constexpr int kBatchK = 2;                   // targets per lane
+constexpr int kBatchTB = kBlock * kBatchK;   // bodies per block
 constexpr int kBlocksPerCU = 8;
+constexpr int64_t kMaxBatchItems = int64_t(1) << 24;
+constexpr int kNA = Traits<OP_VEL>::NACC;
 
 __global__ void reset_counter_kernel(int *__restrict__ counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
 
-template <int STAGING>
-__global__ void __launch_bounds__(kBlock)
-    batched_velocity_kernel(const int4 *__restrict__ items, int n_items, int *__restrict__ counter,
-                            const int *__restrict__ off, const float *__restrict__ d2s,
-                            const float *__restrict__ xy, const float *__restrict__ gam, int total,
-                            float *__restrict__ part) {
-  __shared__ float lds[STAGING == STAGE_LDS ? 3 * kTile : 1];
+// (at most 64 VGPRs: eight waves per SIMD, as the single-system kernel
+// reaches without the bound)
+__global__ void __launch_bounds__(kBlock, 8)
+    batched_sym_kernel(const int4 *__restrict__ items, int n_items, int *__restrict__ counter,
+                       const int *__restrict__ off, const float *__restrict__ d2s,
+                       const int64_t *__restrict__ slot_off, const float *__restrict__ xy,
+                       const float *__restrict__ gam, float *__restrict__ P) {
+  constexpr int NS = Traits<OP_VEL>::NSRC;
+  __shared__ float4 s_src[128][2];
+  __shared__ float racc_lds[kBlock / 64][kNA][64];
+  __shared__ float lds_diag[NS * kTile];
   __shared__ int item_s;
+  const int tid = threadIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+    if (tid == 0) item_s = atomicAdd(counter, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(item_s);
     __syncthreads();  // everyone has read item_s before it is overwritten
     if (it >= n_items) break;
     const int4 w = items[it];
-    const int b = w.x;
+    const int b = w.x, I = w.y, J = w.z;
     const int o = off[b];
-    const int nb = off[b + 1] - o;
-    const int tgt0 = w.y * kBatchTargets;
-    const int sb = w.z * kChunk;
-    const int se = min(nb, sb + kChunk);
-    float res[kBatchK][2];
-    pair_block<OP_VEL, kBatchK, STAGING>(nb, xy + 2 * (size_t)o, gam + o, nullptr, d2s[b], tgt0, sb,
-                                         se, lds, res);
+    const int n = off[b + 1] - o;
+    const float *xb = xy + 2 * (size_t)o;
+    const float *gb = gam + o;
+    float *Pb = P + slot_off[b];
+    const float d2 = d2s[b];
+    const int tgt0 = I * kBatchTB;
+    if (I == J) {
+      float res[kBatchK][kNA];
+      pair_block<OP_VEL, kBatchK, STAGE_LDS>(n, xb, gb, nullptr, d2, tgt0, tgt0, min(n, tgt0 + kBatchTB), lds_diag,
+                                              res);
 #pragma unroll
-    for (int k = 0; k < kBatchK; ++k) {
-      const int i = tgt0 + k * kBlock + threadIdx.x;
-      if (i < nb) {
-        part[(size_t)(w.z * 2) * total + o + i] = res[k][0];
-        part[(size_t)(w.z * 2 + 1) * total + o + i] = res[k][1];
+      for (int k = 0; k < kBatchK; ++k) {
+        const int i = tgt0 + k * kBlock + tid;
+        if (i < n)
+#pragma unroll
+          for (int a = 0; a < kNA; ++a) Pb[(size_t)(I * kNA + a) * n + i] = res[k][a];
       }
+      continue;
     }
+    sym_block_pair<OP_VEL, kBatchK>(n, xb, gb, nullptr, d2, tgt0, J * kBatchTB, s_src, racc_lds,
+                                    Pb + (size_t)J * kNA * n, Pb + (size_t)I * kNA * n);
   }
 }
 
+// Per body: its forward slots B .. nbk-1, then its reaction slots 0 .. B-1,
+// Kahan-compensated, loads issued eight slots at a time.
 __global__ void __launch_bounds__(256)
-    batched_reduce_kernel(int total, const int *__restrict__ inst, const int *__restrict__ off,
-                          const int *__restrict__ nsplit, const float *__restrict__ part,
-                          float *__restrict__ out) {
+    batched_sym_reduce_kernel(int total, const int *__restrict__ inst, const int *__restrict__ off,
+                              const int64_t *__restrict__ slot_off, const float *__restrict__ P,
+                              float *__restrict__ out) {
+  constexpr int kB = 8;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int b = inst[g];
   const int o = off[b];
-  const int nb = off[b + 1] - o;
-  const int S = nsplit[b];
-  for (int q = 0; q < 2; ++q) {
-    float s = 0.0f, c = 0.0f;
-    for (int p = 0; p < S; ++p) kahan_add(s, c, part[(size_t)(p * 2 + q) * total + g]);
-    out[2 * (size_t)o + (size_t)q * nb + (g - o)] = (s - c) * kInv2Pi;
+  const int n = off[b + 1] - o;
+  const int i = g - o;
+  const int B = i / kBatchTB, nbk = (n + kBatchTB - 1) / kBatchTB;
+  const float *Pb = P + slot_off[b];
+  float s[kNA] = {}, c[kNA] = {};
+  for (int q0 = 0; q0 < nbk; q0 += kB) {
+    const int cnt = min(kB, nbk - q0);
+    float t[kB][kNA];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int q = q0 + u;
+      const int slot = q < nbk - B ? B + q : q - (nbk - B);
+#pragma unroll
+      for (int a = 0; a < kNA; ++a) t[u][a] = u < cnt ? Pb[(size_t)(slot * kNA + a) * n + i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (u < cnt) {
+#pragma unroll
+        for (int a = 0; a < kNA; ++a) kahan_add(s[a], c[a], t[u][a]);
+      }
   }
+#pragma unroll
+  for (int a = 0; a < kNA; ++a) out[2 * (size_t)o + (size_t)a * n + i] = (s[a] - c[a]) * kInv2Pi;
 }
 
 }  // namespace
@@ -83,10 +120,12 @@ __global__ void __launch_bounds__(256)
 struct BatchPlan {
   std::vector<int64_t> offsets;
   std::vector<float> delta;
-  int nb = 0, total = 0, n_items = 0, max_split = 0, staging = STAGE_SCALAR;
-  void *buf = nullptr;  // items | off | d2 | nsplit | inst | counter
+  int nb = 0, total = 0, n_items = 0;
+  size_t slot_floats = 0;  // per-block slots of all instances, sum of nbk_b * 2 * N_b
+  void *buf = nullptr;     // items | off | d2 | slot_off | inst | counter
   int4 *items = nullptr;
-  int *off = nullptr, *nsplit = nullptr, *inst = nullptr, *counter = nullptr;
+  int *off = nullptr, *inst = nullptr, *counter = nullptr;
+  int64_t *slot_off = nullptr;
   float *d2 = nullptr;
   ~BatchPlan() {
     if (buf) hipFree(buf);
@@ -117,39 +156,51 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
   p->delta.assign(delta, delta + nb);
   p->nb = nb;
   p->total = int(offsets[nb]);
-  p->staging = ctx->tune.get(OP_VEL, 8192).staging;
   struct It {
     int4 v;
     int64_t cost;
   };
   std::vector<It> items;
-  std::vector<int> nsplit(nb), off32(nb + 1), inst(p->total);
+  std::vector<int> off32(nb + 1), inst(p->total);
+  std::vector<int64_t> slot_off(nb);
   std::vector<float> d2(nb);
+  int64_t n_items = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t n = offsets[b + 1] - offsets[b];
+    const int64_t nbk = (n + kBatchTB - 1) / kBatchTB;
+    n_items += nbk * (nbk + 1) / 2;
+  }
+  if (n_items > kMaxBatchItems)
+    return ctx->fail(PTROM_EINVAL, "instances too large for one batched launch (block pairs > 2^24)");
+  items.reserve(size_t(n_items));
+  size_t slots = 0;
   for (int b = 0; b < nb; ++b) {
     const int n = int(offsets[b + 1] - offsets[b]);
-    const int T = (n + kBatchTargets - 1) / kBatchTargets;
-    const int S = (n + kChunk - 1) / kChunk;
-    nsplit[b] = S;
-    p->max_split = std::max(p->max_split, S);
+    const int nbk = (n + kBatchTB - 1) / kBatchTB;
+    slot_off[b] = int64_t(slots);
+    slots += size_t(nbk) * kNA * size_t(n);
     off32[b] = int(offsets[b]);
     d2[b] = delta[b] * delta[b];
     for (int i = int(offsets[b]); i < int(offsets[b + 1]); ++i) inst[i] = b;
-    for (int t = 0; t < T; ++t)
-      for (int s = 0; s < S; ++s) {
-        const int64_t nt = std::min(kBatchTargets, n - t * kBatchTargets);
-        const int64_t ns = std::min(kChunk, n - s * kChunk);
-        items.push_back({make_int4(b, t, s, 0), nt * ns});
+    for (int I = 0; I < nbk; ++I)
+      for (int J = I; J < nbk; ++J) {
+        const int64_t nt = std::min(kBatchTB, n - I * kBatchTB);
+        const int64_t ns = std::min(kBatchTB, n - J * kBatchTB);
+        // one-sided diagonal tile: nt^2 ordered pairs; off-diagonal: nt ns
+        // unordered pairs at about 1.5 times the one-sided cost per pair
+        items.push_back({make_int4(b, I, J, 0), I == J ? nt * nt : 3 * nt * ns / 2});
       }
   }
+  p->slot_floats = slots;
   off32[nb] = p->total;
   std::stable_sort(items.begin(), items.end(), [](const It &a, const It &b) { return a.cost > b.cost; });
   p->n_items = int(items.size());
   std::vector<int4> iv(items.size());
   for (size_t q = 0; q < items.size(); ++q) iv[q] = items[q].v;
   const size_t b_items = align256(iv.size() * sizeof(int4)), b_off = align256((nb + 1) * sizeof(int)),
-               b_d2 = align256(nb * sizeof(float)), b_ns = align256(nb * sizeof(int)),
+               b_d2 = align256(nb * sizeof(float)), b_so = align256(nb * sizeof(int64_t)),
                b_inst = align256(size_t(p->total) * sizeof(int)), b_cnt = 256;
-  hipError_t e = hipMalloc(&p->buf, b_items + b_off + b_d2 + b_ns + b_inst + b_cnt);
+  hipError_t e = hipMalloc(&p->buf, b_items + b_off + b_d2 + b_so + b_inst + b_cnt);
   if (e != hipSuccess) {
     p->buf = nullptr;
     return ctx->fail(PTROM_ENOMEM, "batched plan allocation");
@@ -158,13 +209,13 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
   p->items = reinterpret_cast<int4 *>(q); q += b_items;
   p->off = reinterpret_cast<int *>(q); q += b_off;
   p->d2 = reinterpret_cast<float *>(q); q += b_d2;
-  p->nsplit = reinterpret_cast<int *>(q); q += b_ns;
+  p->slot_off = reinterpret_cast<int64_t *>(q); q += b_so;
   p->inst = reinterpret_cast<int *>(q); q += b_inst;
   p->counter = reinterpret_cast<int *>(q);
   e = hipMemcpy(p->items, iv.data(), iv.size() * sizeof(int4), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->off, off32.data(), (nb + 1) * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d2, d2.data(), nb * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->nsplit, nsplit.data(), nb * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->slot_off, slot_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->inst, inst.data(), size_t(p->total) * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return ctx->hip_fail(e, "batched plan upload");
   // graphs captured for an earlier instance set reference its buffers
@@ -175,19 +226,15 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
   return PTROM_OK;
 }
 
-// counter reset + persistent pass + chunk reduction, all stream-ordered
+// counter reset + persistent pass + slot reduction, all stream-ordered
 static hipError_t launch_batched_velocity(ptrom_ctx *ctx, const BatchPlan &p, const float *xy,
-                                          const float *gamma, float *f, float *part, hipStream_t st) {
+                                          const float *gamma, float *f, float *slots, hipStream_t st) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, p.counter);
   const dim3 grid(ctx->num_cus * kBlocksPerCU);
-  if (p.staging == STAGE_LDS)
-    hipLaunchKernelGGL(batched_velocity_kernel<STAGE_LDS>, grid, dim3(kBlock), 0, st, p.items, p.n_items,
-                       p.counter, p.off, p.d2, xy, gamma, p.total, part);
-  else
-    hipLaunchKernelGGL(batched_velocity_kernel<STAGE_SCALAR>, grid, dim3(kBlock), 0, st, p.items,
-                       p.n_items, p.counter, p.off, p.d2, xy, gamma, p.total, part);
-  hipLaunchKernelGGL(batched_reduce_kernel, dim3((p.total + 255) / 256), dim3(256), 0, st, p.total,
-                     p.inst, p.off, p.nsplit, part, f);
+  hipLaunchKernelGGL(batched_sym_kernel, grid, dim3(kBlock), 0, st, p.items, p.n_items, p.counter, p.off, p.d2,
+                     p.slot_off, xy, gamma, slots);
+  hipLaunchKernelGGL(batched_sym_reduce_kernel, dim3((p.total + 255) / 256), dim3(256), 0, st, p.total, p.inst,
+                     p.off, p.slot_off, slots, f);
   return hipGetLastError();
 }
 
@@ -200,7 +247,7 @@ extern "C" int ptrom_velocity_batched(ptrom_ctx *ctx, int nb, const int64_t *off
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
   std::shared_ptr<BatchPlan> p;
   if (int rc = get_plan(ctx, nb, offsets, delta, p)) return rc;
-  const size_t partf = size_t(p->max_split) * 2 * p->total;
+  const size_t partf = p->slot_floats;
   if (int rc = ctx->reserve(partf * sizeof(float))) return rc;
   hipError_t e = launch_batched_velocity(ctx, *p, xy, gamma, f, static_cast<float *>(ctx->ws),
                                          (hipStream_t)stream);
@@ -220,7 +267,7 @@ extern "C" int ptrom_rk4_batched(ptrom_ctx *ctx, int nb, const int64_t *offsets,
   if (int rc = get_plan(ctx, nb, offsets, delta, p)) return rc;
   if (nsteps == 0) return PTROM_OK;
   const int64_t m = 2 * int64_t(p->total);
-  const size_t partf = size_t(p->max_split) * 2 * p->total;
+  const size_t partf = p->slot_floats;
   if (int rc = ctx->reserve(5 * align256(m * sizeof(float)) + align256(partf * sizeof(float)) + 256)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
   float *k[4];
