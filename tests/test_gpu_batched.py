@@ -105,3 +105,12 @@ def test_batched_rejects_bad_offsets(dev):
     g = torch.zeros(4, device=dev)
     with pytest.raises(native.PtromError):
         native.velocity_batched([0, 2, 2, 4], x, g, [0.1, 0.1, 0.1])
+
+
+def test_batched_rejects_too_many_block_pairs(dev):
+    # one instance of 3e6 bodies: 5860 blocks of 512, 17.2e6 block pairs > 2^24
+    n = 3_000_000
+    x = torch.zeros(2 * n, device=dev)
+    g = torch.zeros(n, device=dev)
+    with pytest.raises(native.PtromError):
+        native.velocity_batched([0, n], x, g, [0.1])
