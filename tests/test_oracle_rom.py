@@ -369,3 +369,53 @@ def test_hyperpair_velocity_includes_the_background(small_problem):
     np.testing.assert_allclose(fb1, fb0 + u[rows], rtol=0, atol=1e-15)
     np.testing.assert_allclose(rb1, rb0 - 0.5e-3 * u[rows], rtol=0, atol=1e-15)
     np.testing.assert_array_equal(C1, C0)
+
+
+def test_one_gauss_newton_iteration_solves_a_linear_residual(small_problem):
+    # With every surrogate strength zero and a background velocity u, the
+    # sampled residual Phibar (xhat - xhat_prev) - dt ubar is linear in xhat:
+    # the first Gauss-Newton step of every time step lands on the
+    # least-squares minimiser of |A (Phibar d - dt ubar)| and the next one
+    # finds a zero gradient.
+    cl, _, Phi, sig, tree = small_problem
+    n = cl.n
+    sample = np.array([3, 40, 77, 120, 150, 190])
+    u = np.random.default_rng(4).standard_normal(2 * n)
+    A = np.random.default_rng(5).standard_normal((9, 12))
+    art = off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A, u=u)
+    art["Gt"] = np.zeros_like(art["Gt"])
+    out = oracle.Rom(art).run(3, tol=1e-10, max_iter=10)
+    rows = off.sampled_rows(sample, n)
+    step = np.linalg.lstsq(A @ Phi[rows], A @ (1e-3 * u[rows]), rcond=None)[0]
+    for t in range(3):
+        np.testing.assert_allclose(out["hist"][t], (t + 1) * step, rtol=1e-10, atol=1e-15)
+    assert out["status"] == 0 and np.all(out["iters"] <= 2)
+
+
+def test_gnat_with_full_sample_and_full_residual_basis_is_lspg():
+    # n_s = N sampled bodies and a residual basis spanning every residual the
+    # LSPG iterations produce: A = Phi_r^T weighs those residuals exactly as
+    # the unweighted norm does, so GNAT follows LSPG iterate by iterate.
+    cl = W.gaussian_patch(40, seed=9, delta=0.05)
+    g = cl.gamma * 40
+    dt, T = 2e-3, 5
+    S = off.trapezoid_snapshots(cl.xy, g, cl.delta, dt, T)
+    Phi, sig = off.pod(S, 3, x0=cl.xy)
+    tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+    lspg = oracle.Rom(off.rom_artifacts(np.arange(40), tree, 1.0, cl.xy, Phi, g, cl.delta, dt)).run(
+        T, tol=1e-12, max_iter=8, resid_cap=T * 8)
+    R = lspg["resid"].T
+    U, s, _ = np.linalg.svd(R, full_matrices=False)
+    Phi_r = U[:, s > 1e-12 * s[0]]
+    assert Phi_r.shape[1] < 80
+    A = np.linalg.pinv(Phi_r[off.sampled_rows(np.arange(40), 40)])
+    gnat = oracle.Rom(off.rom_artifacts(np.arange(40), tree, 1.0, cl.xy, Phi, g, cl.delta, dt, A=A)).run(
+        T, tol=1e-12, max_iter=8)
+    np.testing.assert_array_equal(gnat["iters"], lspg["iters"])
+    np.testing.assert_allclose(gnat["hist"], lspg["hist"], rtol=1e-9, atol=1e-12)
+    # a residual basis missing one of those directions weighs them
+    # differently and moves the minimiser
+    A2 = np.linalg.pinv(np.delete(Phi_r, 1, axis=1)[off.sampled_rows(np.arange(40), 40)])
+    moved = oracle.Rom(off.rom_artifacts(np.arange(40), tree, 1.0, cl.xy, Phi, g, cl.delta, dt, A=A2)).run(
+        T, tol=1e-12, max_iter=8)
+    assert np.abs(moved["hist"] - lspg["hist"]).max() > 1e-4
