@@ -83,6 +83,7 @@ def lib():
                                   ctypes.POINTER(NewtonStats)]
         L.or_implicit_forced.argtypes = [i64, _dp, _dp, dbl, _dp, dbl, i32, i32, dbl, i32, dbl, i32, i32,
                                          ctypes.POINTER(NewtonStats)]
+        L.or_block_jacobian_at.argtypes = [i64, _dp, _dp, dbl, i64, _i64p, _dp]
         L.or_implicit_block.argtypes = [i64, _dp, _dp, dbl, _dp, dbl, i32, i32, dbl, i32, i32,
                                         ctypes.POINTER(NewtonStats)]
         L.or_rk4_adjoint.argtypes = [i64, _dp, _dp, dbl, dbl, i32, _dp, _dp, _dp, _dp, _dp]
@@ -146,6 +147,15 @@ def jvp_at(xy, gamma, delta, v, idx):
     xy, pxy = _d(xy); g, pg = _d(gamma); v, pv = _d(v); idx, pi = _i(idx)
     out = np.empty(2 * idx.size)
     lib().or_jvp_at(n, pxy, pg, float(delta), pv, idx.size, pi, out.ctypes.data_as(_dp))
+    return out
+
+
+def block_jacobian_at(xy, gamma, delta, idx):
+    """The 2x2 blocks of the targets ``idx`` only; returns [4][len(idx)] flattened."""
+    n = _n(xy)
+    xy, pxy = _d(xy); g, pg = _d(gamma); idx, pi = _i(idx)
+    out = np.empty(4 * idx.size)
+    lib().or_block_jacobian_at(n, pxy, pg, float(delta), idx.size, pi, out.ctypes.data_as(_dp))
     return out
 
 

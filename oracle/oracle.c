@@ -112,19 +112,38 @@ void or_jvp_at(int64_t n, const double *xy, const double *gam, double delta, con
 }
 
 /* Per-target 2x2 block of df/dx (the paper's inexact "diagonal block"
- * Jacobian): B_i = sum_{j != i} gamma_j du/dr(r_ij).  Layout [4][N]. */
+ * Jacobian): B_i = sum_{j != i} gamma_j du/dr(r_ij), entries row-major. */
+static void bjac_one(int64_t n, const double *xy, const double *gam, double d2, int64_t i, double b[4]) {
+  for (int q = 0; q < 4; ++q) b[q] = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (j == i) continue;
+    double h[4];
+    du_dr(xy[i] - xy[j], xy[n + i] - xy[n + j], d2, h);
+    for (int q = 0; q < 4; ++q) b[q] += gam[j] * h[q];
+  }
+  for (int q = 0; q < 4; ++q) b[q] /= OR_TWO_PI;
+}
+
+/* All blocks, layout [4][N]. */
 void or_block_jacobian(int64_t n, const double *xy, const double *gam, double delta, double *B) {
   const double d2 = delta * delta;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    double b[4] = {0, 0, 0, 0};
-    for (int64_t j = 0; j < n; ++j) {
-      if (j == i) continue;
-      double h[4];
-      du_dr(xy[i] - xy[j], xy[n + i] - xy[n + j], d2, h);
-      for (int q = 0; q < 4; ++q) b[q] += gam[j] * h[q];
-    }
-    for (int q = 0; q < 4; ++q) B[q * n + i] = b[q] / OR_TWO_PI;
+    double b[4];
+    bjac_one(n, xy, gam, d2, i, b);
+    for (int q = 0; q < 4; ++q) B[q * n + i] = b[q];
+  }
+}
+
+/* The blocks of the targets idx[0..nt), layout [4][nt]. */
+void or_block_jacobian_at(int64_t n, const double *xy, const double *gam, double delta, int64_t nt,
+                          const int64_t *idx, double *out) {
+  const double d2 = delta * delta;
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nt; ++t) {
+    double b[4];
+    bjac_one(n, xy, gam, d2, idx[t], b);
+    for (int q = 0; q < 4; ++q) out[q * nt + t] = b[q];
   }
 }
 

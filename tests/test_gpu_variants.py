@@ -91,3 +91,5 @@ def test_variant_full_size_sampled(dev, vctx):
     ox, og = oracle.vjp_at(xy, g, d, v, idx)
     assert rel(gx.cpu().numpy()[sel], ox) <= 1e-5
     assert rel(gg.cpu().numpy()[idx], og) <= 1e-5
+    B = native.block_jacobian(xd, gd, d, ctx=vctx).cpu().numpy().reshape(4, n)
+    assert rel(B[:, idx].ravel(), oracle.block_jacobian_at(xy, g, d, idx)) <= 1e-5

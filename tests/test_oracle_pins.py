@@ -198,6 +198,8 @@ def test_sampled_entry_points_match_full():
     ax, ag = oracle.vjp_at(xy, g, d, v, idx)
     np.testing.assert_array_equal(ax, np.concatenate([gx[idx], gx[n + idx]]))
     np.testing.assert_array_equal(ag, gg[idx])
+    B = oracle.block_jacobian(xy, g, d).reshape(4, n)
+    np.testing.assert_array_equal(oracle.block_jacobian_at(xy, g, d, idx), B[:, idx].ravel())
 
 
 # ---------------------------------------------------------------- steppers
