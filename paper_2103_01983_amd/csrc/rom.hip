@@ -136,6 +136,7 @@ __device__ __forceinline__ void sampled_position(const float *Phibar, const floa
 constexpr int kMaxEw = 4 + 2 * kSmallM;
 
 constexpr int kShortEw = 36;  // rows of bases with M <= 16
+constexpr int kTinyEw = 20;   // rows of bases with M <= 8
 
 template <int EW>
 __device__ __forceinline__ void load_entry(const float *ent, int ew, int e, float (&v)[EW]) {
@@ -255,14 +256,29 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
   const int M = d.M, ns = d.ns;
   GatherAcc<EXACT> a;
   if (valid) {
-    // two entries per lane per pass: both rows are requested before either
-    // is used, halving the exposed load latency on long lists
+    // two (four for M <= 8) entries per lane per pass: the rows are
+    // requested before any is used, cutting the exposed load latency on long
+    // lists; each lane still adds its entries in list order
     const int e1 = d.off[t + 1];
     int e = d.off[t] + gl;
     if constexpr (!EXACT) {
       if (M > kSmallM) {
         for (; e < e1; e += G) entry_terms_stream(d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
       } else if (d.ew <= kShortEw) {
+        if (d.ew <= kTinyEw) {
+          // four rows in flight per lane for the smallest bases
+          for (; e + 3 * G < e1; e += 4 * G) {
+            float v0[kTinyEw], v1[kTinyEw], v2[kTinyEw], v3[kTinyEw];
+            load_entry(d.ent, d.ew, e, v0);
+            load_entry(d.ent, d.ew, e + G, v1);
+            load_entry(d.ent, d.ew, e + 2 * G, v2);
+            load_entry(d.ent, d.ew, e + 3 * G, v3);
+            entry_terms<false>(v0, nullptr, xf, gt, M, d.d2, a);
+            entry_terms<false>(v1, nullptr, xf, gt, M, d.d2, a);
+            entry_terms<false>(v2, nullptr, xf, gt, M, d.d2, a);
+            entry_terms<false>(v3, nullptr, xf, gt, M, d.d2, a);
+          }
+        }
         for (; e + G < e1; e += 2 * G) {
           float v0[kShortEw], v1[kShortEw];
           load_entry(d.ent, d.ew, e, v0);
