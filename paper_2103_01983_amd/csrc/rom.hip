@@ -1318,7 +1318,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.ldc = (M + 1 + 3) / 4 * 4;
   {
     // run-kernel gather: groups of G lanes per target, chosen to minimise
-    // (rounds of 16 waves over the targets) x (entry passes of the longest list)
+    // (rounds of the workgroup's waves over the targets) x (entry passes of the
+    // longest list)
     int64_t maxlen = 0;
     for (int i = 0; i < s.ns; ++i) maxlen = std::max<int64_t>(maxlen, s.off[i + 1] - s.off[i]);
     d.maxlen = int(std::min<int64_t>(maxlen, int64_t(1) << 30));
