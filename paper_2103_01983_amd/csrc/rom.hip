@@ -600,40 +600,46 @@ __global__ void __launch_bounds__(kRunThreads)
       __syncthreads();
       // ---- in wave 0: the relative reduced gradient |G^T b| / |G_1^T b_1|,
       // then Gauss-Jordan inversion of N = G^T G (symmetric positive
-      // semi-definite) on the tableau [N | I] in LDS, lane j owning column j
-      // (a wave needs no barriers).  Each step loads the pivot column and
-      // the lane's own column in chunks of 8 rows (rows past M are padding),
-      // updates them and stores them back.  A non-positive pivot leaves its
-      // direction out (its row of the inverse is zero).
+      // semi-definite) on the tableau [N | I], lane j owning column j in
+      // registers (rows past M are zero padding and stay zero).  The pivot
+      // loop is unrolled, so every row index is static; each step reads the
+      // pivot column's entries from lane kk (lane_d) and updates the
+      // lane's own column.  A non-positive pivot leaves its direction out
+      // (its row of the inverse is zero).
       if (wave == 0) {
         const double gv = lane < M ? gvec[lane] : 0.0;
         const double gn = sqrt(wsumd(gv * gv));
         if (lane == 0) s_gn = gn;
-        for (int kk = 0; kk < M; ++kk) {
-          const double piv = T0[kk * 64 + kk];
-          double ip = 0.0;
-          if (piv > 0.0) {
-            // reciprocal: hardware estimate refined by two Newton steps
-            ip = __builtin_amdgcn_rcp(piv);
-            ip = fma(ip, fma(-piv, ip, 1.0), ip);
-            ip = fma(ip, fma(-piv, ip, 1.0), ip);
-          }
-          const double rk = T0[kk * 64 + lane] * ip;
+        double col[kSmallM];
 #pragma unroll
-          for (int i0 = 0; i0 < kSmallM; i0 += 8) {
-            if (i0 < M) {
-              double c[8], o[8];
+        for (int u = 0; u < kSmallM; ++u) col[u] = T0[u * 64 + lane];
 #pragma unroll
-              for (int u = 0; u < 8; ++u) c[u] = T0[(i0 + u) * 64 + kk];
+        for (int kk = 0; kk < kSmallM; ++kk) {
+          if (kk < M) {
+            const double piv = lane_d(col[kk], kk);
+            double ip = 0.0;
+            if (piv > 0.0) {
+              // reciprocal: hardware estimate refined by two Newton steps
+              ip = __builtin_amdgcn_rcp(piv);
+              ip = fma(ip, fma(-piv, ip, 1.0), ip);
+              ip = fma(ip, fma(-piv, ip, 1.0), ip);
+            }
+            const double rk = col[kk] * ip;
+            // rows in blocks of 8; blocks wholly past M are padding
 #pragma unroll
-              for (int u = 0; u < 8; ++u) o[u] = T0[(i0 + u) * 64 + lane];
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            for (int i0 = 0; i0 < kSmallM; i0 += 8) {
+              if (i0 < M) {
 #pragma unroll
-              for (int u = 0; u < 8; ++u) T0[(i0 + u) * 64 + lane] = i0 + u == kk ? rk : fma(-c[u], rk, o[u]);
+                for (int u = i0; u < i0 + 8; ++u) {
+                  const double c = lane_d(col[u], kk);
+                  col[u] = u == kk ? rk : fma(-c, rk, col[u]);
+                }
+              }
             }
           }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
+#pragma unroll
+        for (int u = 0; u < kSmallM; ++u) T0[u * 64 + lane] = col[u];
       }
       __syncthreads();
       // ---- x = N^+ g, then one refinement step: r' = b - G x, g' = G^T r',
