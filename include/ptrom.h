@@ -106,6 +106,13 @@ int ptrom_jvp(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, fl
 int ptrom_block_jacobian(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma,
                          float delta, float *B, ptrom_stream stream);
 
+/* Velocity f[2N] (as ptrom_velocity) and the self blocks B[4N] (as
+ * ptrom_block_jacobian) in one pass over the pairs: both need the same
+ * separation and reciprocal per pair, and the paper's inexact Newton needs
+ * both at every iterate (problem formulation, after eq. "linKstep"). */
+int ptrom_velocity_block_jacobian(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma,
+                                  float delta, float *f, float *B, ptrom_stream stream);
+
 /* Adjoint (vector-Jacobian product) for a cotangent w [2N]:
  *   gxy[2N]    = (df/dx)^T w,  (J^T w)_k = sum_{j != k} H(r_kj)^T (G_j w_k - G_k w_j)/(2pi)
  *   ggamma[N]  = d(w.f)/dGamma_k = (1/2pi) sum_{i != k} w_i . (-r_y, r_x)/s, r = x_i - x_k. */
@@ -387,7 +394,8 @@ enum {
   PTROM_OP_BLOCK_JACOBIAN = 1,
   PTROM_OP_JVP = 2,
   PTROM_OP_VJP = 3,
-  PTROM_OP_STREAM_FUNCTION = 4
+  PTROM_OP_STREAM_FUNCTION = 4,
+  PTROM_OP_VELOCITY_BLOCK_JACOBIAN = 5
 };
 
 /* The launch the context would use for operation op at n bodies, written to

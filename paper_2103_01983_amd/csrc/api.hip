@@ -119,6 +119,13 @@ extern "C" int ptrom_block_jacobian(ptrom_ctx *ctx, int64_t n, const float *xy, 
   return run_pair(ctx, OP_BJAC, n, xy, gamma, nullptr, delta, B, nullptr, (hipStream_t)stream);
 }
 
+extern "C" int ptrom_velocity_block_jacobian(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma,
+                                             float delta, float *f, float *B, ptrom_stream stream) {
+  if (int rc = check_common(ctx, n, delta)) return rc;
+  if (!xy || !gamma || !f || !B) return ctx->fail(PTROM_EINVAL, "NULL array");
+  return run_pair(ctx, OP_VBJ, n, xy, gamma, nullptr, delta, f, B, (hipStream_t)stream);
+}
+
 extern "C" int ptrom_vjp(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
                          const float *w, float *gxy, float *ggamma, ptrom_stream stream) {
   if (int rc = check_common(ctx, n, delta)) return rc;

@@ -69,8 +69,10 @@ __global__ void __launch_bounds__(64)
 
 // The paper's inexact Newton correction: per body, solve
 // (I - c B_i) d_i = -r_i with B_i = [B0 B1; B2 B3] (layout [4][n]) by
-// Cramer's rule in FP64, and add d_i to the increment D.
-__global__ void block_solve_kernel(int64_t n, float *__restrict__ D, const float *__restrict__ r,
+// Cramer's rule in FP64, add d_i to the increment D and form the next
+// iterate xi = x_prev + D.
+__global__ void block_solve_kernel(int64_t n, float *__restrict__ D, float *__restrict__ xi,
+                                   const float *__restrict__ xprev, const float *__restrict__ r,
                                    const float *__restrict__ B, float c) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -79,8 +81,23 @@ __global__ void block_solve_kernel(int64_t n, float *__restrict__ D, const float
   const double a10 = -cc * B[2 * n + i], a11 = 1.0 - cc * B[3 * n + i];
   const double det = a00 * a11 - a01 * a10;
   const double bx = -(double)r[i], by = -(double)r[n + i];
-  D[i] = (float)((double)D[i] + (bx * a11 - a01 * by) / det);
-  D[n + i] = (float)((double)D[n + i] + (a00 * by - a10 * bx) / det);
+  const float dx = (float)((double)D[i] + (bx * a11 - a01 * by) / det);
+  const float dy = (float)((double)D[n + i] + (a00 * by - a10 * bx) / det);
+  D[i] = dx;
+  D[n + i] = dy;
+  xi[i] = xprev[i] + dx;
+  xi[n + i] = xprev[n + i] + dy;
+}
+
+// Start of a step: x_prev = x, D = 0, xi = x.
+__global__ void step_start_kernel(int64_t m, float *__restrict__ xprev, float *__restrict__ D,
+                                  float *__restrict__ xi, const float *__restrict__ x) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const float v = x[q];
+  xprev[q] = v;
+  xi[q] = v;
+  D[q] = 0.0f;
 }
 
 // out[v] = X_v . y for short vectors: one workgroup per vector, the whole
@@ -165,6 +182,28 @@ __global__ void __launch_bounds__(kGSThreads)
   }
 }
 
+// The residual (as residual_kernel) and its squared norm for short vectors
+// (m <= kShortDot): one workgroup, the norm summed as dot_short_kernel sums.
+__global__ void __launch_bounds__(256)
+    residual_norm_kernel(int64_t m, float *__restrict__ r, const float *__restrict__ D, const float *__restrict__ f,
+                         const float *__restrict__ fp, float dtb0, float dtb1, const float *__restrict__ u, float dtu,
+                         double *__restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += 256) {
+    const float v = D[q] - (dtb0 * f[q] + dtb1 * fp[q] + (u ? dtu * u[q] : 0.0f));
+    r[q] = v;
+    s += (double)v * (double)v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // y -= sum_v c[v] X_v  (c on the device), or y = scale * y + sum_v c[v] X_v when accumulate.
 __global__ void multi_axpy_kernel(int64_t m, int nvec, const float *__restrict__ X, int64_t ldx,
                                   const double *__restrict__ c, float sign, float *__restrict__ y) {
@@ -238,6 +277,19 @@ struct Solver {
     if (int rc = fetch(dd, hp, 1)) return rc;
     *out = std::sqrt(hp[0]);
     return PTROM_OK;
+  }
+
+  // r = D - dt (b0 f + b1 fp) - dt (b0 + b1) u, and |r|
+  int residual(float *r, const float *D, const float *f, const float *fp, float dtb0, float dtb1, const float *u,
+               float dtu, double *out) {
+    if (m <= kShortDot) {
+      hipLaunchKernelGGL(residual_norm_kernel, dim3(1), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu, dd);
+      if (int rc = fetch(dd, hp, 1)) return rc;
+      *out = std::sqrt(hp[0]);
+      return PTROM_OK;
+    }
+    hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu);
+    return norm(r, out);
   }
 
   // Solve (I - c J) d = b from d = 0 to relative tolerance rtol; returns
@@ -351,10 +403,10 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   const float b0 = scheme == PTROM_BACKWARD_EULER ? 1.0f : 0.5f;
   const float b1 = scheme == PTROM_BACKWARD_EULER ? 0.0f : 0.5f;
   const PairCfg vcfg = ctx->tune.get(OP_VEL, n), jcfg = ctx->tune.get(OP_JVP, n);
-  const PairCfg bcfg = ctx->tune.get(OP_BJAC, n);
+  const PairCfg bcfg = ctx->tune.get(OP_VBJ, n);
   const size_t pwsf = std::max({pair_ws_floats(OP_VEL, vcfg, ctx->num_cus, n),
                                 pair_ws_floats(OP_JVP, jcfg, ctx->num_cus, n),
-                                block ? pair_ws_floats(OP_BJAC, bcfg, ctx->num_cus, n) : size_t(0)});
+                                block ? pair_ws_floats(OP_VBJ, bcfg, ctx->num_cus, n) : size_t(0)});
   const int R = o.gmres_restart;
   const size_t vb = align256(m * sizeof(float));
   const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (3 * R + 4)) +
@@ -375,24 +427,28 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   hipStream_t st = (hipStream_t)stream;
   Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hp, dpart, R};
 
+  // velocity at x (and, for the block model, the self blocks in the same pass)
+  auto rhs = [&](const float *x, float *fo, bool blocks) -> int {
+    const hipError_t e = blocks ? launch_pair(OP_VBJ, bcfg, ctx->num_cus, n, x, gamma, nullptr, delta, fo, Bj,
+                                              pws, pwsf, st)
+                                : launch_pair(OP_VEL, vcfg, ctx->num_cus, n, x, gamma, nullptr, delta, fo, nullptr,
+                                              pws, pwsf, st);
+    return e == hipSuccess ? PTROM_OK : ctx->hip_fail(e, blocks ? "velocity and block jacobian" : "velocity");
+  };
   for (int step = 0; step < nsteps; ++step) {
-    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(xprev, xy, m * sizeof(float), hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, D, xprev, 0.0f);
-    hipError_t e = launch_pair(OP_VEL, vcfg, ctx->num_cus, n, xprev, gamma, nullptr, delta, fp, nullptr, pws, pwsf, st);
-    if (e != hipSuccess) return ctx->hip_fail(e, "velocity");
+    hipLaunchKernelGGL(step_start_kernel, g1(m), dim3(256), 0, st, m, xprev, D, xi, xy);
+    // blocks at the first iterate x_prev: every step, or every jac_period-th
+    const bool refresh = block && (o.jac_period == 0 || step % o.jac_period == 0);
+    if (int rc = rhs(xprev, fp, refresh)) return rc;
     double r0 = -1.0, rn = 0.0;
     int it = 0;
     for (;; ++it) {
-      hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xi, xprev, D);
-      if (it == 0) {
-        hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, f, fp, 1.0f);
-      } else {
-        e = launch_pair(OP_VEL, vcfg, ctx->num_cus, n, xi, gamma, nullptr, delta, f, nullptr, pws, pwsf, st);
-        if (e != hipSuccess) return ctx->hip_fail(e, "velocity");
+      if (it > 0) {
+        // xi = x_prev + D (the block solve forms it itself)
+        if (!block) hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xi, xprev, D);
+        if (int rc = rhs(xi, f, block && o.jac_period == 0)) return rc;
       }
-      hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dt * b0, dt * b1, uinf,
-                         dt * (b0 + b1));
-      if (int rc = S.norm(r, &rn)) return rc;
+      if (int rc = S.residual(r, D, it == 0 ? fp : f, fp, dt * b0, dt * b1, uinf, dt * (b0 + b1), &rn)) return rc;
       if (r0 < 0.0) r0 = rn;
       if (rn <= o.newton_tol * r0 || r0 == 0.0) break;
       if (it >= o.max_newton) {
@@ -400,12 +456,7 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
         break;
       }
       if (block) {
-        // blocks at xi = x_prev + D: every iterate, or the first iterate of every jac_period-th step
-        if (o.jac_period == 0 || (it == 0 && step % o.jac_period == 0)) {
-          e = launch_pair(OP_BJAC, bcfg, ctx->num_cus, n, xi, gamma, nullptr, delta, Bj, nullptr, pws, pwsf, st);
-          if (e != hipSuccess) return ctx->hip_fail(e, "block jacobian");
-        }
-        hipLaunchKernelGGL(block_solve_kernel, g1(n), dim3(256), 0, st, n, D, r, Bj, dt * b0);
+        hipLaunchKernelGGL(block_solve_kernel, g1(n), dim3(256), 0, st, n, D, xi, xprev, r, Bj, dt * b0);
         continue;
       }
       hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, r, r, -1.0f);

@@ -18,10 +18,10 @@ constexpr int kBlock = 256;   // threads per workgroup of the pair kernels (4 wa
 constexpr int kTile = 256;    // sources staged per LDS tile
 constexpr int64_t kMaxN = int64_t(1) << 30;
 
-enum PairOp { OP_VEL = 0, OP_BJAC = 1, OP_JVP = 2, OP_VJP = 3, OP_PSI = 4, OP_COUNT = 5 };
+enum PairOp { OP_VEL = 0, OP_BJAC = 1, OP_JVP = 2, OP_VJP = 3, OP_PSI = 4, OP_VBJ = 5, OP_COUNT = 6 };
 
 // operations with an each-unordered-pair-once variant
-inline bool has_sym(int op) { return op == OP_VEL || op == OP_JVP || op == OP_VJP || op == OP_BJAC; }
+inline bool has_sym(int op) { return op != OP_PSI; }
 
 // Source staging of the pair kernels.
 //  LDS:    the workgroup stages a tile of sources in LDS; every lane reads it

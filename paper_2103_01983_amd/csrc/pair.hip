@@ -88,6 +88,7 @@ int nacc(int op) {
     case OP_BJAC: return Traits<OP_BJAC>::NACC;
     case OP_JVP: return Traits<OP_JVP>::NACC;
     case OP_PSI: return Traits<OP_PSI>::NACC;
+    case OP_VBJ: return Traits<OP_VBJ>::NACC;
     default: return Traits<OP_VJP>::NACC;
   }
 }
@@ -303,6 +304,7 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, con
     case OP_BJAC: e = dispatch<OP_BJAC>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
     case OP_JVP: e = dispatch<OP_JVP>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
     case OP_PSI: e = dispatch<OP_PSI>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
+    case OP_VBJ: e = dispatch<OP_VBJ>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
     default: e = dispatch<OP_VJP>(cfg, grid, stream, n, xy, gamma, aux, d2, int(chunk), partial, o1, out2); break;
   }
   if (e != hipSuccess || !partial) return e;
@@ -312,6 +314,7 @@ hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, con
     case OP_BJAC: hipLaunchKernelGGL(reduce_kernel<OP_BJAC>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
     case OP_JVP: hipLaunchKernelGGL(reduce_kernel<OP_JVP>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
     case OP_PSI: hipLaunchKernelGGL(reduce_kernel<OP_PSI>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
+    case OP_VBJ: hipLaunchKernelGGL(reduce_kernel<OP_VBJ>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
     default: hipLaunchKernelGGL(reduce_kernel<OP_VJP>, rg, dim3(256), 0, stream, n, s, ws, out, out2); break;
   }
   return hipGetLastError();

@@ -14,6 +14,8 @@ template <> struct Traits<OP_BJAC> { static constexpr int NSRC = 3, NTGT = 2, NA
 template <> struct Traits<OP_JVP> { static constexpr int NSRC = 5, NTGT = 4, NACC = 2; };
 template <> struct Traits<OP_VJP> { static constexpr int NSRC = 5, NTGT = 5, NACC = 3; };
 template <> struct Traits<OP_PSI> { static constexpr int NSRC = 3, NTGT = 2, NACC = 1; };
+// velocity and the self block in one pass: fx, fy, then the block's B00, B01, B10
+template <> struct Traits<OP_VBJ> { static constexpr int NSRC = 3, NTGT = 2, NACC = 5; };
 
 // -ln(2)/(4 pi): the stream-function sum is accumulated with log2
 constexpr float kPsiScale = -0.0551589363396979447f;
@@ -54,6 +56,16 @@ __device__ __forceinline__ void interact(const float *t, const float *s, float d
     acc[0] = fmaf(g2, a2, acc[0]);
     acc[1] = fmaf(g2, dd - d2, acc[1]);
     acc[2] = fmaf(g2, dd + d2, acc[2]);
+  } else if constexpr (OP == OP_VBJ) {
+    const float g = s[2] * r;
+    acc[0] = fmaf(-dy, g, acc[0]);
+    acc[1] = fmaf(dx, g, acc[1]);
+    const float g2 = g * r;
+    const float a2 = (dx + dx) * dy;
+    const float dd = fmaf(dy, dy, -dx * dx);
+    acc[2] = fmaf(g2, a2, acc[2]);
+    acc[3] = fmaf(g2, dd - d2, acc[3]);
+    acc[4] = fmaf(g2, dd + d2, acc[4]);
   } else if constexpr (OP == OP_JVP) {
     // du/dr = R (I - 2 r r^T / q) / q with R the rotation by +90 degrees, so
     // H e = R (e - c r) / q,  c = 2 (r . e) / q,  e = v_i - v_j.
@@ -106,6 +118,13 @@ __device__ __forceinline__ void store_final(int n, int i, const float *v, float 
     out[3 * n + i] = -v[0] * kInv2Pi;
   } else if constexpr (OP == OP_PSI) {
     out[i] = v[0] * kPsiScale;
+  } else if constexpr (OP == OP_VBJ) {
+    out[i] = v[0] * kInv2Pi;
+    out[n + i] = v[1] * kInv2Pi;
+    out2[i] = v[2] * kInv2Pi;
+    out2[n + i] = v[3] * kInv2Pi;
+    out2[2 * n + i] = v[4] * kInv2Pi;
+    out2[3 * n + i] = -v[2] * kInv2Pi;
   } else {
     out[i] = v[0] * kInv2Pi;
     out[n + i] = v[1] * kInv2Pi;

@@ -142,7 +142,7 @@ hipError_t launch_sym_op(int k, int n, const float *xy, const float *gam, const 
 size_t pair_sym_ws_floats(int op, int k, int64_t n) {
   const int64_t tb = kBlock * int64_t(k);
   const int64_t nb = (n + tb - 1) / tb;
-  const int na = (op == OP_VJP || op == OP_BJAC) ? 3 : 2;
+  const int na = op == OP_VBJ ? Traits<OP_VBJ>::NACC : (op == OP_VJP || op == OP_BJAC) ? 3 : 2;
   return size_t(2 * nb * na * n + 64);
 }
 
@@ -158,6 +158,7 @@ hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64
     case OP_JVP: return launch_sym_op<OP_JVP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     case OP_VJP: return launch_sym_op<OP_VJP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     case OP_BJAC: return launch_sym_op<OP_BJAC>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
+    case OP_VBJ: return launch_sym_op<OP_VBJ>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     default: return hipErrorInvalidValue;
   }
 }

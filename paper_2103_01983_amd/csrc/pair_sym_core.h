@@ -59,6 +59,23 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
     react[0] = fmaf(gi, h0, react[0]);
     react[1] = fmaf(gi, h1, react[1]);
     react[2] = fmaf(gi, h2, react[2]);
+  } else if constexpr (OP == OP_VBJ) {
+    // velocity (antisymmetric reaction) and self block (symmetric reaction)
+    const float gj = s[2] * r, gi = t[4] * r;
+    acc[0] = fmaf(-dy, gj, acc[0]);
+    acc[1] = fmaf(dx, gj, acc[1]);
+    react[0] = fmaf(dy, gi, react[0]);
+    react[1] = fmaf(-dx, gi, react[1]);
+    const float h0 = (dx + dx) * dy;
+    const float m = fmaf(dy, dy, -dx * dx);
+    const float h1 = m - d2, h2 = m + d2;
+    const float gj2 = gj * r, gi2 = gi * r;
+    acc[2] = fmaf(gj2, h0, acc[2]);
+    acc[3] = fmaf(gj2, h1, acc[3]);
+    acc[4] = fmaf(gj2, h2, acc[4]);
+    react[2] = fmaf(gi2, h0, react[2]);
+    react[3] = fmaf(gi2, h1, react[3]);
+    react[4] = fmaf(gi2, h2, react[4]);
   } else {
     const float qx = fmaf(s[2], t[2], -t[4] * s[3]);
     const float qy = fmaf(s[2], t[3], -t[4] * s[4]);

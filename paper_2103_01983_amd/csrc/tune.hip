@@ -13,7 +13,8 @@
 
 using namespace ptrom;
 
-static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp", "stream_function"};
+static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp", "stream_function",
+                                         "velocity_block_jacobian"};
 
 extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
   if (!ctx || !path) return PTROM_EINVAL;
@@ -67,8 +68,8 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
   float *d = nullptr, *o = nullptr, *o2 = nullptr, *wsb = nullptr;
   PTROM_CHECK_HIP(ctx, hipMalloc(&d, 5 * nmax * sizeof(float)));
   hipError_t e = hipMalloc(&o, 4 * nmax * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&o2, nmax * sizeof(float));
-  const size_t wsf = std::max(size_t(64) * 3 * nmax, pair_sym_ws_floats(OP_VJP, 2, nmax));  // split / pair-block partials
+  if (e == hipSuccess) e = hipMalloc(&o2, 4 * nmax * sizeof(float));
+  const size_t wsf = std::max(size_t(64) * 5 * nmax, pair_sym_ws_floats(OP_VBJ, 2, nmax));  // split / pair-block partials
   if (e == hipSuccess) e = hipMalloc(&wsb, wsf * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(d, h.data(), 5 * nmax * sizeof(float), hipMemcpyHostToDevice);
   hipEvent_t a = nullptr, b = nullptr;

@@ -60,6 +60,7 @@ SIGNATURES = {
     "ptrom_velocity_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f64, _vp, _vp]),
     "ptrom_jvp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp]),
     "ptrom_block_jacobian": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
+    "ptrom_velocity_block_jacobian": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp]),
     "ptrom_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp, _vp]),
     "ptrom_stream_function": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
     "ptrom_velocity_points": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _f32, _vp, _vp]),
@@ -231,6 +232,20 @@ def block_jacobian(xy, gamma, delta, out=None, ctx=None):
                                          _ptr(out, torch.float32, 4 * n, "out"), _stream(xy)),
            "ptrom_block_jacobian")
     return out
+
+
+def velocity_block_jacobian(xy, gamma, delta, f=None, B=None, ctx=None):
+    """Velocity [2N] and self blocks [4N] in one pass; returns (f, B)."""
+    n = _n(xy)
+    f = torch.empty(2 * n, dtype=torch.float32, device=xy.device) if f is None else f
+    B = torch.empty(4 * n, dtype=torch.float32, device=xy.device) if B is None else B
+    c = context(xy.device) if ctx is None else ctx
+    _check(c, lib().ptrom_velocity_block_jacobian(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
+                                                  _ptr(gamma, torch.float32, n, "gamma"), float(delta),
+                                                  _ptr(f, torch.float32, 2 * n, "f"),
+                                                  _ptr(B, torch.float32, 4 * n, "B"), _stream(xy)),
+           "ptrom_velocity_block_jacobian")
+    return f, B
 
 
 def vjp(xy, gamma, delta, w, gxy=None, ggamma=None, ctx=None):
@@ -575,7 +590,8 @@ def load_tuning(cache_path, device=None):
     _check(c, lib().ptrom_load_tuning(c, cache_path.encode()), "ptrom_load_tuning")
 
 
-PAIR_OPS = {"velocity": 0, "block_jacobian": 1, "jvp": 2, "vjp": 3, "stream_function": 4}
+PAIR_OPS = {"velocity": 0, "block_jacobian": 1, "jvp": 2, "vjp": 3, "stream_function": 4,
+            "velocity_block_jacobian": 5}
 
 
 def pair_config(op, n, device=None, ctx=None):

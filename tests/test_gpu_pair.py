@@ -80,6 +80,23 @@ def test_block_jacobian_parity(dev, n):
     assert rel(B, oracle.block_jacobian(xy, g, float(d))) <= TOL
 
 
+@pytest.mark.parametrize("n", [2, 257, 4099, 40000])
+@pytest.mark.parametrize("delta", [0.0, 0.01])
+def test_velocity_block_jacobian_parity(dev, n, delta):
+    # the fused pass against both oracle definitions (40000 bodies take the
+    # each-pair-once launch under the tuning table)
+    xy, g, d = cloud(n, 450 + n, "gauss", delta)
+    f, B = native.velocity_block_jacobian(to_dev(xy, dev), to_dev(g, dev), d)
+    if n <= 4099:
+        assert rel(f.cpu().numpy(), oracle.velocity(xy, g, float(d))) <= TOL
+        assert rel(B.cpu().numpy(), oracle.block_jacobian(xy, g, float(d))) <= TOL
+    else:
+        idx = np.random.default_rng(n).choice(n, 96, replace=False)
+        fs, Bs = f.cpu().numpy(), B.cpu().numpy().reshape(4, n)
+        assert rel(np.concatenate([fs[idx], fs[n + idx]]), oracle.velocity_at(xy, g, float(d), idx)) <= TOL
+        assert rel(Bs[:, idx].ravel(), oracle.block_jacobian_at(xy, g, float(d), idx)) <= TOL
+
+
 def test_velocity_f64_parity(dev):
     xy, g, _ = cloud(777, 5, "disk", 0.02)
     f = native.velocity_f64(to_dev(xy, dev, torch.float64), to_dev(g, dev, torch.float64), 0.02).cpu().numpy()

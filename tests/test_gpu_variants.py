@@ -25,7 +25,7 @@ def vctx(request, dev):
     st, k, w, sym = request.param
     fd, path = tempfile.mkstemp(suffix=".txt")
     with os.fdopen(fd, "w") as fh:
-        for op in ("velocity", "jvp", "vjp", "block_jacobian"):
+        for op in ("velocity", "jvp", "vjp", "block_jacobian", "velocity_block_jacobian"):
             fh.write("%s 16 %d %d %d %d\n" % (op, st, k, w, sym))
     h = native.make_context(0, path)
     os.unlink(path)
@@ -61,7 +61,11 @@ def test_variant_parity(dev, vctx, n, delta):
     assert rel(gx.cpu().numpy(), ox) <= 1e-5
     assert rel(gg.cpu().numpy(), og) <= 1e-5
     B = native.block_jacobian(xd, gd, d, ctx=vctx).cpu().numpy()
-    assert rel(B, oracle.block_jacobian(xy, g, d)) <= 1e-5
+    ob = oracle.block_jacobian(xy, g, d)
+    assert rel(B, ob) <= 1e-5
+    f2, B2 = native.velocity_block_jacobian(xd, gd, d, ctx=vctx)
+    assert rel(f2.cpu().numpy(), oracle.velocity(xy, g, d)) <= 1e-5
+    assert rel(B2.cpu().numpy(), ob) <= 1e-5
 
 
 def test_variant_deterministic(dev, vctx):
@@ -92,4 +96,8 @@ def test_variant_full_size_sampled(dev, vctx):
     assert rel(gx.cpu().numpy()[sel], ox) <= 1e-5
     assert rel(gg.cpu().numpy()[idx], og) <= 1e-5
     B = native.block_jacobian(xd, gd, d, ctx=vctx).cpu().numpy().reshape(4, n)
-    assert rel(B[:, idx].ravel(), oracle.block_jacobian_at(xy, g, d, idx)) <= 1e-5
+    ob = oracle.block_jacobian_at(xy, g, d, idx)
+    assert rel(B[:, idx].ravel(), ob) <= 1e-5
+    f2, B2 = native.velocity_block_jacobian(xd, gd, d, ctx=vctx)
+    assert rel(f2.cpu().numpy()[sel], oracle.velocity_at(xy, g, d, idx)) <= 1e-5
+    assert rel(B2.cpu().numpy().reshape(4, n)[:, idx].ravel(), ob) <= 1e-5
