@@ -53,7 +53,10 @@ struct RomDev {
   float d2, dt;
   double tol, alpha;
   const float *Phibar, *xbar0;  // [nd][M], [nd]
-  const float *ent;             // [nnz][ew]: r0x r0y Gamma~ surrogate-id (Dx_m Dy_m) pairs
+  const float *ent;             // entry rows r0x r0y Gamma~ surrogate-id, then (Dx_m Dy_m)
+                                // pairs; paper Jacobian: chunk-major, float4 chunk c of
+                                // entry e at ((float4 *)ent)[c * nnz + e]; exact
+                                // Jacobian: row-major, ent[e * ew ..]
   const int *off;               // [ns+1]
   // point form used by the larger-basis kernel: P = nd + 2 Nc coordinates
   // (the sampled rows, then x and y of every surrogate), basis rows stored
@@ -132,19 +135,23 @@ __device__ __forceinline__ void sampled_position(const float *Phibar, const floa
 }
 
 // One entry row in registers: r0x r0y Gamma~ pad, then (Dx_m, Dy_m) pairs,
-// padded to whole float4 chunks.
+// padded to whole float4 chunks.  With the paper's Jacobian the table stores
+// the rows chunk-major (CM), so lanes reading consecutive entries read one
+// contiguous span per chunk; the exact Jacobian re-reads D from its row while
+// it accumulates, and keeps the rows whole (row-major), where one address
+// serves every chunk.
 constexpr int kMaxEw = 4 + 2 * kSmallM;
 
 constexpr int kShortEw = 36;  // rows of bases with M <= 16
 constexpr int kTinyEw = 20;   // rows of bases with M <= 8
 
-template <int EW>
-__device__ __forceinline__ void load_entry(const float *ent, int ew, int e, float (&v)[EW]) {
-  const float4 *p = reinterpret_cast<const float4 *>(ent + (size_t)e * ew);
+template <bool CM, int EW>
+__device__ __forceinline__ void load_entry(const float *ent, int ew, int64_t nnz, int e, float (&v)[EW]) {
+  const float4 *p = reinterpret_cast<const float4 *>(CM ? ent : ent + (size_t)e * ew) + (CM ? e : 0);
 #pragma unroll
   for (int c = 0; c < EW / 4; ++c) {
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c * 4 < ew) q = p[c];
+    if (c * 4 < ew) q = p[CM ? (size_t)c * nnz : (size_t)c];
     v[4 * c] = q.x;
     v[4 * c + 1] = q.y;
     v[4 * c + 2] = q.z;
@@ -161,8 +168,8 @@ struct GatherAcc {
 // Velocity and Jacobian terms of one (target, surrogate) entry at xhat:
 // r = r0 + D xhat; the 2x2 block (or, exact mode, its product with D).
 template <bool EXACT, int EW>
-__device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *row, const float *xf, const float *gt,
-                                            int M, float d2, GatherAcc<EXACT> &a) {
+__device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *ent, int ew, int e, const float *xf,
+                                            const float *gt, int M, float d2, GatherAcc<EXACT> &a) {
   float rx = v[0], ry = v[1];
 #pragma unroll
   for (int m = 0; m < (EW - 4) / 2; ++m)
@@ -184,6 +191,7 @@ __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *r
   if constexpr (EXACT) {
     // D re-read from the row (cache hit) so the register copy is not kept live
     const float h00 = g2 * a2, h01 = g2 * (dd - d2), h10 = g2 * (dd + d2);
+    const float *row = ent + (size_t)e * ew;
 #pragma unroll
     for (int m = 0; m < kSmallM; ++m)
       if (m < M) {
@@ -201,15 +209,15 @@ __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *r
 // The same terms for an entry row read straight from memory in float4 chunks
 // (bases with M > 32, paper Jacobian): r = r0 + D xhat, then the velocity and
 // the 2x2 block.
-__device__ __forceinline__ void entry_terms_stream(const float *row, const float *xf, const float *gt, int M, float d2,
-                                                   GatherAcc<false> &a) {
-  const float4 head = *reinterpret_cast<const float4 *>(row);
+__device__ __forceinline__ void entry_terms_stream(const float *ent, int64_t nnz, int e, const float *xf, const float *gt,
+                                                   int M, float d2, GatherAcc<false> &a) {
+  const float4 *row = reinterpret_cast<const float4 *>(ent) + e;
+  const float4 head = row[0];
   float rx = head.x, ry = head.y;
-  const float4 *p = reinterpret_cast<const float4 *>(row + 4);
   const int nq = (2 * M + 3) / 4;  // chunks of two modes
 #pragma unroll 4
   for (int c = 0; c < nq; ++c) {
-    const float4 q = p[c];
+    const float4 q = row[(size_t)(1 + c) * nnz];
     const int m = 2 * c;
     rx = fmaf(q.x, xf[m], rx);
     ry = fmaf(q.y, xf[m], ry);
@@ -263,35 +271,35 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
     int e = d.off[t] + gl;
     if constexpr (!EXACT) {
       if (M > kSmallM) {
-        for (; e < e1; e += G) entry_terms_stream(d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
+        for (; e < e1; e += G) entry_terms_stream(d.ent, d.nnz, e, xf, gt, M, d.d2, a);
       } else if (d.ew <= kShortEw) {
         if (d.ew <= kTinyEw) {
           // four rows in flight per lane for the smallest bases
           for (; e + 3 * G < e1; e += 4 * G) {
             float v0[kTinyEw], v1[kTinyEw], v2[kTinyEw], v3[kTinyEw];
-            load_entry(d.ent, d.ew, e, v0);
-            load_entry(d.ent, d.ew, e + G, v1);
-            load_entry(d.ent, d.ew, e + 2 * G, v2);
-            load_entry(d.ent, d.ew, e + 3 * G, v3);
-            entry_terms<false>(v0, nullptr, xf, gt, M, d.d2, a);
-            entry_terms<false>(v1, nullptr, xf, gt, M, d.d2, a);
-            entry_terms<false>(v2, nullptr, xf, gt, M, d.d2, a);
-            entry_terms<false>(v3, nullptr, xf, gt, M, d.d2, a);
+            load_entry<true>(d.ent, d.ew, d.nnz, e, v0);
+            load_entry<true>(d.ent, d.ew, d.nnz, e + G, v1);
+            load_entry<true>(d.ent, d.ew, d.nnz, e + 2 * G, v2);
+            load_entry<true>(d.ent, d.ew, d.nnz, e + 3 * G, v3);
+            entry_terms<false>(v0, nullptr, 0, 0, xf, gt, M, d.d2, a);
+            entry_terms<false>(v1, nullptr, 0, 0, xf, gt, M, d.d2, a);
+            entry_terms<false>(v2, nullptr, 0, 0, xf, gt, M, d.d2, a);
+            entry_terms<false>(v3, nullptr, 0, 0, xf, gt, M, d.d2, a);
           }
         }
         for (; e + G < e1; e += 2 * G) {
           float v0[kShortEw], v1[kShortEw];
-          load_entry(d.ent, d.ew, e, v0);
-          load_entry(d.ent, d.ew, e + G, v1);
-          entry_terms<false>(v0, nullptr, xf, gt, M, d.d2, a);
-          entry_terms<false>(v1, nullptr, xf, gt, M, d.d2, a);
+          load_entry<true>(d.ent, d.ew, d.nnz, e, v0);
+          load_entry<true>(d.ent, d.ew, d.nnz, e + G, v1);
+          entry_terms<false>(v0, nullptr, 0, 0, xf, gt, M, d.d2, a);
+          entry_terms<false>(v1, nullptr, 0, 0, xf, gt, M, d.d2, a);
         }
       }
     }
     for (; e < e1; e += G) {
       float v[kMaxEw];
-      load_entry(d.ent, d.ew, e, v);
-      entry_terms<EXACT>(v, d.ent + (size_t)e * d.ew, xf, gt, M, d.d2, a);
+      load_entry<!EXACT>(d.ent, d.ew, d.nnz, e, v);
+      entry_terms<EXACT>(v, d.ent, d.ew, e, xf, gt, M, d.d2, a);
     }
   }
   const double Fx = gsum(a.fx, G) * kInv2PiD + (valid ? d.ubar[t] : 0.0);
@@ -487,9 +495,9 @@ __global__ void __launch_bounds__(kRunThreads)
         // sampled rows at the current xhat are formed alongside.
         for (int e = tid; e < nnz; e += kRunThreads) {
           float v[kMaxEw];
-          load_entry(d.ent, d.ew, e, v);
+          load_entry<true>(d.ent, d.ew, d.nnz, e, v);
           GatherAcc<false> a;
-          entry_terms<false>(v, nullptr, xf, gt, M, d.d2, a);
+          entry_terms<false>(v, nullptr, 0, 0, xf, gt, M, d.d2, a);
           ct[e] = a.fx;
           ct[nnz + e] = a.fy;
           ct[2 * nnz + e] = a.ba;
@@ -1243,20 +1251,26 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   for (size_t q = 0; q < phibar.size(); ++q) phibar[q] = float(s.Phibar[q]);
   for (int q = 0; q < nd; ++q) xbar0[q] = float(s.xbar0[q]);
   for (int i = 0; i <= s.ns; ++i) off32[i] = int(s.off[i]);
-  // entry rows: r0 = xbar0_i - xqt0_c, Gamma~_c, D = Phibar_i - Phit_c (differences in FP64)
-  std::vector<float> ent(size_t(s.nnz > 0 ? s.nnz : 1) * ew, 0.0f);
+  // entry rows: r0 = xbar0_i - xqt0_c, Gamma~_c, D = Phibar_i - Phit_c
+  // (differences in FP64); component k of entry e at ((k / 4) nnz + e) 4 +
+  // k % 4 (chunk-major, paper Jacobian) or e ew + k (row-major, exact)
+  const size_t ne = size_t(s.nnz > 0 ? s.nnz : 1);
+  const bool cm = s.jac_mode != PTROM_JAC_EXACT;
+  std::vector<float> ent(ne * ew, 0.0f);
+  auto at = [&](int64_t e, int k) -> float & {
+    return cm ? ent[(size_t(k / 4) * ne + size_t(e)) * 4 + size_t(k % 4)] : ent[size_t(e) * ew + size_t(k)];
+  };
   for (int i = 0; i < s.ns; ++i)
     for (int64_t e = s.off[i]; e < s.off[i + 1]; ++e) {
       const int64_t c = s.ids[e];
-      float *E = ent.data() + (size_t)e * ew;
-      E[0] = float(s.xbar0[i] - s.xqt0[2 * c]);
-      E[1] = float(s.xbar0[s.ns + i] - s.xqt0[2 * c + 1]);
-      E[2] = float(s.Gt[c]);
+      at(e, 0) = float(s.xbar0[i] - s.xqt0[2 * c]);
+      at(e, 1) = float(s.xbar0[s.ns + i] - s.xqt0[2 * c + 1]);
+      at(e, 2) = float(s.Gt[c]);
       const int32_t cid = int32_t(c);
-      std::memcpy(&E[3], &cid, sizeof(cid));
+      std::memcpy(&at(e, 3), &cid, sizeof(cid));
       for (int m = 0; m < M; ++m) {
-        E[4 + 2 * m] = float(s.Phibar[(size_t)i * M + m] - s.Phit[(size_t)(2 * c) * M + m]);
-        E[5 + 2 * m] = float(s.Phibar[(size_t)(s.ns + i) * M + m] - s.Phit[(size_t)(2 * c + 1) * M + m]);
+        at(e, 4 + 2 * m) = float(s.Phibar[(size_t)i * M + m] - s.Phit[(size_t)(2 * c) * M + m]);
+        at(e, 5 + 2 * m) = float(s.Phibar[(size_t)(s.ns + i) * M + m] - s.Phit[(size_t)(2 * c + 1) * M + m]);
       }
     }
 
