@@ -7,7 +7,10 @@
 // HBM (FP32); dot products accumulate in FP64 on the device; the small
 // Hessenberg least-squares problem is solved on the host in FP64.  With
 // the paper's inexact Jacobian the Newton systems are instead the per-body
-// 2x2 blocks (I - dt beta0 B_i) d_i = -r_i of the block-Jacobian kernel.
+// 2x2 blocks (I - dt beta0 B_i) d_i = -r_i, the blocks coming from the same
+// pair pass as the velocity (fused velocity + block-Jacobian operation).
+// For vectors of up to 16384 entries the residual and its norm are one
+// kernel, so each Newton iteration waits for one host round trip.
 #include <algorithm>
 #include <cmath>
 #include <vector>
