@@ -67,3 +67,16 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_binding_argument_counts_match_the_header():
+    # every declared function: the number of C parameters equals the number
+    # of ctypes argument types the binding passes
+    src = open(os.path.join(ROOT, "include", "ptrom.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    decls = dict(re.findall(r"\b(ptrom_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S))
+    assert set(decls) == set(native.SIGNATURES)
+    for name, params in decls.items():
+        params = " ".join(params.split())
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        assert n == len(native.SIGNATURES[name][1]), (name, n, len(native.SIGNATURES[name][1]))
