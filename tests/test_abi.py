@@ -80,3 +80,28 @@ def test_binding_argument_counts_match_the_header():
         params = " ".join(params.split())
         n = 0 if params in ("", "void") else params.count(",") + 1
         assert n == len(native.SIGNATURES[name][1]), (name, n, len(native.SIGNATURES[name][1]))
+
+
+def test_binding_argument_types_match_the_header():
+    # scalar parameters by width and kind, pointers as pointers
+    src = open(os.path.join(ROOT, "include", "ptrom.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    decls = dict(re.findall(r"\b(ptrom_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S))
+    scalar = {"float": ctypes.c_float, "double": ctypes.c_double, "int": ctypes.c_int, "int32_t": ctypes.c_int32,
+              "int64_t": ctypes.c_int64, "size_t": ctypes.c_size_t}
+    for name, params in decls.items():
+        params = " ".join(params.split())
+        if params in ("", "void"):
+            continue
+        for k, p in enumerate(params.split(",")):
+            words = p.replace("*", " * ").split()
+            ct = native.SIGNATURES[name][1][k]
+            if "*" in words or words[0] == "ptrom_stream":
+                assert ct in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(ct, "_type_") and issubclass(
+                    ct, ctypes._Pointer), (name, p, ct)
+            else:
+                base = [w for w in words[:-1] if w != "const"]
+                assert len(base) == 1 and base[0] in scalar, (name, p)
+                want = scalar[base[0]]
+                assert ctypes.sizeof(ct) == ctypes.sizeof(want) and (ct in (ctypes.c_float, ctypes.c_double)) == (
+                    want in (ctypes.c_float, ctypes.c_double)), (name, p, ct)
