@@ -1,7 +1,8 @@
 // All-pairs kernels of the regularized 2D Biot-Savart sum (kernel equation
 // of the problem formulation) and its derivatives: velocity, per-body 2x2
-// self blocks (the paper's inexact Jacobian), Jacobian-vector product and
-// vector-Jacobian product with the circulation gradient.
+// self blocks (the paper's inexact Jacobian), both in one pass, the
+// Jacobian-vector product, the vector-Jacobian product with the circulation
+// gradient, and the stream function of the Hamiltonian.
 //
 // Work decomposition: a workgroup of 4 wave64 owns 256*K consecutive targets
 // (K per lane, kept in VGPRs) and one contiguous chunk of sources (grid.y
