@@ -126,3 +126,39 @@ def test_members_match_oracle(criterion, theta):
     g = np.random.default_rng(2).standard_normal(cl.n)
     art = dict(mem_off=r["mem_off"], mem_ids=r["mem_ids"])
     np.testing.assert_allclose(po.reassign_host(art, g), oo.reassign_circulation(mem, g), rtol=0, atol=1e-12)
+
+
+def test_barnes_hut_distance_is_measured_from_the_weighted_mean():
+    # checkPrune, Barnes-Hut branch: a cell is pruned when w / |s - s_i| <= theta,
+    # s the cell's (|Gamma|-weighted) mean point.  Hand-built tree over five
+    # points: root [0, 8]^2, level-1 cells of width 4.
+    #   body 0 (target) (0, 0); bodies 1, 2 in cell [4, 8] x [0, 4):
+    #   (4.2, 0.2) with Gamma 0.01 and (7.8, 0.2) with Gamma 1; bodies 3, 4
+    #   alone in their cells at (0, 8) and (8, 8).
+    # Cell of bodies 1, 2 at theta = 0.6:
+    #   weighted mean (7.8427 / 1.01, 0.2) = (7.7644, 0.2), distance 7.7669,
+    #   4 / 7.7669 = 0.515 <= 0.6 -> pruned, listed as one surrogate;
+    #   the cell's geometric centre (6, 2) would give 4 / 6.325 = 0.632 and
+    #   the plain member mean (6, 0.2) 4 / 6.003 = 0.666: both open the cell
+    #   and list bodies 1 and 2 one by one.
+    # Bodies 3 and 4: 4 / 8 and 4 / 11.3 -> pruned single bodies.
+    P = np.array([[0.0, 0.0], [4.2, 0.2], [7.8, 0.2], [0.0, 8.0], [8.0, 8.0]])
+    g = np.array([1.0, 0.01, 1.0, 1.0, 1.0])
+    tree = oo.QuadTree(P, 6)
+    want = [(0, 3, 0, 0), (0, 4, 0, 0), (1, 1, 0, 1)]
+    assert sorted(oo.find_clusters(tree, 0, 0.0, "barnes-hut", 0.6, g)) == want
+    # the same tree read with the other two centres opens the cell
+    cell = [nd for nd in tree.nodes if nd.key == (1, 1, 0, 1)][0]
+    for centre in ((cell.lo + cell.hi) / 2, P[[1, 2]].mean(axis=0)):
+        assert cell.width / np.linalg.norm(centre - P[0]) > 0.6
+    assert cell.width / np.linalg.norm(oo.weighted_point_mean(tree, cell, g) - P[0]) <= 0.6
+    # the native clustering takes the same decision
+    xy0 = np.concatenate([P[:, 0], P[:, 1]])
+    phi = np.linalg.qr(np.random.default_rng(0).standard_normal((10, 2)))[0]
+    r = native.cluster_build(P, xy0, phi, g, 6, 0.0, np.array([0]), native.BARNES_HUT, 0.6)
+    assert list(r["keys"]) == [3, 4, (1 << 60) | (1 << 40) | (0 << 20) | 1]
+    assert list(r["off"]) == [0, 3]
+    # and lists bodies 1 and 2 separately once theta is below 0.515
+    r = native.cluster_build(P, xy0, phi, g, 6, 0.0, np.array([0]), native.BARNES_HUT, 0.5)
+    assert list(r["keys"]) == [1, 2, 3, 4]
+    assert sorted(oo.find_clusters(tree, 0, 0.0, "barnes-hut", 0.5, g)) == [(0, j, 0, 0) for j in (1, 2, 3, 4)]

@@ -419,3 +419,36 @@ def test_gnat_with_full_sample_and_full_residual_basis_is_lspg():
     moved = oracle.Rom(off.rom_artifacts(np.arange(40), tree, 1.0, cl.xy, Phi, g, cl.delta, dt, A=A2)).run(
         T, tol=1e-12, max_iter=8)
     assert np.abs(moved["hist"] - lspg["hist"]).max() > 1e-4
+
+
+def test_greedy_refit_on_sampled_rows_decides_the_second_pick():
+    # Greedy sampling, later groups: the new residual-basis vector is replaced
+    # by its gappy reconstruction error from the processed vectors, fitted on
+    # the rows of the bodies sampled so far.  Worked by hand on n = 4 bodies
+    # (rows chi_0..chi_3, psi_0..psi_3), two orthogonal columns, ns = 2, so
+    # n_c = 2 and n_it = 2: one column and one body per group.
+    #   a = ( 2, 0, -1,  0 |  0,  0, 1, 0) / sqrt(6)
+    #   b = (-1, 0,  0, -2 | -2, -2, 2, 1) / sqrt(18)       a . b = 0
+    # group 1 scores (a):  body 0: 4, body 1: 0, body 2: 2, body 3: 0  (x 1/6)  -> body 0
+    # group 2, fit of b on a over body 0's rows (chi_0, psi_0): coefficient
+    #   (2 (-1) + 0 (-2)) / (2^2 + 0^2) = -1/2 (in the unscaled entries), so
+    #   R = b + a/2 = (0, 0, -1/2, -2 | -2, -2, 5/2, 1)
+    #   scores: body 1: 4, body 2: 1/4 + 25/4 = 13/2, body 3: 5  -> body 2
+    # Without the refit R = b: body 1: 4, body 2: 4, body 3: 5 -> body 3; a
+    # fit over all rows has coefficient a . b = 0 and gives the same body 3.
+    a = np.array([2, 0, -1, 0, 0, 0, 1, 0], float) / np.sqrt(6.0)
+    b = np.array([-1, 0, 0, -2, -2, -2, 2, 1], float) / np.sqrt(18.0)
+    Phi_r = np.column_stack([a, b])
+    assert list(off.greedy_sample(Phi_r, 2)) == [0, 2]
+    n = 4
+
+    def second_pick(R):
+        s = R[:n] ** 2 + R[n:] ** 2
+        s[0] = -np.inf
+        return int(np.argmax(s))
+
+    # the two other readings pick body 3, so the pin tells them apart
+    assert second_pick(b) == 3
+    assert second_pick(b - a * (a @ b) / (a @ a)) == 3
+    rows = [0, n]
+    assert second_pick(b - a * (a[rows] @ b[rows]) / (a[rows] @ a[rows])) == 2
