@@ -401,10 +401,23 @@ enum {
 /* The launch the context would use for operation op at n bodies, written to
  * the caller's HOST array out[5]: source staging (0 LDS tiles, 1 scalar
  * cache), targets per lane, waves per SIMD, each-unordered-pair-once form
- * (0/1), and the number of source chunks of the one-sided form (0 for the
- * each-pair-once form).  Host only; EINVAL for an unknown op or n outside
- * [1, 2^30]. */
+ * (0/1), and the number of source chunks of the one-sided form
+ * (0 for the each-pair-once form).  The each-pair-once form keeps one
+ * partial-sum slot per body and block of 256 K bodies, a workspace that grows
+ * as N^2; where it would pass 1/32 of the device's memory the one-sided form
+ * (workspace O(N)) is used instead.  Host only; EINVAL for an unknown op or n
+ * outside [1, 2^30]. */
 int ptrom_pair_config(ptrom_ctx *ctx, int op, int64_t n, int32_t *out);
+
+/* The same decision without a device or context (capacity planning; uses no
+ * HIP call): the launch a device with num_cus compute units and device_bytes
+ * of memory would use for op at n bodies under the tuning file tuning_path
+ * (NULL: the built-in defaults), written to out[5] as above, and the
+ * workspace in bytes that launch needs (ws_bytes may be NULL).  EINVAL for an
+ * unknown op, n outside [1, 2^30], num_cus < 1, device_bytes = 0, or a
+ * tuning file that cannot be read or holds no entries. */
+int ptrom_pair_plan(const char *tuning_path, int num_cus, uint64_t device_bytes, int op, int64_t n,
+                    int32_t *out, uint64_t *ws_bytes);
 
 #ifdef __cplusplus
 }

@@ -44,7 +44,10 @@ extern "C" int ptrom_create(ptrom_ctx **out, int device) {
   ptrom_ctx *c = new ptrom_ctx();
   c->device = device;
   hipDeviceProp_t p;
-  if (hipGetDeviceProperties(&p, device) == hipSuccess) c->num_cus = p.multiProcessorCount;
+  if (hipGetDeviceProperties(&p, device) == hipSuccess) {
+    c->num_cus = p.multiProcessorCount;
+    if (p.totalGlobalMem) c->tune.ws_cap_bytes = uint64_t(p.totalGlobalMem) / kWsCapDivisor;
+  }
   if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return PTROM_EHIP;

@@ -39,10 +39,20 @@ struct PairCfg {
 };
 
 // One tuned entry per operation and size class (log2 of N, clamped).
+// The each-pair-once form keeps one partial-sum slot per body and block
+// (2 nb NA N floats, growing as N^2); where that would pass ws_cap_bytes
+// the one-sided form (workspace O(N)) is used instead.
 struct Tuning {
   std::map<std::pair<int, int>, PairCfg> table;
+  uint64_t ws_cap_bytes = uint64_t(8) << 30;  // set per device: its memory / kWsCapDivisor
   PairCfg get(int op, int64_t n) const;
+  PairCfg get_table(int op, int64_t n) const;  // the table's entry, without the cap
 };
+
+constexpr uint64_t kWsCapDivisor = 32;
+
+// One-sided launch used where the each-pair-once workspace would be too large.
+PairCfg large_n_cfg();
 
 int size_class(int64_t n);
 

@@ -231,7 +231,24 @@ int size_class(int64_t n) {
   return c < 8 ? 8 : (c > 24 ? 24 : c);
 }
 
+PairCfg large_n_cfg() {
+  PairCfg c;
+  c.staging = STAGE_LDS;
+  c.k = 2;
+  c.waves_per_simd = 8;
+  c.sym = 0;
+  return c;
+}
+
 PairCfg Tuning::get(int op, int64_t n) const {
+  PairCfg c = get_table(op, n);
+  if (c.sym && has_sym(op) && uint64_t(pair_sym_ws_floats(op, c.k, n)) * sizeof(float) > ws_cap_bytes)
+    c = large_n_cfg();
+  if (!has_sym(op)) c.sym = 0;
+  return c;
+}
+
+PairCfg Tuning::get_table(int op, int64_t n) const {
   const int cls = size_class(n);
   const PairCfg *best = nullptr;
   int bestd = 1 << 30;

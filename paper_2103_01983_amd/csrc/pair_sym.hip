@@ -7,28 +7,41 @@
 // q_ji = -q_ij).  The self blocks of the Jacobian are symmetric instead:
 // H(-r) = H(r), so body j's block gains Gamma_i H(r) with the same sign.
 // The body index range is cut into blocks of 256*K; block pairs (I, J) with
-// J > I are evaluated once (sym_block_pair in pair_sym_core.h), each
-// interaction adding the forward term to the target (registers) and the
-// reaction term to the source; diagonal blocks (I, I) use the ordinary
-// one-sided tile.  Workgroups pop items from a device counter (persistent
-// launch).  Forward sums land in F[J][.][N], reactions in R[I][.][N]; a final
-// kernel adds, per body, its forward slots J >= block(b) and reaction slots
-// I < block(b) in a fixed order (Kahan compensated sums over 8 contiguous
-// slot ranges, combined in range order), so results are bitwise
-// reproducible.
+// J > I are evaluated once, each interaction adding the forward term to the
+// target (registers) and the reaction term to the source; diagonal blocks
+// (I, I) use the ordinary one-sided tile.
+// Workgroups pop items from a device counter (persistent launch).  Item q
+// of the nb (nb + 1) / 2 block pairs is decoded arithmetically: the items
+// run by decreasing block distance d = J - I, so the cheaper diagonal items
+// (d = 0) come last and fill the launch's tail.  Forward sums land in
+// F[J][.][N], reactions in R[I][.][N]; a final kernel adds, per body, its
+// forward slots J >= block(b) and reaction slots I < block(b) in a fixed
+// order (Kahan compensated sums over 8 contiguous slot ranges, combined in
+// range order), so results are bitwise reproducible.
 #include "pair_sym_core.h"
 
 namespace ptrom {
 namespace {
 
-__global__ void sym_reset_kernel(int *__restrict__ counter) {
+__global__ void sym_reset_kernel(unsigned long long *__restrict__ counter) {
   if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// Block pair of item q: with e = floor((sqrt(8 q + 1) - 1) / 2) the items
+// e (e + 1) / 2 .. e (e + 1) / 2 + e share the distance d = nb - 1 - e, and
+// I runs from 0 in that group.
+__device__ __forceinline__ void tri_item(long long q, int nb, int &I, int &J) {
+  long long e = (long long)((__builtin_sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
+  while (e * (e + 1) / 2 > q) --e;
+  while ((e + 1) * (e + 2) / 2 <= q) ++e;
+  I = int(q - e * (e + 1) / 2);
+  J = I + (nb - 1 - int(e));
 }
 
 template <int OP, int K>
 __global__ void __launch_bounds__(kBlock)
     pair_sym_kernel(int n, const float *__restrict__ xy, const float *__restrict__ gam,
-                    const float *__restrict__ aux, float d2, int nb, int *__restrict__ counter,
+                    const float *__restrict__ aux, float d2, int nb, unsigned long long *__restrict__ counter,
                     float *__restrict__ F, float *__restrict__ R) {
   using T = Traits<OP>;
   constexpr int NA = T::NACC, NS = T::NSRC;
@@ -39,17 +52,18 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ float4 s_src[128][2];
   __shared__ float racc_lds[kBlock / 64][NA][64];
   __shared__ float lds_diag[NS * kTile];
-  __shared__ int item_s;
+  __shared__ unsigned long long item_s;
   const int tid = threadIdx.x;
+  const long long items = (long long)nb * (nb + 1) / 2;
 
   for (;;) {
-    if (tid == 0) item_s = atomicAdd(counter, 1);
+    if (tid == 0) item_s = atomicAdd(counter, 1ull);
     __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(item_s);
+    const long long it = (long long)item_s;
     __syncthreads();
-    if (it >= nb * nb) break;
-    const int I = it / nb, J = it % nb;
-    if (J < I) continue;
+    if (it >= items) break;
+    int I, J;
+    tri_item(it, nb, I, J);
     const int tgt0 = I * TB;
     if (J == I) {
       float res[K][NA];
@@ -120,7 +134,7 @@ hipError_t launch_sym_t(int n, const float *xy, const float *gam, const float *a
   const int nb = (n + tb - 1) / tb;
   float *F = ws;
   float *R = ws + (size_t)nb * NA * n;
-  int *counter = reinterpret_cast<int *>(R + (size_t)nb * NA * n);
+  auto *counter = reinterpret_cast<unsigned long long *>(R + (size_t)nb * NA * n);
   hipLaunchKernelGGL(sym_reset_kernel, dim3(1), dim3(64), 0, st, counter);
   hipLaunchKernelGGL((pair_sym_kernel<OP, K>), dim3(grid), dim3(kBlock), 0, st, n, xy, gam, aux, d2, nb,
                      counter, F, R);

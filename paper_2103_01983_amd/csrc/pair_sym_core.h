@@ -128,11 +128,13 @@ __device__ __forceinline__ void sym_block_pair(int n, const float *__restrict__ 
     }
     tg[k][4] = ok ? gam[i] : 0.0f;
   }
-  float sum[K][NA], cmp[K][NA];
+  // forward partials: plain FP32 over a 256-source tile, then added to the
+  // compensated sums
+  float sum[K][NA], cmp[K][NA], part[K][NA];
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
-    for (int a = 0; a < NA; ++a) sum[k][a] = cmp[k][a] = 0.0f;
+    for (int a = 0; a < NA; ++a) sum[k][a] = cmp[k][a] = part[k][a] = 0.0f;
 
   for (int u = 0; u < TB; u += 64) {
     const int j0 = src0 + u;
@@ -150,11 +152,7 @@ __device__ __forceinline__ void sym_block_pair(int n, const float *__restrict__ 
       s_src[tid + 64][1] = b;
     }
     __syncthreads();
-    float part[K][NA], racc[NA];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int a = 0; a < NA; ++a) part[k][a] = 0.0f;
+    float racc[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) racc[a] = 0.0f;
     const float4(*src)[2] = s_src + lane;
@@ -173,10 +171,15 @@ __device__ __forceinline__ void sym_block_pair(int n, const float *__restrict__ 
     // lane l now holds the reaction on source (l - 1) mod 64
 #pragma unroll
     for (int a = 0; a < NA; ++a) racc_lds[wave][a][(lane + 63) & 63] = racc[a];
+    if ((u & (kTile - 64)) == kTile - 64 || u + 64 >= TB || j0 + 64 >= n) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+      for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int a = 0; a < NA; ++a) kahan_add(sum[k][a], cmp[k][a], part[k][a]);
+        for (int a = 0; a < NA; ++a) {
+          kahan_add(sum[k][a], cmp[k][a], part[k][a]);
+          part[k][a] = 0.0f;
+        }
+    }
     __syncthreads();
     if (tid < 64 && j0 + tid < n) {
 #pragma unroll
@@ -198,3 +201,4 @@ __device__ __forceinline__ void sym_block_pair(int n, const float *__restrict__ 
 }
 
 }  // namespace ptrom
+

@@ -16,10 +16,11 @@ using namespace ptrom;
 static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp", "stream_function",
                                          "velocity_block_jacobian"};
 
-extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
-  if (!ctx || !path) return PTROM_EINVAL;
+// Reads a tuning file into t; returns the number of entries loaded (-1 if the
+// file cannot be opened).
+static int read_tuning(const char *path, Tuning &t) {
   std::ifstream in(path);
-  if (!in) return ctx->fail(PTROM_EINVAL, std::string("cannot open ") + path);
+  if (!in) return -1;
   std::string line;
   int loaded = 0;
   while (std::getline(in, line)) {
@@ -42,9 +43,16 @@ extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
     c.k = k;
     c.waves_per_simd = waves;
     c.sym = has_sym(op) ? sym : 0;
-    ctx->tune.table[{op, cls}] = c;
+    t.table[{op, cls}] = c;
     ++loaded;
   }
+  return loaded;
+}
+
+extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
+  if (!ctx || !path) return PTROM_EINVAL;
+  const int loaded = read_tuning(path, ctx->tune);
+  if (loaded < 0) return ctx->fail(PTROM_EINVAL, std::string("cannot open ") + path);
   return loaded ? PTROM_OK : ctx->fail(PTROM_EINVAL, "no tuning entries");
 }
 
@@ -149,14 +157,30 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
   return PTROM_OK;
 }
 
-extern "C" int ptrom_pair_config(ptrom_ctx *ctx, int op, int64_t n, int32_t *out) {
-  if (!ctx || !out || op < 0 || op >= OP_COUNT || n < 1 || n > kMaxN) return PTROM_EINVAL;
-  const PairCfg c = ctx->tune.get(op, n);
+static void describe(const PairCfg &c, int op, int num_cus, int64_t n, int32_t *out) {
   const bool sym = c.sym && has_sym(op);
   out[0] = c.staging;
   out[1] = c.k;
   out[2] = c.waves_per_simd;
   out[3] = sym ? 1 : 0;
-  out[4] = sym ? 0 : pair_splits(op, c, ctx->num_cus, n);
+  out[4] = sym ? 0 : pair_splits(op, c, num_cus, n);
+}
+
+extern "C" int ptrom_pair_config(ptrom_ctx *ctx, int op, int64_t n, int32_t *out) {
+  if (!ctx || !out || op < 0 || op >= OP_COUNT || n < 1 || n > kMaxN) return PTROM_EINVAL;
+  describe(ctx->tune.get(op, n), op, ctx->num_cus, n, out);
+  return PTROM_OK;
+}
+
+extern "C" int ptrom_pair_plan(const char *tuning_path, int num_cus, uint64_t device_bytes, int op, int64_t n,
+                               int32_t *out, uint64_t *ws_bytes) {
+  if (!out || op < 0 || op >= OP_COUNT || n < 1 || n > kMaxN || num_cus < 1 || device_bytes == 0)
+    return PTROM_EINVAL;
+  Tuning t;
+  t.ws_cap_bytes = device_bytes / kWsCapDivisor;
+  if (tuning_path && read_tuning(tuning_path, t) <= 0) return PTROM_EINVAL;
+  const PairCfg c = t.get(op, n);
+  describe(c, op, num_cus, n, out);
+  if (ws_bytes) *ws_bytes = uint64_t(pair_ws_floats(op, c, num_cus, n)) * sizeof(float);
   return PTROM_OK;
 }

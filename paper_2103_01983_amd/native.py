@@ -95,6 +95,8 @@ SIGNATURES = {
     "ptrom_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "ptrom_load_tuning": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "ptrom_pair_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+    "ptrom_pair_plan": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None
@@ -602,3 +604,17 @@ def pair_config(op, n, device=None, ctx=None):
     _check(c, lib().ptrom_pair_config(c, PAIR_OPS[op], int(n), out), "ptrom_pair_config")
     return dict(staging=int(out[0]), k=int(out[1]), waves_per_simd=int(out[2]), sym=int(out[3]),
                 splits=int(out[4]))
+
+
+def pair_plan(op, n, num_cus=256, device_bytes=288 * 10**9, tuning_path=TUNING_PATH):
+    """The launch and workspace (bytes) a device with ``num_cus`` compute units
+    and ``device_bytes`` of memory would use for ``op`` at n bodies (host only,
+    no GPU needed): dict(staging, k, waves_per_simd, sym, splits, ws_bytes)."""
+    out = (ctypes.c_int32 * 5)()
+    ws = ctypes.c_uint64()
+    rc = lib().ptrom_pair_plan(tuning_path.encode() if tuning_path else None, int(num_cus), int(device_bytes),
+                               PAIR_OPS[op], int(n), out, ctypes.byref(ws))
+    if rc != PTROM_OK:
+        raise PtromError("ptrom_pair_plan failed (%d)" % rc)
+    return dict(staging=int(out[0]), k=int(out[1]), waves_per_simd=int(out[2]), sym=int(out[3]),
+                splits=int(out[4]), ws_bytes=int(ws.value))
