@@ -87,6 +87,24 @@ const char *ptrom_last_error(const ptrom_ctx *ctx);
 int ptrom_velocity(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
                    float *f, ptrom_stream stream);
 
+/* ptrom_velocity for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments and result, but the call allocates nothing.  Partial sums
+ * go to a fixed 36 MiB device array that the library holds on every device
+ * it runs on until the process ends (its address is looked up once per
+ * device by ptrom_create).  The launch is the context's own when its
+ * workspace fits that array (N <= 32768 with the shipped table: results
+ * bitwise equal to ptrom_velocity's); beyond, the one-sided pair kernel with
+ * as many source chunks as fit (the same FP32 sums in another order; above
+ * 2.36 million bodies one chunk, which needs no scratch).  A launch needing
+ * more than the array is rejected with PTROM_ENOMEM and a message (it cannot
+ * arise with these rules).  All calls on one device share the array, so
+ * calls that overlap on one device (other streams, other threads or
+ * contexts) race; serialise them.  Errors as ptrom_velocity; PTROM_EHIP if
+ * the array's address could not be looked up. */
+int ptrom_velocity_noalloc(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
+                           float *f, ptrom_stream stream);
+
 /* FP64 version of ptrom_velocity (plain double sums, IEEE division). */
 int ptrom_velocity_f64(ptrom_ctx *ctx, int64_t n, const double *xy, const double *gamma,
                        double delta, double *f, ptrom_stream stream);

@@ -52,6 +52,9 @@ extern "C" int ptrom_create(ptrom_ctx **out, int device) {
     delete c;
     return PTROM_EHIP;
   }
+  // the allocation-free velocity call's scratch address on this device
+  // (kept per device; a failure is reported by that call)
+  (void)noalloc_init(device);
   const char *cache = std::getenv("PTROM_TUNE_CACHE");
   if (cache && *cache) ptrom_load_tuning(c, cache);
   c->err.clear();

@@ -36,6 +36,7 @@ struct PairCfg {
   int k = 2;               // targets per lane
   int waves_per_simd = 8;  // occupancy target used to choose the source split
   int sym = 0;             // 1: evaluate each unordered pair once (pair_sym.hip)
+  int max_splits = 0;      // one-sided form: at most this many source chunks (0 = no limit)
 };
 
 // One tuned entry per operation and size class (log2 of N, clamped).
@@ -90,6 +91,10 @@ hipError_t launch_rk4_combine_f64(int64_t m, double *x, const double *k1, const 
                                   const double *k3, const double *k4, double h, hipStream_t s);
 
 struct BatchPlan;
+
+// Looks up, once per device, the device address of the allocation-free
+// velocity call's scratch array (noalloc.hip); device must be current.
+hipError_t noalloc_init(int device);
 
 }  // namespace ptrom
 

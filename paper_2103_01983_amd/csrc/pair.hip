@@ -285,6 +285,7 @@ int64_t pair_chunk(const PairCfg &cfg, int num_cus, int64_t n) {
     unit = kSubChunk;
     max_s = std::min<int64_t>((n + kSubChunk - 1) / kSubChunk, kMaxSubSplits);
   }
+  if (cfg.max_splits > 0 && max_s > cfg.max_splits) max_s = cfg.max_splits;
   if (s < 1) s = 1;
   if (s > max_s) s = max_s;
   return ((n + s - 1) / s + unit - 1) / unit * unit;

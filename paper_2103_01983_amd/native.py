@@ -57,6 +57,7 @@ SIGNATURES = {
     "ptrom_destroy": (None, [_vp]),
     "ptrom_last_error": (ctypes.c_char_p, [_vp]),
     "ptrom_velocity": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
+    "ptrom_velocity_noalloc": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
     "ptrom_velocity_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f64, _vp, _vp]),
     "ptrom_jvp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp]),
     "ptrom_block_jacobian": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
@@ -201,6 +202,18 @@ def velocity(xy, gamma, delta, out=None, ctx=None):
     _check(c, lib().ptrom_velocity(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
                                    _ptr(gamma, torch.float32, n, "gamma"), float(delta),
                                    _ptr(out, torch.float32, 2 * n, "out"), _stream(xy)), "ptrom_velocity")
+    return out
+
+
+def velocity_noalloc(xy, gamma, delta, out, ctx=None):
+    """ptrom_velocity_noalloc: the velocity into the caller's ``out`` [2N]; the
+    library allocates no device memory for it."""
+    n = _n(xy)
+    c = context(xy.device) if ctx is None else ctx
+    _check(c, lib().ptrom_velocity_noalloc(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
+                                           _ptr(gamma, torch.float32, n, "gamma"), float(delta),
+                                           _ptr(out, torch.float32, 2 * n, "out"), _stream(xy)),
+           "ptrom_velocity_noalloc")
     return out
 
 
