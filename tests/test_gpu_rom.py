@@ -409,3 +409,45 @@ def test_empty_list_parity(dev, trained, large_shapes):
         assert a["off"][1] == a["off"][2]
         _hyperpair_check(dev, a, 9)
         _run_check(dev, a)
+
+
+@pytest.fixture(scope="module")
+def trained_large():
+    """Artifacts trained by the oracle's offline pipeline at the paper's
+    parametric sizes: the vortex pair (N = 500, M = 85, M_r = 110, n_s = 60)
+    and the mushroom cloud with its inflow (N = 500, M = 110, M_r = 185,
+    n_s = 75), four training parameters each, over the first 30 steps of the
+    studies' time step (the full horizon takes minutes in the oracle)."""
+    out = {}
+    vp = [W.vortex_pair(m) for m in ((80.0, 200.0), (150.0, 100.0), (230.0, 240.0), (110.0, 70.0))]
+    art, _ = off.train_parametric(vp, 0.01, 30, M=85, Mr=110, ns=60, depth=16, pc=1.0, tol=1e-4)
+    out["vortex_pair"] = rounded(art)
+    mc = [W.mushroom_cloud(m) for m in ((-200.0, 130.0), (-120.0, 210.0), (-170.0, 170.0), (-140.0, 120.0))]
+    art, _ = off.train_parametric(mc, 0.005, 30, M=110, Mr=185, ns=75, depth=16, pc=1.0, tol=1e-4,
+                                  u=W.mushroom_inflow(500))
+    out["mushroom_cloud"] = rounded(art)
+    return out
+
+
+@pytest.mark.parametrize("case", ["vortex_pair", "mushroom_cloud"])
+def test_large_run_trained_artifacts(dev, trained_large, case):
+    # the larger-basis path (normal equations of A C on the FP64 matrix cores,
+    # blocked Gauss-Jordan, C held in FP32) on trained artifacts, fixed K
+    # Gauss-Newton iterations per step, against the oracle's Householder QR
+    art = trained_large[case]
+    M = art["M"]
+    xb, fb, rb, C = oracle.Rom(art).hyperpair(np.zeros(M), art["xbar0"], np.zeros(len(art["xbar0"])))
+    cond = np.linalg.cond(art["A"] @ C)
+    steps, K = 12, 3
+    o = oracle.Rom(art).run(steps, tol=0.0, max_iter=K)
+    rom = native.Rom(art, tol=0.0, max_iter=K)
+    xh = torch.zeros(M, dtype=torch.float64, device=dev)
+    hist = torch.empty(steps * M, dtype=torch.float64, device=dev)
+    it = torch.empty(steps, dtype=torch.int32, device=dev)
+    rom.run(steps, xh, hist, it)
+    torch.cuda.synchronize()
+    assert np.all(it.cpu().numpy() == K)
+    h = hist.cpu().numpy().reshape(steps, M)
+    assert np.all(np.isfinite(h))
+    assert rel(h, o["hist"]) <= 1e-5, "cond(AC) = %.3g" % cond
+    rom.close()

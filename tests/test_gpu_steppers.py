@@ -180,3 +180,49 @@ def test_backward_euler_full_size_residual(dev, solver):
     u = 2.0 ** -24
     rounding = u * np.linalg.norm(np.abs(xn[sel]) + np.abs(xprev[sel]))
     assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(dtf * fo) + rounding
+
+
+def test_backward_euler_c2_fifty_steps(dev):
+    # the whole backward-Euler run of the Gaussian-patch configuration
+    # (N = 65536, 50 steps at dt 5e-4, Newton-GMRES): every step converges,
+    # and the last step satisfies x_50 - x_49 - dt f(x_50) = 0 on sampled
+    # rows with f from the oracle, within the Newton tolerance (1e-6 of the
+    # step's initial residual dt f) plus the FP32 velocity error and the
+    # rounding of the stored states
+    cfg = W.CONFIGS["c2_gaussian_patch"]
+    c = W.config_cloud("c2_gaussian_patch")
+    n = c.n
+    x = torch.tensor(c.xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(c.gamma, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], cfg["steps"] - 1)
+    assert st.nonconverged_steps == 0 and st.max_final_rel_residual <= 1e-6
+    xprev = x.cpu().numpy().astype(np.float64)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], 1)
+    assert st.nonconverged_steps == 0 and st.max_final_rel_residual <= 1e-6
+    xn = x.cpu().numpy().astype(np.float64)
+    idx = np.random.default_rng(50).choice(n, 128, replace=False)
+    sel = np.concatenate([idx, n + idx])
+    fo = oracle.velocity_at(xn, f32(c.gamma), float(np.float32(c.delta)), idx)
+    dtf = float(np.float32(cfg["dt"]))
+    r = xn[sel] - xprev[sel] - dtf * fo
+    u = 2.0 ** -24
+    rounding = u * np.linalg.norm(np.abs(xn[sel]) + np.abs(xprev[sel]))
+    assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(dtf * fo) + rounding
+
+
+def test_backward_euler_fifty_steps_trajectory_reduced_n(dev):
+    # the same 50-step backward-Euler run on the configuration's Gaussian
+    # patch at N = 4096: final positions against the FP64 oracle's implicit
+    # stepper (Newton to 1e-12, GMRES to 1e-14)
+    cfg = W.CONFIGS["c2_gaussian_patch"]
+    c = W.config_cloud("c2_gaussian_patch", n=4096)
+    xy, g = f32(c.xy), f32(c.gamma)
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    gd = torch.tensor(g, dtype=torch.float32, device=dev)
+    st = native.implicit(x, gd, c.delta, cfg["dt"], cfg["steps"], newton_tol=1e-6)
+    assert st.nonconverged_steps == 0
+    o, ost = oracle.implicit(xy, g, float(np.float32(c.delta)), float(np.float32(cfg["dt"])), cfg["steps"])
+    assert ost.nonconverged_steps == 0
+    xs = x.cpu().numpy()
+    assert rel(xs, o) <= 1e-5
+    assert rel(xs - xy, o - xy) <= 1e-4
