@@ -144,6 +144,15 @@ int ptrom_vjp(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, fl
 int ptrom_stream_function(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
                           float *psi, ptrom_stream stream);
 
+/* The Hamiltonian of the metrics section in its regularized, conserved form,
+ *   H = -(1/4pi) sum_{i != j} Gamma_i Gamma_j 1/2 log(|r_ij|^2 + delta^2)
+ *     = 1/2 sum_i Gamma_i psi_i   (psi as in ptrom_stream_function),
+ * written to H (DEVICE, one double).  The stream function is summed in FP32
+ * (compensated), the final sum over bodies in FP64 in a fixed order.  The
+ * paper's printed form is its delta = 0 case with the opposite sign. */
+int ptrom_hamiltonian(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta, double *H,
+                      ptrom_stream stream);
+
 /* Velocity induced at nt arbitrary points p [2][nt] (SoA) by all n bodies, no
  * exclusion (the grid velocity field of the metrics section); f [2][nt]. */
 int ptrom_velocity_points(ptrom_ctx *ctx, int64_t nt, const float *p, int64_t n, const float *xy,

@@ -146,6 +146,72 @@ extern "C" int ptrom_stream_function(ptrom_ctx *ctx, int64_t n, const float *xy,
   return run_pair(ctx, OP_PSI, n, xy, gamma, nullptr, delta, psi, nullptr, (hipStream_t)stream);
 }
 
+namespace {
+
+// H = 1/2 sum_i Gamma_i psi_i in FP64: each workgroup adds a contiguous
+// range in a fixed order (tree over its threads), then one workgroup adds
+// the partials in workgroup order, so the result is reproducible.
+constexpr int kHamBlock = 256;
+constexpr int kHamMaxParts = 1024;
+
+__global__ void __launch_bounds__(kHamBlock)
+    ham_partial_kernel(int64_t n, const float *__restrict__ gam, const float *__restrict__ psi, int64_t per,
+                       double *__restrict__ part) {
+  __shared__ double s[kHamBlock];
+  const int64_t b0 = int64_t(blockIdx.x) * per;
+  const int64_t b1 = b0 + per < n ? b0 + per : n;
+  double acc = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kHamBlock) acc += double(gam[i]) * double(psi[i]);
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kHamBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(kHamBlock)
+    ham_final_kernel(int parts, const double *__restrict__ part, double *__restrict__ H) {
+  __shared__ double s[kHamBlock];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < parts; q += kHamBlock) acc += part[q];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kHamBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) H[0] = 0.5 * s[0];
+}
+
+}  // namespace
+
+extern "C" int ptrom_hamiltonian(ptrom_ctx *ctx, int64_t n, const float *xy, const float *gamma, float delta,
+                                 double *H, ptrom_stream stream) {
+  if (int rc = check_common(ctx, n, delta)) return rc;
+  if (!xy || !gamma || !H) return ctx->fail(PTROM_EINVAL, "NULL array");
+  const PairCfg cfg = ctx->tune.get(OP_PSI, n);
+  const size_t pwsf = pair_ws_floats(OP_PSI, cfg, ctx->num_cus, n);
+  const int parts = int(std::min<int64_t>(kHamMaxParts, (n + kHamBlock - 1) / kHamBlock));
+  const int64_t per = (n + parts - 1) / parts;
+  if (int rc = ctx->reserve(align256(size_t(n) * sizeof(float)) + align256(parts * sizeof(double)) +
+                            align256(pwsf * sizeof(float)) + 256))
+    return rc;
+  Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
+  float *psi = cv.take<float>(n);
+  double *part = cv.take<double>(parts);
+  float *pws = cv.take<float>(pwsf ? pwsf : 1);
+  if (!psi || !part || !pws) return ctx->fail(PTROM_ENOMEM, "workspace carve");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_pair(OP_PSI, cfg, ctx->num_cus, n, xy, gamma, nullptr, delta, psi, nullptr, pws, pwsf, st);
+  if (e != hipSuccess) return ctx->hip_fail(e, "stream function launch");
+  hipLaunchKernelGGL(ham_partial_kernel, dim3(parts), dim3(kHamBlock), 0, st, n, gamma, psi, per, part);
+  hipLaunchKernelGGL(ham_final_kernel, dim3(1), dim3(kHamBlock), 0, st, parts, part, H);
+  PTROM_CHECK_HIP(ctx, hipGetLastError());
+  return PTROM_OK;
+}
+
 extern "C" int ptrom_velocity_points(ptrom_ctx *ctx, int64_t nt, const float *p, int64_t n, const float *xy,
                                      const float *gamma, float delta, float *f, ptrom_stream stream) {
   if (int rc = check_common(ctx, n, delta)) return rc;

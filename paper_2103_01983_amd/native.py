@@ -64,6 +64,7 @@ SIGNATURES = {
     "ptrom_velocity_block_jacobian": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp]),
     "ptrom_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp, _vp, _vp]),
     "ptrom_stream_function": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
+    "ptrom_hamiltonian": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _vp, _vp]),
     "ptrom_velocity_points": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _f32, _vp, _vp]),
     "ptrom_rk4": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f32, _f32, ctypes.c_int, _vp]),
     "ptrom_rk4_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp, _f64, _f64, ctypes.c_int, _vp]),
@@ -286,10 +287,16 @@ def stream_function(xy, gamma, delta, out=None, ctx=None):
     return out
 
 
-def hamiltonian(xy, gamma, delta):
-    """Regularized Hamiltonian 1/2 sum_i Gamma_i psi_i (the final sum in FP64 on the device)."""
-    psi = stream_function(xy, gamma, delta)
-    return 0.5 * torch.dot(gamma.double(), psi.double())
+def hamiltonian(xy, gamma, delta, out=None, ctx=None):
+    """Regularized Hamiltonian 1/2 sum_i Gamma_i psi_i (ptrom_hamiltonian): a
+    one-element FP64 device tensor."""
+    n = _n(xy)
+    out = torch.empty(1, dtype=torch.float64, device=xy.device) if out is None else out
+    c = context(xy.device) if ctx is None else ctx
+    _check(c, lib().ptrom_hamiltonian(c, n, _ptr(xy, torch.float32, 2 * n, "xy"),
+                                      _ptr(gamma, torch.float32, n, "gamma"), float(delta),
+                                      _ptr(out, torch.float64, 1, "H"), _stream(xy)), "ptrom_hamiltonian")
+    return out[0]
 
 
 def velocity_points(points, xy, gamma, delta, out=None):

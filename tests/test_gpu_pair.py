@@ -153,6 +153,22 @@ def test_stream_function_parity(dev, n, delta):
     assert abs(H - Ho) <= 1e-5 * abs(Ho)
 
 
+def test_hamiltonian_many_bodies_few_strengths(dev):
+    # 300000 bodies of which three carry circulation: the device reduction
+    # (1024 partial ranges of 293 bodies, then their sum) gives the
+    # three-body Hamiltonian, since bodies without circulation add nothing
+    n = 300000
+    rng = np.random.default_rng(12)
+    xy = rng.standard_normal(2 * n).astype(np.float32).astype(np.float64)
+    g = np.zeros(n)
+    pick = np.array([5, 150001, n - 1])
+    g[pick] = [0.75, -1.25, 2.0]
+    H = native.hamiltonian(to_dev(xy, dev), to_dev(g, dev), 0.05).item()
+    sub = np.concatenate([xy[pick], xy[n + pick]])
+    Ho = oracle.hamiltonian(sub, g[pick], float(np.float32(0.05)))
+    assert abs(H - Ho) <= 1e-5 * abs(Ho)
+
+
 @pytest.mark.parametrize("n, nt", [(3000, 1000), (1025, 777), (256, 1)])
 def test_velocity_points_parity(dev, n, nt):
     # source chunks split across workgroups (ragged last chunk, a single
