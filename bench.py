@@ -481,8 +481,9 @@ def rom_form(native, W, dev, timed, gather_ns=(16, 256, 2048, 16384)):
 
 
 def gather_sweep(native, offline, info, cl, art, dev, timed, sizes=(16, 256, 2048, 16384)):
-    """HyperPair gather over growing sample sets (random bodies; same tree,
-    basis and clustering): HBM bytes streamed per evaluation / time."""
+    """HyperPair gather (point form: surrogate positions once, then 4 bytes
+    per list entry) over growing sample sets (random bodies; same tree, basis
+    and clustering): algorithmic bytes per evaluation / time."""
     import torch
     n = cl.n
     rng = np.random.default_rng(11)
@@ -501,11 +502,24 @@ def gather_sweep(native, offline, info, cl, art, dev, timed, sizes=(16, 256, 204
         reps = 20
         sec = timed(lambda: rom.hyperpair(xh, prev, prev), reps=reps)
         nnz = int(a["ids"].size)
-        ew = 4 + (2 * M + 3) // 4 * 4
-        # entry rows, offsets, sampled rows and previous-step rows read; xbar, fbar, rbar, C written
-        byts = nnz * ew * 4 + (sample.size + 1) * 4 + nd * (M + 1) * 4 + 5 * nd * 8 + nd * M * 8
-        out.append({"ns": int(sample.size), "nnz": nnz, "us": sec * 1e6, "bytes": byts,
-                    "GB_per_s": byts / sec / 1e9, "pairs_per_s": nnz / sec})
+        nc = int(np.asarray(a["Gt"]).size)
+        # algorithmic bytes per evaluation: one 4-byte surrogate id per list
+        # entry, the offsets, each unique surrogate's reference position,
+        # basis rows and circulation (FP32), the sampled rows' basis and
+        # reference positions (FP32), the previous-step rows read and xbar,
+        # fbar, rbar, C written (FP64)
+        byts = 4 * nnz + 4 * (sample.size + 1) + (8 + 8 * M + 4) * nc + 4 * nd * (M + 2) + 5 * nd * 8 + nd * M * 8
+        # what the point form moves: the ids, the FP64 mode-major basis and
+        # reference positions of all P = nd + 2 Nc coordinates, the positions
+        # written (and the targets' read back), the circulations, the packed
+        # 32-byte surrogate records written and read, Phibar (for C), the
+        # inflow rows, the previous-step rows and the outputs
+        P = nd + 2 * nc
+        layout = (4 * nnz + 4 * (sample.size + 1) + 8 * P * (M + 1) + 8 * P + 8 * nd + 4 * nc + 64 * nc
+                  + 4 * nd * M + 8 * nd + 5 * nd * 8 + nd * M * 8)
+        out.append({"ns": int(sample.size), "nnz": nnz, "Nc": nc, "us": sec * 1e6, "bytes": byts,
+                    "GB_per_s": byts / sec / 1e9, "layout_bytes": layout, "layout_GB_per_s": layout / sec / 1e9,
+                    "pairs_per_s": nnz / sec})
         rom.close()
     return out
 

@@ -67,6 +67,8 @@ struct RomDev {
   const double *pt, *p0;
   const int *etg, *eid;
   const float *gt0;
+  double *pos;  // [P] point-form positions of the hook's last evaluation
+  double *spk;  // [Nc][4] the same surrogate positions packed with Gamma~: x, y, Gamma~, 0
   const double *A;              // [Mr][nd]
   // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
   // leading dimension ldc
@@ -369,9 +371,102 @@ __global__ void __launch_bounds__(256)
                       rbar, 1, C, d.M);
 }
 
-// ----------------------------------------------------------- device-resident loop
+// Point form of the hook (paper Jacobian).  First every coordinate of the
+// point form at xhat, in FP64 (one thread per coordinate, mode-major basis,
+// coalesced): the sampled rows xbar = xbar0 + Phibar xhat, then each
+// surrogate's p_c = xqt0_c + Phit_c xhat.  Then one wave per sampled target
+// walks its list reading only the surrogate id (4 bytes per entry; the
+// positions and circulations of the surrogates stay in L2), forms the
+// separation in FP64 and the pair terms in FP32.
+__global__ void __launch_bounds__(256)
+    point_positions_kernel(RomDev d, const double *__restrict__ xhat, double *__restrict__ pos) {
+  __shared__ double xh[kMaxM];
+  if (threadIdx.x < d.M) xh[threadIdx.x] = xhat[threadIdx.x];
+  __syncthreads();
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d.P) return;
+  double v = d.p0[q];
+  for (int m = 0; m < d.M; ++m) v = fma(d.pt[(size_t)m * d.P + q], xh[m], v);
+  pos[q] = v;
+  if (q >= d.nd) {
+    // one 32-byte record per surrogate: a list entry touches one cache line
+    const int c = (q - d.nd) >> 1, k = (q - d.nd) & 1;
+    d.spk[4 * c + k] = v;
+    if (k == 0) {
+      d.spk[4 * c + 2] = (double)d.gt0[c];
+      d.spk[4 * c + 3] = 0.0;
+    }
+  }
+}
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void point_terms(double tx, double ty, const dbl4 p, float d2, GatherAcc<false> &a) {
+  const float rx = float(tx - p.x), ry = float(ty - p.y);
+  const float q = fmaf(rx, rx, fmaf(ry, ry, d2));
+  const float r = q > 0.f ? 1.0f / q : 0.f;  // a surrogate on its target adds nothing
+  const float g = float(p.z) * r;
+  a.fx = fmaf(-ry, g, a.fx);
+  a.fy = fmaf(rx, g, a.fy);
+  const float g2 = g * r;
+  const float a2 = (rx + rx) * ry;
+  const float dd = fmaf(ry, ry, -rx * rx);
+  a.ba = fmaf(g2, a2, a.ba);
+  a.bb = fmaf(g2, dd - d2, a.bb);
+  a.bc = fmaf(g2, dd + d2, a.bc);
+}
+
+__global__ void __launch_bounds__(256)
+    gather_point_kernel(RomDev d, const double *__restrict__ pos, const double *__restrict__ xbar_prev,
+                        const double *__restrict__ fbar_prev, double *xbar, double *fbar, double *rbar, double *C) {
+  const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (t >= d.ns) return;
+  const int ns = d.ns, M = d.M;
+  const double tx = pos[t], ty = pos[ns + t];
+  const dbl4 *sp = reinterpret_cast<const dbl4 *>(d.spk);
+  GatherAcc<false> a;
+  const int e1 = d.off[t + 1];
+  int e = d.off[t] + lane;
+  // four entries in flight per lane: the ids, then the records they name,
+  // are all requested before any is used
+  for (; e + 192 < e1; e += 256) {
+    const int c0 = d.eid[e], c1 = d.eid[e + 64], c2 = d.eid[e + 128], c3 = d.eid[e + 192];
+    const dbl4 p0 = sp[c0], p1 = sp[c1], p2 = sp[c2], p3 = sp[c3];
+    point_terms(tx, ty, p0, d.d2, a);
+    point_terms(tx, ty, p1, d.d2, a);
+    point_terms(tx, ty, p2, d.d2, a);
+    point_terms(tx, ty, p3, d.d2, a);
+  }
+  for (; e < e1; e += 64) point_terms(tx, ty, sp[d.eid[e]], d.d2, a);
+  const double Fx = gsum(a.fx, 64) * kInv2PiD + d.ubar[t];
+  const double Fy = gsum(a.fy, 64) * kInv2PiD + d.ubar[ns + t];
+  const double hdt = 0.5 * (double)d.dt;
+  if (lane == 0) {
+    if (xbar) {
+      xbar[t] = tx;
+      xbar[ns + t] = ty;
+    }
+    if (fbar) {
+      fbar[t] = Fx;
+      fbar[ns + t] = Fy;
+    }
+    if (rbar) {
+      rbar[t] = (tx - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
+      rbar[ns + t] = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+    }
+  }
+  if (C) {
+    const double B00 = gsum(a.ba, 64) * kInv2PiD, B01 = gsum(a.bb, 64) * kInv2PiD, B10 = gsum(a.bc, 64) * kInv2PiD;
+    for (int m = lane; m < M; m += 64) {
+      const double px = d.Phibar[(size_t)t * M + m], py = d.Phibar[(size_t)(ns + t) * M + m];
+      C[(size_t)t * M + m] = px - hdt * (B00 * px + B01 * py);
+      C[(size_t)(ns + t) * M + m] = py - hdt * (B10 * px - B00 * py);
+    }
+  }
+}
+
+// ----------------------------------------------------------- device-resident loop
 
 // One 16 x 16 tile of D = X Y (X: rows x K, Y: K x cols) on one wave with the
 // FP64 matrix-core instruction (16 x 16 x 4 per step): lane l supplies
@@ -1362,7 +1457,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
                           align256(nd * 8), align256(nd * 8), align256(nd * 8),
                           align256(size_t(nd) * ((M + 4) / 4 * 4) * 8), align256(pt.size() * 8),
                           align256(p0.size() * 8), align256(etg.size() * 4), align256(eid.size() * 4),
-                          align256(gt0.size() * 4), align256(ubar.size() * 8)};
+                          align256(gt0.size() * 4), align256(ubar.size() * 8), align256(size_t(P) * 8),
+                          align256(size_t(s.Nc > 0 ? s.Nc : 1) * 32)};
   constexpr int NB = sizeof(bytes) / sizeof(bytes[0]);
   size_t total = 0;
   for (size_t b : bytes) total += b;
@@ -1380,7 +1476,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.A = (double *)ptrs[4]; d.xbar_prev = (double *)ptrs[5]; d.fbar = (double *)ptrs[6];
   d.fbar_prev = (double *)ptrs[7]; d.C = (double *)ptrs[8];
   d.P = int(P); d.pt = (double *)ptrs[9]; d.p0 = (double *)ptrs[10]; d.etg = (int *)ptrs[11];
-  d.eid = (int *)ptrs[12]; d.gt0 = (float *)ptrs[13]; d.ubar = (double *)ptrs[14];
+  d.eid = (int *)ptrs[12]; d.gt0 = (float *)ptrs[13]; d.ubar = (double *)ptrs[14]; d.pos = (double *)ptrs[15];
+  d.spk = (double *)ptrs[16];
   hipError_t e = hipMemcpy(ptrs[0], phibar.data(), phibar.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[1], xbar0.data(), xbar0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[2], ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
@@ -1421,12 +1518,16 @@ extern "C" int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const dou
   hipStream_t st = (hipStream_t)stream;
   const RomDev &d = rom->d;
   const unsigned gg = (unsigned)((d.ns + 3) / 4);
-  if (d.jac_mode == PTROM_JAC_EXACT)
+  if (d.jac_mode == PTROM_JAC_EXACT) {
     hipLaunchKernelGGL(gather_kernel<true>, dim3(gg), dim3(256), 0, st, d, xhat, xbar_prev, fbar_prev, xbar, fbar,
                        rbar, C);
-  else
-    hipLaunchKernelGGL(gather_kernel<false>, dim3(gg), dim3(256), 0, st, d, xhat, xbar_prev, fbar_prev, xbar,
-                       fbar, rbar, C);
+  } else {
+    // point form: positions once per surrogate, 4 bytes per list entry
+    hipLaunchKernelGGL(point_positions_kernel, dim3((unsigned)((d.P + 255) / 256)), dim3(256), 0, st, d, xhat,
+                       d.pos);
+    hipLaunchKernelGGL(gather_point_kernel, dim3(gg), dim3(256), 0, st, d, d.pos, xbar_prev, fbar_prev, xbar, fbar,
+                       rbar, C);
+  }
   PTROM_CHECK_HIP(ctx, hipGetLastError());
   return PTROM_OK;
 }
