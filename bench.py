@@ -279,6 +279,9 @@ def run_forms(native, W, dev, only, plain_pairs_per_s, gather_ns=(16, 256, 2048,
         xb.copy_(xb0)
         sec1 = timed(lambda: native.velocity_batched(bt.offsets, xb, gb, bt.delta), reps=3)
         forms["batched"]["velocity_eval_pairs_per_s"] = pairs_eval / sec1
+        nbar = int(np.sum(nb * nb) / np.sum(nb))
+        forms["batched"]["launch"] = dict(native.pair_config("batched_velocity", nbar), pair_weighted_mean_size=nbar,
+                                          source="tuning table (ptrom_autotune)")
         del xb0, xb, gb
 
     if not only or "adjoint" in only:

@@ -225,10 +225,14 @@ int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const float *gam
  *   offsets (host) [nb+1]: instance b owns bodies offsets[b]..offsets[b+1]-1;
  *   xy: instance b's SoA block [x..., y...] occupies xy[2*offsets[b] .. 2*offsets[b+1]);
  *   gamma[offsets[nb]]; delta (host) [nb] per-instance cores.
- * Every unordered pair of an instance is evaluated once (blocks of 512
- * bodies); EINVAL when the instances hold more than 2^24 block pairs in
- * total (one instance of about 2.9 million bodies).  The workspace holds one
- * slot per block and body: 8 * sum_b ceil(N_b / 512) * N_b bytes.
+ * Every unordered pair of an instance is evaluated once, in blocks of 256 K
+ * bodies, K targets per lane (1, 2 or 4) and the workgroups per CU taken from
+ * the tuning table's "batched_velocity" entry for the instance set's
+ * pair-weighted mean size sum N_b^2 / sum N_b (ptrom_autotune measures it;
+ * default K = 2, 8 per CU).  The workspace holds one slot per block and body:
+ * 8 * sum_b ceil(N_b / (256 K)) * N_b bytes.  EINVAL when the instances hold
+ * more than 2^24 block pairs in total or the slots would pass 1/32 of the
+ * device's memory.
  * ---------------------------------------------------------------------- */
 int ptrom_velocity_batched(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float *xy,
                            const float *gamma, const float *delta, float *f, ptrom_stream stream);
@@ -409,6 +413,8 @@ int ptrom_combine_f64(ptrom_ctx *ctx, int64_t nd, int k, const double *X, int M,
 /* Time the candidate launch configurations of the pair kernels on this
  * device at a set of sizes, keep the fastest per (operation, size class) in
  * the context and, if cache_path is not NULL, write them there (text).
+ * The batched velocity launch is tuned too, on instance sets of equal sizes
+ * 2048, 8192 and 32768.
  * SYNCHRONISES; allocates temporary device buffers. */
 int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path);
 
@@ -422,7 +428,11 @@ enum {
   PTROM_OP_JVP = 2,
   PTROM_OP_VJP = 3,
   PTROM_OP_STREAM_FUNCTION = 4,
-  PTROM_OP_VELOCITY_BLOCK_JACOBIAN = 5
+  PTROM_OP_VELOCITY_BLOCK_JACOBIAN = 5,
+  PTROM_OP_BATCHED_VELOCITY = 6 /* ptrom_pair_config only: the batched launch for
+                                   instance sets whose pair-weighted mean size
+                                   sum N_b^2 / sum N_b is n (out[1] targets per
+                                   lane, out[2] workgroups per CU) */
 };
 
 /* The launch the context would use for operation op at n bodies, written to

@@ -1,7 +1,9 @@
 // Many independent parametric instances (own N_b, own core delta_b) in one
 // persistent launch per velocity evaluation, every unordered pair of an
-// instance evaluated once.  The host cuts every instance into blocks of 512
-// bodies and lists its block pairs (instance, I, J), J >= I, sorted by pair
+// instance evaluated once.  The host cuts every instance into blocks of 256 K
+// bodies (K targets per lane and the workgroups per CU come from the tuning
+// table, keyed by the pair-weighted mean instance size sum N_b^2 / sum N_b)
+// and lists its block pairs (instance, I, J), J >= I, sorted by pair
 // count (largest first), once per instance set; every workgroup then pops
 // items from a device counter until the list is exhausted, so large and
 // small instances share the chip without a tail.  Off-diagonal items run
@@ -21,9 +23,6 @@
 namespace ptrom {
 namespace {
 
-constexpr int kBatchK = 2;                   // targets per lane
-constexpr int kBatchTB = kBlock * kBatchK;   // bodies per block
-constexpr int kBlocksPerCU = 8;
 constexpr int64_t kMaxBatchItems = int64_t(1) << 24;
 constexpr int kNA = Traits<OP_VEL>::NACC;
 
@@ -31,14 +30,17 @@ __global__ void reset_counter_kernel(int *__restrict__ counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
 
-// (at most 64 VGPRs: eight waves per SIMD, as the single-system kernel
-// reaches without the bound)
-__global__ void __launch_bounds__(kBlock, 8)
+// K targets per lane: blocks of 256 K bodies.  K <= 2 keeps the kernel at 64
+// VGPRs or fewer (eight waves per SIMD), as the single-system kernel reaches
+// without the bound.
+template <int K>
+__global__ void __launch_bounds__(kBlock, K <= 2 ? 8 : 1)
     batched_sym_kernel(const int4 *__restrict__ items, int n_items, int *__restrict__ counter,
                        const int *__restrict__ off, const float *__restrict__ d2s,
                        const int64_t *__restrict__ slot_off, const float *__restrict__ xy,
                        const float *__restrict__ gam, float *__restrict__ P) {
   constexpr int NS = Traits<OP_VEL>::NSRC;
+  constexpr int TB = kBlock * K;
   __shared__ float4 s_src[128][2];
   __shared__ float racc_lds[kBlock / 64][kNA][64];
   __shared__ float lds_diag[NS * kTile];
@@ -58,13 +60,12 @@ __global__ void __launch_bounds__(kBlock, 8)
     const float *gb = gam + o;
     float *Pb = P + slot_off[b];
     const float d2 = d2s[b];
-    const int tgt0 = I * kBatchTB;
+    const int tgt0 = I * TB;
     if (I == J) {
-      float res[kBatchK][kNA];
-      pair_block<OP_VEL, kBatchK, STAGE_LDS>(n, xb, gb, nullptr, d2, tgt0, tgt0, min(n, tgt0 + kBatchTB), lds_diag,
-                                              res);
+      float res[K][kNA];
+      pair_block<OP_VEL, K, STAGE_LDS>(n, xb, gb, nullptr, d2, tgt0, tgt0, min(n, tgt0 + TB), lds_diag, res);
 #pragma unroll
-      for (int k = 0; k < kBatchK; ++k) {
+      for (int k = 0; k < K; ++k) {
         const int i = tgt0 + k * kBlock + tid;
         if (i < n)
 #pragma unroll
@@ -72,15 +73,15 @@ __global__ void __launch_bounds__(kBlock, 8)
       }
       continue;
     }
-    sym_block_pair<OP_VEL, kBatchK>(n, xb, gb, nullptr, d2, tgt0, J * kBatchTB, s_src, racc_lds,
-                                    Pb + (size_t)J * kNA * n, Pb + (size_t)I * kNA * n);
+    sym_block_pair<OP_VEL, K>(n, xb, gb, nullptr, d2, tgt0, J * TB, s_src, racc_lds, Pb + (size_t)J * kNA * n,
+                              Pb + (size_t)I * kNA * n);
   }
 }
 
 // Per body: its forward slots B .. nbk-1, then its reaction slots 0 .. B-1,
 // Kahan-compensated, loads issued eight slots at a time.
 __global__ void __launch_bounds__(256)
-    batched_sym_reduce_kernel(int total, const int *__restrict__ inst, const int *__restrict__ off,
+    batched_sym_reduce_kernel(int total, int tb, const int *__restrict__ inst, const int *__restrict__ off,
                               const int64_t *__restrict__ slot_off, const float *__restrict__ P,
                               float *__restrict__ out) {
   constexpr int kB = 8;
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(256)
   const int o = off[b];
   const int n = off[b + 1] - o;
   const int i = g - o;
-  const int B = i / kBatchTB, nbk = (n + kBatchTB - 1) / kBatchTB;
+  const int B = i / tb, nbk = (n + tb - 1) / tb;
   const float *Pb = P + slot_off[b];
   float s[kNA] = {}, c[kNA] = {};
   for (int q0 = 0; q0 < nbk; q0 += kB) {
@@ -120,6 +121,7 @@ __global__ void __launch_bounds__(256)
 struct BatchPlan {
   std::vector<int64_t> offsets;
   std::vector<float> delta;
+  int k = 2, blocks_per_cu = 8;  // targets per lane (blocks of 256 k bodies), workgroups per CU
   int nb = 0, total = 0, n_items = 0;
   size_t slot_floats = 0;  // per-block slots of all instances, sum of nbk_b * 2 * N_b
   void *buf = nullptr;     // items | off | d2 | slot_off | inst | counter
@@ -145,15 +147,20 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
     if (!(delta[b] >= 0.0f) || !std::isfinite(delta[b])) return ctx->fail(PTROM_EINVAL, "delta must be >= 0");
   }
   if (offsets[nb] > kMaxN) return ctx->fail(PTROM_EINVAL, "total bodies must be <= 2^30");
+  const PairCfg cfg = ctx->tune.get_batched(batched_size(nb, offsets));
+  const int kb = cfg.k, bpc = cfg.waves_per_simd;
+  const int64_t tbk = int64_t(kBlock) * kb;
   const auto &cur = ctx->batch_plan;
-  if (cur && cur->nb == nb && std::equal(offsets, offsets + nb + 1, cur->offsets.begin()) &&
-      std::equal(delta, delta + nb, cur->delta.begin())) {
+  if (cur && cur->nb == nb && cur->k == kb && cur->blocks_per_cu == bpc &&
+      std::equal(offsets, offsets + nb + 1, cur->offsets.begin()) && std::equal(delta, delta + nb, cur->delta.begin())) {
     out = cur;
     return PTROM_OK;
   }
   auto p = std::make_shared<BatchPlan>();
   p->offsets.assign(offsets, offsets + nb + 1);
   p->delta.assign(delta, delta + nb);
+  p->k = kb;
+  p->blocks_per_cu = bpc;
   p->nb = nb;
   p->total = int(offsets[nb]);
   struct It {
@@ -165,18 +172,23 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
   std::vector<int64_t> slot_off(nb);
   std::vector<float> d2(nb);
   int64_t n_items = 0;
+  uint64_t slot_bytes = 0;
   for (int b = 0; b < nb; ++b) {
     const int64_t n = offsets[b + 1] - offsets[b];
-    const int64_t nbk = (n + kBatchTB - 1) / kBatchTB;
+    const int64_t nbk = (n + tbk - 1) / tbk;
     n_items += nbk * (nbk + 1) / 2;
+    slot_bytes += uint64_t(nbk) * kNA * uint64_t(n) * sizeof(float);
   }
   if (n_items > kMaxBatchItems)
     return ctx->fail(PTROM_EINVAL, "instances too large for one batched launch (block pairs > 2^24)");
+  if (slot_bytes > ctx->tune.ws_cap_bytes)
+    return ctx->fail(PTROM_EINVAL, "instances too large for one batched launch (block slots of " +
+                                       std::to_string(slot_bytes) + " bytes beyond 1/32 of the device memory)");
   items.reserve(size_t(n_items));
   size_t slots = 0;
   for (int b = 0; b < nb; ++b) {
     const int n = int(offsets[b + 1] - offsets[b]);
-    const int nbk = (n + kBatchTB - 1) / kBatchTB;
+    const int nbk = int((n + tbk - 1) / tbk);
     slot_off[b] = int64_t(slots);
     slots += size_t(nbk) * kNA * size_t(n);
     off32[b] = int(offsets[b]);
@@ -184,8 +196,8 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
     for (int i = int(offsets[b]); i < int(offsets[b + 1]); ++i) inst[i] = b;
     for (int I = 0; I < nbk; ++I)
       for (int J = I; J < nbk; ++J) {
-        const int64_t nt = std::min(kBatchTB, n - I * kBatchTB);
-        const int64_t ns = std::min(kBatchTB, n - J * kBatchTB);
+        const int64_t nt = std::min<int64_t>(tbk, n - I * tbk);
+        const int64_t ns = std::min<int64_t>(tbk, n - J * tbk);
         // one-sided diagonal tile: nt^2 ordered pairs; off-diagonal: nt ns
         // unordered pairs at about 1.5 times the one-sided cost per pair
         items.push_back({make_int4(b, I, J, 0), I == J ? nt * nt : 3 * nt * ns / 2});
@@ -230,11 +242,18 @@ static int get_plan(ptrom_ctx *ctx, int nb, const int64_t *offsets, const float 
 static hipError_t launch_batched_velocity(ptrom_ctx *ctx, const BatchPlan &p, const float *xy,
                                           const float *gamma, float *f, float *slots, hipStream_t st) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, p.counter);
-  const dim3 grid(ctx->num_cus * kBlocksPerCU);
-  hipLaunchKernelGGL(batched_sym_kernel, grid, dim3(kBlock), 0, st, p.items, p.n_items, p.counter, p.off, p.d2,
-                     p.slot_off, xy, gamma, slots);
-  hipLaunchKernelGGL(batched_sym_reduce_kernel, dim3((p.total + 255) / 256), dim3(256), 0, st, p.total, p.inst,
-                     p.off, p.slot_off, slots, f);
+  const dim3 grid(ctx->num_cus * p.blocks_per_cu);
+  if (p.k == 4)
+    hipLaunchKernelGGL(batched_sym_kernel<4>, grid, dim3(kBlock), 0, st, p.items, p.n_items, p.counter, p.off, p.d2,
+                       p.slot_off, xy, gamma, slots);
+  else if (p.k == 1)
+    hipLaunchKernelGGL(batched_sym_kernel<1>, grid, dim3(kBlock), 0, st, p.items, p.n_items, p.counter, p.off, p.d2,
+                       p.slot_off, xy, gamma, slots);
+  else
+    hipLaunchKernelGGL(batched_sym_kernel<2>, grid, dim3(kBlock), 0, st, p.items, p.n_items, p.counter, p.off, p.d2,
+                       p.slot_off, xy, gamma, slots);
+  hipLaunchKernelGGL(batched_sym_reduce_kernel, dim3((p.total + 255) / 256), dim3(256), 0, st, p.total,
+                     kBlock * p.k, p.inst, p.off, p.slot_off, slots, f);
   return hipGetLastError();
 }
 

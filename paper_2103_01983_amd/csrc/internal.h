@@ -48,7 +48,15 @@ struct Tuning {
   uint64_t ws_cap_bytes = uint64_t(8) << 30;  // set per device: its memory / kWsCapDivisor
   PairCfg get(int op, int64_t n) const;
   PairCfg get_table(int op, int64_t n) const;  // the table's entry, without the cap
+  // batched velocity launch (k = targets per lane, waves_per_simd = workgroups
+  // per CU) for instance sets of pair-weighted mean size nbar
+  PairCfg get_batched(int64_t nbar) const;
 };
+
+// tuning-table key of the batched velocity launch ("batched_velocity")
+constexpr int OP_BATCH = OP_COUNT;
+// pair-weighted mean instance size sum N_b^2 / sum N_b (at least 1)
+int64_t batched_size(int nb, const int64_t *offsets);
 
 constexpr uint64_t kWsCapDivisor = 32;
 

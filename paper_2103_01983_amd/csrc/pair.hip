@@ -248,6 +248,25 @@ PairCfg Tuning::get(int op, int64_t n) const {
   return c;
 }
 
+PairCfg Tuning::get_batched(int64_t nbar) const {
+  // nearest tuned class; without any batched entry K = 2, 8 workgroups per CU
+  PairCfg c = get_table(OP_BATCH, nbar);
+  c.staging = STAGE_LDS;
+  c.sym = 1;
+  return c;
+}
+
+int64_t batched_size(int nb, const int64_t *offsets) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double n = double(offsets[b + 1] - offsets[b]);
+    s1 += n;
+    s2 += n * n;
+  }
+  const double v = s1 > 0.0 ? s2 / s1 : 1.0;
+  return v < 1.0 ? 1 : int64_t(v);
+}
+
 PairCfg Tuning::get_table(int op, int64_t n) const {
   const int cls = size_class(n);
   const PairCfg *best = nullptr;

@@ -15,6 +15,7 @@ using namespace ptrom;
 
 static const char *kOpNames[OP_COUNT] = {"velocity", "block_jacobian", "jvp", "vjp", "stream_function",
                                          "velocity_block_jacobian"};
+static const char *kBatchName = "batched_velocity";
 
 // Reads a tuning file into t; returns the number of entries loaded (-1 if the
 // file cannot be opened).
@@ -34,6 +35,7 @@ static int read_tuning(const char *path, Tuning &t) {
     int op = -1;
     for (int q = 0; q < OP_COUNT; ++q)
       if (name == kOpNames[q]) op = q;
+    if (name == kBatchName) op = OP_BATCH;
     if (op < 0 || (k != 1 && k != 2 && k != 4) || (staging != STAGE_LDS && staging != STAGE_SCALAR) ||
         waves < 1 || waves > 64)
       continue;
@@ -42,7 +44,7 @@ static int read_tuning(const char *path, Tuning &t) {
     c.staging = staging;
     c.k = k;
     c.waves_per_simd = waves;
-    c.sym = has_sym(op) ? sym : 0;
+    c.sym = (op == OP_BATCH || has_sym(op)) ? sym : 0;
     t.table[{op, cls}] = c;
     ++loaded;
   }
@@ -54,6 +56,99 @@ extern "C" int ptrom_load_tuning(ptrom_ctx *ctx, const char *path) {
   const int loaded = read_tuning(path, ctx->tune);
   if (loaded < 0) return ctx->fail(PTROM_EINVAL, std::string("cannot open ") + path);
   return loaded ? PTROM_OK : ctx->fail(PTROM_EINVAL, "no tuning entries");
+}
+
+// Batched velocity launch: targets per lane (blocks of 256 K bodies) and
+// workgroups per CU, timed on instance sets of equal sizes 2048, 8192 and
+// 32768 (262144 bodies each) and on 24 instances log-spaced from 2048 to
+// 32768 bodies, keyed by the class of the pair-weighted mean size.
+static int tune_batched(ptrom_ctx *ctx, std::ostringstream &report) {
+  std::vector<std::vector<int64_t>> sets;
+  for (int64_t m : {int64_t(2048), int64_t(8192), int64_t(32768)}) sets.push_back(std::vector<int64_t>(262144 / m, m));
+  {
+    std::vector<int64_t> mix;
+    for (int q = 0; q < 24; ++q) mix.push_back(int64_t(std::llround(2048.0 * std::pow(16.0, q / 23.0))));
+    sets.push_back(mix);
+  }
+  int64_t total = 0;
+  for (auto &v : sets) {
+    int64_t t = 0;
+    for (int64_t m : v) t += m;
+    total = std::max(total, t);
+  }
+  std::vector<float> h(3 * total);
+  float *d = nullptr, *f = nullptr;
+  PTROM_CHECK_HIP(ctx, hipMalloc(&d, 3 * total * sizeof(float)));
+  hipError_t e = hipMalloc(&f, 2 * total * sizeof(float));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  int rc = PTROM_OK;
+  for (const auto &sizes : sets) {
+    if (e != hipSuccess || rc) break;
+    const int nb = int(sizes.size());
+    std::vector<int64_t> off(nb + 1, 0);
+    std::vector<float> delta(nb);
+    for (int q = 0; q < nb; ++q) off[q + 1] = off[q] + sizes[q];
+    const int64_t tot = off[nb];
+    for (int q = 0; q < nb; ++q) {
+      const int64_t m = sizes[q];
+      delta[q] = 0.005f + 0.045f * float(q) / float(nb);
+      for (int64_t i = 0; i < m; ++i) {
+        // golden-angle spiral per instance (x block, y block, then Gamma)
+        const double t = 2.399963229728653 * double(i) + 0.7 * q;
+        const double rr = 0.25 * std::sqrt((i + 0.5) / double(m));
+        h[2 * off[q] + i] = float(rr * std::cos(t));
+        h[2 * off[q] + m + i] = float(rr * std::sin(t));
+        h[2 * tot + off[q] + i] = float(1.0 / double(m));
+      }
+    }
+    e = hipMemcpy(d, h.data(), 3 * tot * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) break;
+    const int64_t nb_size = batched_size(nb, off.data());
+    const int cls = size_class(nb_size);
+    float best = 1e30f;
+    PairCfg bestc;
+    for (int k : {1, 2, 4})
+      for (int bpc : {4, 8, 16}) {
+        PairCfg c;
+        c.staging = STAGE_LDS;
+        c.k = k;
+        c.waves_per_simd = bpc;
+        c.sym = 1;
+        ctx->tune.table[{OP_BATCH, cls}] = c;
+        for (int rep = 0; rep < 2 && !rc; ++rep)
+          rc = ptrom_velocity_batched(ctx, nb, off.data(), d, d + 2 * tot, delta.data(), f, nullptr);
+        if (rc) break;
+        const int reps = 3;
+        e = hipEventRecord(a, nullptr);
+        for (int rep = 0; rep < reps && !rc && e == hipSuccess; ++rep)
+          rc = ptrom_velocity_batched(ctx, nb, off.data(), d, d + 2 * tot, delta.data(), f, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess || rc) break;
+        ms /= reps;
+        if (ms < best) {
+          best = ms;
+          bestc = c;
+        }
+      }
+    if (e != hipSuccess || rc) break;
+    ctx->tune.table[{OP_BATCH, cls}] = bestc;
+    report << kBatchName << " " << cls << " " << bestc.staging << " " << bestc.k << " " << bestc.waves_per_simd
+           << " " << bestc.sym << "   # " << best << " ms at " << nb << " instances, pair-weighted mean size "
+           << nb_size << "\n";
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  hipFree(d);
+  hipFree(f);
+  ctx->batch_plan.reset();
+  if (rc) return rc;
+  if (e != hipSuccess) return ctx->hip_fail(e, "autotune (batched)");
+  return PTROM_OK;
 }
 
 extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
@@ -149,6 +244,7 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
   hipFree(o2);
   hipFree(wsb);
   if (e != hipSuccess) return ctx->hip_fail(e, "autotune");
+  if (int rc = tune_batched(ctx, report)) return rc;
   if (cache_path) {
     std::ofstream out(cache_path);
     if (!out) return ctx->fail(PTROM_EINVAL, std::string("cannot write ") + cache_path);
@@ -167,7 +263,16 @@ static void describe(const PairCfg &c, int op, int num_cus, int64_t n, int32_t *
 }
 
 extern "C" int ptrom_pair_config(ptrom_ctx *ctx, int op, int64_t n, int32_t *out) {
-  if (!ctx || !out || op < 0 || op >= OP_COUNT || n < 1 || n > kMaxN) return PTROM_EINVAL;
+  if (!ctx || !out || op < 0 || op > OP_BATCH || n < 1 || n > kMaxN) return PTROM_EINVAL;
+  if (op == OP_BATCH) {
+    const PairCfg c = ctx->tune.get_batched(n);
+    out[0] = c.staging;
+    out[1] = c.k;
+    out[2] = c.waves_per_simd;
+    out[3] = 1;
+    out[4] = 0;
+    return PTROM_OK;
+  }
   describe(ctx->tune.get(op, n), op, ctx->num_cus, n, out);
   return PTROM_OK;
 }

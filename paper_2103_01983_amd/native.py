@@ -364,13 +364,13 @@ def _host_f32(a):
     return a, a.ctypes.data_as(_vp)
 
 
-def velocity_batched(offsets, xy, gamma, delta, out=None):
+def velocity_batched(offsets, xy, gamma, delta, out=None, ctx=None):
     off, poff = _host_i64(offsets)
     dl, pdl = _host_f32(delta)
     nb = off.size - 1
     tot = int(off[-1])
     out = torch.empty_like(xy) if out is None else out
-    c = context(xy.device)
+    c = context(xy.device) if ctx is None else ctx
     _check(c, lib().ptrom_velocity_batched(c, nb, poff, _ptr(xy, torch.float32, 2 * tot, "xy"),
                                            _ptr(gamma, torch.float32, tot, "gamma"), pdl,
                                            _ptr(out, torch.float32, 2 * tot, "out"), _stream(xy)),
@@ -378,12 +378,12 @@ def velocity_batched(offsets, xy, gamma, delta, out=None):
     return out
 
 
-def rk4_batched(offsets, xy, gamma, delta, dt, nsteps, use_graph=True):
+def rk4_batched(offsets, xy, gamma, delta, dt, nsteps, use_graph=True, ctx=None):
     off, poff = _host_i64(offsets)
     dl, pdl = _host_f32(delta)
     nb = off.size - 1
     tot = int(off[-1])
-    c = context(xy.device)
+    c = context(xy.device) if ctx is None else ctx
     _check(c, lib().ptrom_rk4_batched(c, nb, poff, _ptr(xy, torch.float32, 2 * tot, "xy"),
                                       _ptr(gamma, torch.float32, tot, "gamma"), pdl, float(dt), int(nsteps),
                                       int(bool(use_graph)), _stream(xy)), "ptrom_rk4_batched")
@@ -614,6 +614,8 @@ def load_tuning(cache_path, device=None):
 
 PAIR_OPS = {"velocity": 0, "block_jacobian": 1, "jvp": 2, "vjp": 3, "stream_function": 4,
             "velocity_block_jacobian": 5}
+# tuning-table entry of the batched velocity launch (ptrom_pair_config key 6)
+BATCHED_OP = ("batched_velocity", 6)
 
 
 def pair_config(op, n, device=None, ctx=None):
@@ -621,7 +623,8 @@ def pair_config(op, n, device=None, ctx=None):
     PAIR_OPS) at n bodies: dict(staging, k, waves_per_simd, sym, splits)."""
     c = context(device) if ctx is None else ctx
     out = (ctypes.c_int32 * 5)()
-    _check(c, lib().ptrom_pair_config(c, PAIR_OPS[op], int(n), out), "ptrom_pair_config")
+    code = BATCHED_OP[1] if op == BATCHED_OP[0] else PAIR_OPS[op]
+    _check(c, lib().ptrom_pair_config(c, code, int(n), out), "ptrom_pair_config")
     return dict(staging=int(out[0]), k=int(out[1]), waves_per_simd=int(out[2]), sym=int(out[3]),
                 splits=int(out[4]))
 

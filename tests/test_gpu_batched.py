@@ -1,5 +1,9 @@
 """GPU parity of the batched persistent stepper (many instances with their own
-N_b and delta_b) against the FP64 oracle run instance by instance."""
+N_b and delta_b) against the FP64 oracle run instance by instance, in every
+launch the autotuner can choose (targets per lane, workgroups per CU)."""
+import os
+import tempfile
+
 import numpy as np
 import pytest
 import torch
@@ -38,6 +42,65 @@ def inst(off, xy, g, b):
 
 
 SIZES = [1, 2, 300, 513, 2049, 257]
+
+# targets per lane, workgroups per CU
+LAUNCHES = [(1, 16), (2, 8), (4, 4)]
+
+
+@pytest.fixture(scope="module", params=LAUNCHES, ids=lambda v: "k%d_bpc%d" % v)
+def bctx(request, dev):
+    k, bpc = request.param
+    fd, path = tempfile.mkstemp(suffix=".txt")
+    with os.fdopen(fd, "w") as fh:
+        fh.write("batched_velocity 13 0 %d %d 1\n" % (k, bpc))
+    h = native.make_context(0, path)
+    os.unlink(path)
+    cfg = native.pair_config("batched_velocity", 4096, ctx=h)
+    assert (cfg["k"], cfg["waves_per_simd"]) == (k, bpc)
+    yield h
+    native.destroy_context(h)
+
+
+def test_batched_velocity_launches(dev, bctx):
+    off, xy, g, dl = small_batch(SIZES, 13)
+    f = native.velocity_batched(off, torch.tensor(xy, dtype=torch.float32, device=dev),
+                                torch.tensor(g, dtype=torch.float32, device=dev), dl, ctx=bctx).cpu().numpy()
+    for b in range(len(SIZES)):
+        x, gg = inst(off, xy, g, b)
+        fb = f[2 * off[b]:2 * off[b + 1]]
+        if SIZES[b] == 1:
+            assert np.all(fb == 0)
+            continue
+        assert rel(fb, oracle.velocity(x, gg, float(dl[b]))) <= 1e-5, b
+    # the graph-captured RK4 of the same launch
+    x = torch.tensor(xy, dtype=torch.float32, device=dev)
+    dl2 = dl.copy()
+    dl2[0] = 0.01
+    native.rk4_batched(off, x, torch.tensor(g, dtype=torch.float32, device=dev), dl2, 1e-3, 2, ctx=bctx)
+    xs = x.cpu().numpy()
+    for b in range(1, len(SIZES)):
+        x0, gg = inst(off, xy, g, b)
+        o = oracle.rk4(x0, gg, float(dl2[b]), float(np.float32(1e-3)), 2)
+        xb = xs[2 * off[b]:2 * off[b + 1]]
+        assert rel(xb - x0, o - x0) <= 1e-4, b
+
+
+def test_batched_full_config_launches(dev, bctx):
+    # the 256-instance set in each launch: sampled velocities of the largest
+    # instances against the oracle
+    bt = W.batched_patches()
+    off = bt.offsets
+    xy, g, dl = f32(bt.xy), f32(bt.gamma), np.float32(bt.delta)
+    f = native.velocity_batched(off, torch.tensor(xy, dtype=torch.float32, device=dev),
+                                torch.tensor(g, dtype=torch.float32, device=dev), dl, ctx=bctx).cpu().numpy()
+    nb = np.diff(off)
+    rng = np.random.default_rng(1)
+    for b in list(np.argsort(nb)[-2:]) + [7]:
+        x, gg = inst(off, xy, g, b)
+        n = int(nb[b])
+        idx = rng.choice(n, 32, replace=False)
+        fb = f[2 * off[b]:2 * off[b + 1]]
+        assert rel(np.concatenate([fb[idx], fb[n + idx]]), oracle.velocity_at(x, gg, float(dl[b]), idx)) <= 1e-5
 
 
 def test_batched_velocity_parity(dev):

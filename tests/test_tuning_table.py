@@ -1,5 +1,6 @@
 """The launch table shipped with the package (measured on MI355X) covers every
-pair operation at every size class with launches the library accepts."""
+pair operation at every size class, and the batched launch at its three
+classes, with launches the library accepts."""
 from paper_2103_01983_amd import native
 
 
@@ -10,7 +11,7 @@ def test_shipped_table_covers_every_operation():
         if not line:
             continue
         op, cls, staging, k, waves, sym = line[0], *map(int, line[1:6])
-        assert op in native.PAIR_OPS, op
+        assert op in native.PAIR_OPS or op == native.BATCHED_OP[0], op
         assert staging in (0, 1) and k in (1, 2, 4) and waves in (2, 4, 8, 16) and sym in (0, 1), line
         # the stream function has no each-pair-once form
         assert not (op == "stream_function" and sym), line
@@ -18,3 +19,5 @@ def test_shipped_table_covers_every_operation():
     for op in native.PAIR_OPS:
         for cls in (11, 13, 15, 16, 17):
             assert (op, cls) in rows, (op, cls)
+    for cls in (11, 13, 14, 15):
+        assert rows[(native.BATCHED_OP[0], cls)][3] == 1
