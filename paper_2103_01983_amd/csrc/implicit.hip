@@ -10,9 +10,12 @@
 // 2x2 blocks (I - dt beta0 B_i) d_i = -r_i, the blocks coming from the same
 // pair pass as the velocity (fused velocity + block-Jacobian operation).
 // For vectors of up to 16384 entries the residual and its norm are one
-// kernel, so each Newton iteration waits for one host round trip.
+// kernel.  With GMRES each Newton iteration waits for one host round trip
+// (and each Arnoldi step for one more); with the block model the convergence
+// test runs on the device and the host waits about once per step.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "internal.h"
@@ -70,15 +73,49 @@ __global__ void __launch_bounds__(64)
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// Newton state of the current step on the device (block model): the squared
+// norms of the first and latest residuals, the Newton iterations done, and
+// done = 1 (converged) or 2 (iteration cap hit), 0 while iterating.  The
+// host issues several iterations without waiting; an iteration issued after
+// the step has finished changes nothing.
+struct NewtonDev {
+  double r0sq, rnsq, it, done;
+};
+
+// Update of the state from the latest residual's squared norm s (one thread):
+// the first residual sets r0; converged when |r| <= tol |r0| or r0 = 0;
+// otherwise the cap, otherwise one more iteration follows.
+__device__ __forceinline__ void newton_update(NewtonDev *st, double s, double tol, int max_newton) {
+  if (st->done != 0.0) return;
+  if (st->r0sq < 0.0) st->r0sq = s;
+  st->rnsq = s;
+  if (st->r0sq == 0.0 || std::sqrt(s) <= tol * std::sqrt(st->r0sq))
+    st->done = 1.0;
+  else if (st->it >= double(max_newton))
+    st->done = 2.0;
+  else
+    st->it += 1.0;
+}
+
+__global__ void newton_state_kernel(NewtonDev *st, const double *__restrict__ s, double tol, int max_newton) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) newton_update(st, s[0], tol, max_newton);
+}
+
+__global__ void newton_reset_kernel(NewtonDev *st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *st = NewtonDev{-1.0, 0.0, 0.0, 0.0};
+}
+
 // The paper's inexact Newton correction: per body, solve
 // (I - c B_i) d_i = -r_i with B_i = [B0 B1; B2 B3] (layout [4][n]) by
 // Cramer's rule in FP64, add d_i to the increment D and form the next
-// iterate xi = x_prev + D.
+// iterate xi = x_prev + D.  With a device state, nothing changes once the
+// step has finished.
 __global__ void block_solve_kernel(int64_t n, float *__restrict__ D, float *__restrict__ xi,
                                    const float *__restrict__ xprev, const float *__restrict__ r,
-                                   const float *__restrict__ B, float c) {
+                                   const float *__restrict__ B, float c, const NewtonDev *__restrict__ st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (st && st->done != 0.0) return;
   const double cc = c;
   const double a00 = 1.0 - cc * B[i], a01 = -cc * B[n + i];
   const double a10 = -cc * B[2 * n + i], a11 = 1.0 - cc * B[3 * n + i];
@@ -190,7 +227,7 @@ __global__ void __launch_bounds__(kGSThreads)
 __global__ void __launch_bounds__(256)
     residual_norm_kernel(int64_t m, float *__restrict__ r, const float *__restrict__ D, const float *__restrict__ f,
                          const float *__restrict__ fp, float dtb0, float dtb1, const float *__restrict__ u, float dtu,
-                         double *__restrict__ out) {
+                         double *__restrict__ out, NewtonDev *st, double tol, int max_newton) {
   __shared__ double red[256];
   double s = 0.0;
   for (int64_t q = threadIdx.x; q < m; q += 256) {
@@ -204,7 +241,58 @@ __global__ void __launch_bounds__(256)
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    if (st) newton_update(st, red[0], tol, max_newton);
+  }
+}
+
+// One whole block-Newton iteration for short vectors (m <= kShortDot), in
+// one workgroup: the residual and its squared norm (as residual_norm_kernel),
+// the device state update, then, unless the step has finished, every body's
+// 2x2 correction (as block_solve_kernel).
+__global__ void __launch_bounds__(256)
+    block_newton_kernel(int64_t n, float *__restrict__ r, float *__restrict__ D, float *__restrict__ xi,
+                        const float *__restrict__ xprev, const float *__restrict__ f, const float *__restrict__ fp,
+                        const float *__restrict__ B, float dtb0, float dtb1, const float *__restrict__ u, float dtu,
+                        NewtonDev *st, double tol, int max_newton) {
+  __shared__ double red[256];
+  __shared__ int proceed;
+  const int64_t m = 2 * n;
+  if (threadIdx.x == 0) proceed = st->done == 0.0;
+  __syncthreads();
+  if (!proceed) return;
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += 256) {
+    const float v = D[q] - (dtb0 * f[q] + dtb1 * fp[q] + (u ? dtu * u[q] : 0.0f));
+    r[q] = v;
+    s += (double)v * (double)v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    newton_update(st, red[0], tol, max_newton);
+    proceed = st->done == 0.0;
+  }
+  __syncthreads();
+  if (!proceed) return;
+  const double cc = dtb0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double a00 = 1.0 - cc * B[i], a01 = -cc * B[n + i];
+    const double a10 = -cc * B[2 * n + i], a11 = 1.0 - cc * B[3 * n + i];
+    const double det = a00 * a11 - a01 * a10;
+    const double bx = -(double)r[i], by = -(double)r[n + i];
+    const float dx = (float)((double)D[i] + (bx * a11 - a01 * by) / det);
+    const float dy = (float)((double)D[n + i] + (a00 * by - a10 * bx) / det);
+    D[i] = dx;
+    D[n + i] = dy;
+    xi[i] = xprev[i] + dx;
+    xi[n + i] = xprev[n + i] + dy;
+  }
 }
 
 // y -= sum_v c[v] X_v  (c on the device), or y = scale * y + sum_v c[v] X_v when accumulate.
@@ -286,13 +374,28 @@ struct Solver {
   int residual(float *r, const float *D, const float *f, const float *fp, float dtb0, float dtb1, const float *u,
                float dtu, double *out) {
     if (m <= kShortDot) {
-      hipLaunchKernelGGL(residual_norm_kernel, dim3(1), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu, dd);
+      hipLaunchKernelGGL(residual_norm_kernel, dim3(1), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu, dd,
+                         nullptr, 0.0, 0);
       if (int rc = fetch(dd, hp, 1)) return rc;
       *out = std::sqrt(hp[0]);
       return PTROM_OK;
     }
     hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu);
     return norm(r, out);
+  }
+
+  // The residual, its squared norm and the device Newton state update, with
+  // no host wait.
+  void residual_state(float *r, const float *D, const float *f, const float *fp, float dtb0, float dtb1,
+                      const float *u, float dtu, NewtonDev *ns, double tol, int max_newton) {
+    if (m <= kShortDot) {
+      hipLaunchKernelGGL(residual_norm_kernel, dim3(1), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu, dd, ns,
+                         tol, max_newton);
+      return;
+    }
+    hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu);
+    dots(r, 1, r, dd);
+    hipLaunchKernelGGL(newton_state_kernel, dim3(1), dim3(64), 0, st, ns, dd, tol, max_newton);
   }
 
   // Solve (I - c J) d = b from d = 0 to relative tolerance rtol; returns
@@ -413,7 +516,8 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   const int R = o.gmres_restart;
   const size_t vb = align256(m * sizeof(float));
   const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (3 * R + 4)) +
-                      align256(sizeof(double) * (R + 2) * kDotParts) + align256(4 * n * sizeof(float)) + 1024;
+                      align256(sizeof(double) * (R + 2) * kDotParts) + align256(4 * n * sizeof(float)) +
+                      align256(sizeof(NewtonDev)) + 1024;
   if (int rc = ctx->reserve(need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
   float *xprev = cv.take<float>(m), *D = cv.take<float>(m), *xi = cv.take<float>(m);
@@ -424,8 +528,9 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   double *dd = cv.take<double>(3 * R + 4);
   double *dpart = cv.take<double>(size_t(R + 2) * kDotParts);
   float *Bj = cv.take<float>(4 * n);
-  if (!w || !V || !pws || !dd || !dpart || !Bj) return ctx->fail(PTROM_ENOMEM, "workspace carve");
-  double *hp = ctx->pinned_doubles(3 * R + 4);
+  NewtonDev *nst = cv.take<NewtonDev>(1);
+  if (!w || !V || !pws || !dd || !dpart || !Bj || !nst) return ctx->fail(PTROM_ENOMEM, "workspace carve");
+  double *hp = ctx->pinned_doubles(3 * R + 8);  // GMRES scalars, then the Newton state
   if (!hp) return ctx->fail(PTROM_ENOMEM, "pinned host scratch");
   hipStream_t st = (hipStream_t)stream;
   Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hp, dpart, R};
@@ -438,18 +543,55 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
                                               pws, pwsf, st);
     return e == hipSuccess ? PTROM_OK : ctx->hip_fail(e, blocks ? "velocity and block jacobian" : "velocity");
   };
-  for (int step = 0; step < nsteps; ++step) {
+  // Block model: the convergence test runs on the device, and the host issues
+  // as many Newton iterations as the previous step needed (plus the final
+  // residual) before it reads the state once; iterations issued beyond the
+  // step's end change nothing.
+  int predicted = 2;
+  for (int step = 0; block && step < nsteps; ++step) {
     hipLaunchKernelGGL(step_start_kernel, g1(m), dim3(256), 0, st, m, xprev, D, xi, xy);
-    // blocks at the first iterate x_prev: every step, or every jac_period-th
-    const bool refresh = block && (o.jac_period == 0 || step % o.jac_period == 0);
+    hipLaunchKernelGGL(newton_reset_kernel, dim3(1), dim3(64), 0, st, nst);
+    const bool refresh = o.jac_period == 0 || step % o.jac_period == 0;
     if (int rc = rhs(xprev, fp, refresh)) return rc;
+    int issued = 0;
+    NewtonDev hs{};
+    for (;;) {
+      const int batch = issued == 0 ? predicted : std::max(1, predicted / 4);
+      for (int q = 0; q < batch && issued <= o.max_newton; ++q, ++issued) {
+        if (issued > 0)
+          if (int rc = rhs(xi, f, o.jac_period == 0)) return rc;
+        const float *fc = issued == 0 ? fp : f;
+        if (m <= kShortDot) {
+          hipLaunchKernelGGL(block_newton_kernel, dim3(1), dim3(256), 0, st, n, r, D, xi, xprev, fc, fp, Bj, dt * b0,
+                             dt * b1, uinf, dt * (b0 + b1), nst, o.newton_tol, o.max_newton);
+          continue;
+        }
+        S.residual_state(r, D, fc, fp, dt * b0, dt * b1, uinf, dt * (b0 + b1), nst, o.newton_tol, o.max_newton);
+        hipLaunchKernelGGL(block_solve_kernel, g1(n), dim3(256), 0, st, n, D, xi, xprev, r, Bj, dt * b0, nst);
+      }
+      double *hst = ctx->pinned_doubles(3 * R + 8) + (3 * R + 4);
+      PTROM_CHECK_HIP(ctx, hipMemcpyAsync(hst, nst, sizeof(NewtonDev), hipMemcpyDeviceToHost, st));
+      PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
+      std::memcpy(&hs, hst, sizeof(NewtonDev));
+      if (hs.done != 0.0 || issued > o.max_newton) break;
+    }
+    const int it = int(hs.it);
+    if (hs.done != 1.0) stl.nonconverged_steps++;
+    stl.newton_iters += it;
+    const double rel = hs.r0sq > 0.0 ? std::sqrt(hs.rnsq / hs.r0sq) : 0.0;
+    if (rel > stl.max_final_rel_residual) stl.max_final_rel_residual = rel;
+    predicted = it + 1;
+    hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xy, xprev, D);
+  }
+  for (int step = 0; !block && step < nsteps; ++step) {
+    hipLaunchKernelGGL(step_start_kernel, g1(m), dim3(256), 0, st, m, xprev, D, xi, xy);
+    if (int rc = rhs(xprev, fp, false)) return rc;
     double r0 = -1.0, rn = 0.0;
     int it = 0;
     for (;; ++it) {
       if (it > 0) {
-        // xi = x_prev + D (the block solve forms it itself)
-        if (!block) hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xi, xprev, D);
-        if (int rc = rhs(xi, f, block && o.jac_period == 0)) return rc;
+        hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xi, xprev, D);  // xi = x_prev + D
+        if (int rc = rhs(xi, f, false)) return rc;
       }
       if (int rc = S.residual(r, D, it == 0 ? fp : f, fp, dt * b0, dt * b1, uinf, dt * (b0 + b1), &rn)) return rc;
       if (r0 < 0.0) r0 = rn;
@@ -457,10 +599,6 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
       if (it >= o.max_newton) {
         stl.nonconverged_steps++;
         break;
-      }
-      if (block) {
-        hipLaunchKernelGGL(block_solve_kernel, g1(n), dim3(256), 0, st, n, D, xi, xprev, r, Bj, dt * b0);
-        continue;
       }
       hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, r, r, -1.0f);
       int used = 0;
