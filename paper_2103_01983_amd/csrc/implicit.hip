@@ -4,15 +4,16 @@
 // difference out of FP32 cancellation), each Newton system
 // (I - dt beta0 J(xi)) d = -r solved by restarted GMRES whose matrix-vector
 // products are the Jacobian-product pair kernel.  Krylov vectors live in
-// HBM (FP32); dot products accumulate in FP64 on the device; the small
-// Hessenberg least-squares problem is solved on the host in FP64.  With
+// HBM (FP32); dot products accumulate in FP64 on the device, and so does the
+// small Hessenberg least-squares problem (Givens rotations, back
+// substitution).  With
 // the paper's inexact Jacobian the Newton systems are instead the per-body
 // 2x2 blocks (I - dt beta0 B_i) d_i = -r_i, the blocks coming from the same
 // pair pass as the velocity (fused velocity + block-Jacobian operation).
 // For vectors of up to 16384 entries the residual and its norm are one
-// kernel.  With GMRES each Newton iteration waits for one host round trip
-// (and each Arnoldi step for one more); with the block model the convergence
-// test runs on the device and the host waits about once per step.
+// kernel.  The Newton convergence test runs on the device; the host waits
+// about once per Newton iteration with GMRES (when the Arnoldi steps it issued
+// were enough) and about once per step with the block model.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -177,15 +178,44 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int kFusedGS = 12288;
 constexpr int kGSThreads = 1024;
 
+// GMRES state on the device: |b| of the Newton system, the current cycle's
+// initial residual norm beta, the Arnoldi columns formed in this cycle and
+// done = 1 once the cycle meets the tolerance (or the Krylov space is
+// exhausted).  The Hessenberg matrix, the Givens rotations and the
+// right-hand side g live next to it in device memory.
+struct GmresDev {
+  double bn, beta, kdone, done;
+};
+
+__device__ __forceinline__ bool gmres_idle(const NewtonDev *ns, const GmresDev *gs) {
+  return (ns && ns->done != 0.0) || gs->done != 0.0;
+}
+
+// One whole Arnoldi step for short vectors (m <= kFusedGS), in one workgroup
+// with w held in LDS: w = v_k - c Jv_k (Jv_k from the Jacobian-product
+// kernel), classical Gram-Schmidt against V_0 .. V_k applied twice (the two
+// coefficient sets to c1[0, k] and c2[0, k], |w|^2 to c2[k + 1]),
+// V_{k+1} = w / |w| when |w| > 0, then the Hessenberg column, its Givens
+// rotation and the convergence test (as arnoldi_kernel).  Dot products are
+// FP64 (per-lane strided partials, then a butterfly over the wave); the
+// update of each element adds the projections in vector order.
+__device__ void arnoldi_column(int k, int R, GmresDev *gs, double *__restrict__ H, double *__restrict__ cs,
+                               double *__restrict__ sn, double *__restrict__ g, const double *c1, const double *c2,
+                               double hn2, double rtol);
+
 __global__ void __launch_bounds__(kGSThreads)
-    gs_fused_kernel(int m, int k, float *__restrict__ V, const float *__restrict__ w,
-                    double *__restrict__ c1, double *__restrict__ c2) {
+    gs_fused_kernel(int m, int k, float *__restrict__ V, const float *__restrict__ jv, float c,
+                    double *__restrict__ c1, double *__restrict__ c2, const NewtonDev *ns, GmresDev *gsd, int R,
+                    double *__restrict__ H, double *__restrict__ gcs, double *__restrict__ gsn, double *__restrict__ gg,
+                    double rtol) {
   constexpr int NW = kGSThreads / 64;
   __shared__ float wl[kFusedGS];
-  __shared__ double cs[kMaxRestart + 1];
+  __shared__ double cs[2][kMaxRestart + 1];
   __shared__ double red[NW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int q = tid; q < m; q += kGSThreads) wl[q] = w[q];
+  if (gmres_idle(ns, gsd)) return;
+  const float *vk = V + (size_t)k * m;
+  for (int q = tid; q < m; q += kGSThreads) wl[q] = vk[q] - c * jv[q];
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
     double *cout = pass ? c2 : c1;
@@ -195,14 +225,14 @@ __global__ void __launch_bounds__(kGSThreads)
       for (int q = lane; q < m; q += 64) s += (double)x[q] * (double)wl[q];
       s = wave_sum(s);
       if (lane == 0) {
-        cs[v] = s;
+        cs[pass][v] = s;
         cout[v] = s;
       }
     }
     __syncthreads();
     for (int q = tid; q < m; q += kGSThreads) {
       double s = 0.0;
-      for (int v = 0; v <= k; ++v) s += cs[v] * (double)V[(size_t)v * m + q];
+      for (int v = 0; v <= k; ++v) s += cs[pass][v] * (double)V[(size_t)v * m + q];
       wl[q] = (float)((double)wl[q] - s);
     }
     __syncthreads();
@@ -214,7 +244,10 @@ __global__ void __launch_bounds__(kGSThreads)
   __syncthreads();
   double nn = 0.0;
   for (int i = 0; i < NW; ++i) nn += red[i];
-  if (tid == 0) c2[k + 1] = nn;
+  if (tid == 0) {
+    c2[k + 1] = nn;
+    arnoldi_column(k, R, gsd, H, gcs, gsn, gg, cs[0], cs[1], nn, rtol);
+  }
   if (nn > 0.0) {
     const float a = float(1.0 / sqrt(nn));
     float *out = V + (size_t)(k + 1) * m;
@@ -316,12 +349,99 @@ __global__ void lincomb_kernel(int64_t m, float *__restrict__ out, const float *
   if (q < m) out[q] = v[q] - c * w[q];
 }
 
+// Start of a GMRES cycle: beta = sqrt(sq[0]); the first cycle also takes
+// |b| = beta.  A later cycle is done at once when beta <= rtol |b|.
+__global__ void gmres_init_kernel(GmresDev *gs, double *__restrict__ g, int R, const double *__restrict__ sq,
+                                  int first, double rtol, const NewtonDev *ns) {
+  if (threadIdx.x != 0 || (ns && ns->done != 0.0)) return;
+  const double beta = std::sqrt(sq[0]);
+  if (first) gs->bn = beta;
+  gs->beta = beta;
+  gs->kdone = 0.0;
+  gs->done = (beta == 0.0 || (!first && beta <= rtol * gs->bn)) ? 1.0 : 0.0;
+  g[0] = beta;
+  for (int i = 1; i <= R; ++i) g[i] = 0.0;
+}
+
+// out = in / beta (V_0 of a cycle)
+__global__ void scale_beta_kernel(int64_t m, float *__restrict__ out, const float *__restrict__ in,
+                                  const GmresDev *gs, const NewtonDev *ns) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m || gmres_idle(ns, gs)) return;
+  out[q] = float(1.0 / gs->beta) * in[q];
+}
+
+// V_{k+1} = w / |w| from |w|^2 on the device (separate Gram-Schmidt path)
+__global__ void scale_norm_kernel(int64_t m, float *__restrict__ out, const float *__restrict__ w,
+                                  const double *__restrict__ nsq, const GmresDev *gs, const NewtonDev *ns) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m || gmres_idle(ns, gs) || !(nsq[0] > 0.0)) return;
+  out[q] = float(1.0 / std::sqrt(nsq[0])) * w[q];
+}
+
+// Column k of the Hessenberg matrix from both Gram-Schmidt passes and |w|^2,
+// the earlier Givens rotations applied to it, a new rotation, the updated
+// right-hand side g and the convergence test |g_{k+1}| <= rtol |b|.  H is
+// row-major [R + 1][R].  One thread.
+__device__ void arnoldi_column(int k, int R, GmresDev *gs, double *__restrict__ H, double *__restrict__ cs,
+                               double *__restrict__ sn, double *__restrict__ g, const double *c1, const double *c2,
+                               double hn2, double rtol) {
+  const double hn = std::sqrt(hn2);
+  for (int i = 0; i <= k; ++i) H[i * R + k] = c1[i] + c2[i];
+  H[(k + 1) * R + k] = hn;
+  for (int i = 0; i < k; ++i) {
+    const double a = H[i * R + k], b = H[(i + 1) * R + k];
+    H[i * R + k] = cs[i] * a + sn[i] * b;
+    H[(i + 1) * R + k] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[k * R + k], b = H[(k + 1) * R + k];
+  const double rr = std::sqrt(a * a + b * b);
+  cs[k] = rr == 0.0 ? 1.0 : a / rr;
+  sn[k] = rr == 0.0 ? 0.0 : b / rr;
+  H[k * R + k] = rr;
+  H[(k + 1) * R + k] = 0.0;
+  g[k + 1] = -sn[k] * g[k];
+  g[k] = cs[k] * g[k];
+  gs->kdone = double(k + 1);
+  if (std::fabs(g[k + 1]) <= rtol * gs->bn || hn == 0.0) gs->done = 1.0;
+}
+
+__global__ void arnoldi_kernel(int k, int R, GmresDev *gs, double *__restrict__ H, double *__restrict__ cs,
+                               double *__restrict__ sn, double *__restrict__ g, const double *__restrict__ c1,
+                               const double *__restrict__ c2, double rtol, const NewtonDev *ns) {
+  if (threadIdx.x != 0 || gmres_idle(ns, gs)) return;
+  arnoldi_column(k, R, gs, H, cs, sn, g, c1, c2, c2[k + 1], rtol);
+}
+
+// y = R^{-1} g over the kdone columns of this cycle (back substitution)
+__global__ void gmres_solve_kernel(int R, const GmresDev *gs, const double *__restrict__ H,
+                                   const double *__restrict__ g, double *__restrict__ y, const NewtonDev *ns) {
+  if (threadIdx.x != 0 || (ns && ns->done != 0.0)) return;
+  const int k = int(gs->kdone);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= H[i * R + j] * y[j];
+    y[i] = s / H[i * R + i];
+  }
+}
+
+// d += sum_{v < kdone} y[v] V_v
+__global__ void update_kernel(int64_t m, const float *__restrict__ V, const double *__restrict__ y,
+                              const GmresDev *gs, const NewtonDev *ns, float *__restrict__ d) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m || (ns && ns->done != 0.0)) return;
+  const int k = int(gs->kdone);
+  double s = 0.0;
+  for (int v = 0; v < k; ++v) s += y[v] * (double)V[(size_t)v * m + q];
+  d[q] = (float)((double)d[q] + s);
+}
+
 inline dim3 g1(int64_t m) { return dim3((unsigned)((m + 255) / 256)); }
 
-// Matrix-free GMRES for (I - c J(xi)) d = b.  The Gram-Schmidt coefficients
-// stay on the device (the projections read them there); the host takes one
-// copy per Arnoldi step (both coefficient sets and |w|^2, into pinned memory)
-// for the Hessenberg column, the Givens rotations and the convergence test.
+// Matrix-free GMRES for (I - c J(xi)) d = b.  The Gram-Schmidt coefficients,
+// the Hessenberg matrix, the Givens rotations and the convergence test stay
+// on the device; the host reads the small state once per batch of Arnoldi
+// steps.
 struct Solver {
   ptrom_ctx *ctx;
   hipStream_t st;
@@ -332,8 +452,8 @@ struct Solver {
   float *pws;
   size_t pwsf;
   float *xi, *tmp, *w, *V;
-  double *dd;     // device: coefficients [restart + 1] twice and |w|^2, then y [restart]
-  double *hp;     // pinned host: the same layout
+  double *dd;     // device: |r|^2, then the coefficients [restart + 1] twice and |w|^2
+  double *hp;     // pinned host scratch (the state copies at hp + 3 restart + 4)
   double *dot_part;
   int restart;
 
@@ -356,34 +476,6 @@ struct Solver {
     hipLaunchKernelGGL(dot_final_kernel, dim3(nvec), dim3(kDotParts), 0, st, dot_part, dev);
   }
 
-  // host[0, count) = dev[0, count), then wait
-  int fetch(const double *dev, double *host, int count) {
-    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, st));
-    PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
-    return PTROM_OK;
-  }
-
-  int norm(const float *y, double *out) {
-    dots(y, 1, y, dd);
-    if (int rc = fetch(dd, hp, 1)) return rc;
-    *out = std::sqrt(hp[0]);
-    return PTROM_OK;
-  }
-
-  // r = D - dt (b0 f + b1 fp) - dt (b0 + b1) u, and |r|
-  int residual(float *r, const float *D, const float *f, const float *fp, float dtb0, float dtb1, const float *u,
-               float dtu, double *out) {
-    if (m <= kShortDot) {
-      hipLaunchKernelGGL(residual_norm_kernel, dim3(1), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu, dd,
-                         nullptr, 0.0, 0);
-      if (int rc = fetch(dd, hp, 1)) return rc;
-      *out = std::sqrt(hp[0]);
-      return PTROM_OK;
-    }
-    hipLaunchKernelGGL(residual_kernel, g1(m), dim3(256), 0, st, m, r, D, f, fp, dtb0, dtb1, u, dtu);
-    return norm(r, out);
-  }
-
   // The residual, its squared norm and the device Newton state update, with
   // no host wait.
   void residual_state(float *r, const float *D, const float *f, const float *fp, float dtb0, float dtb1,
@@ -398,88 +490,93 @@ struct Solver {
     hipLaunchKernelGGL(newton_state_kernel, dim3(1), dim3(64), 0, st, ns, dd, tol, max_newton);
   }
 
-  // Solve (I - c J) d = b from d = 0 to relative tolerance rtol; returns
-  // matvecs in *used.  bn = |b| (the caller has it).
-  int gmres(const float *b, double bn, float *d, float c, double rtol, int maxit, int *used) {
+  // Device GMRES state: GmresDev, then H [(R + 1) R], cs [R], sn [R], g [R + 1], y [R].
+  GmresDev *gsd;
+  double *H, *gcs, *gsn, *gg, *gy;
+
+  // Host copies of both device states (one wait).
+  int fetch_states(const NewtonDev *ns, NewtonDev *hn, GmresDev *hg) {
+    double *h = hp + (3 * restart + 4);
+    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(h, ns, sizeof(NewtonDev), hipMemcpyDeviceToHost, st));
+    PTROM_CHECK_HIP(ctx, hipMemcpyAsync(h + 4, gsd, sizeof(GmresDev), hipMemcpyDeviceToHost, st));
+    PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
+    std::memcpy(hn, h, sizeof(NewtonDev));
+    std::memcpy(hg, h + 4, sizeof(GmresDev));
+    return PTROM_OK;
+  }
+
+  // Solve (I - c J) d = b from d = 0 to relative tolerance rtol by restarted
+  // GMRES whose Hessenberg matrix, rotations and convergence test stay on the
+  // device.  |b|^2 is in dd[0] (the Newton residual's).  The host issues
+  // `predict` Arnoldi steps (more if needed) and then reads the state once;
+  // steps issued after convergence change nothing.  Nothing runs when the
+  // Newton state says the step has finished (*newton_done then true).
+  // *used = Jacobian products that counted, *cols = Arnoldi columns of the
+  // first cycle.
+  int gmres(const float *b, float *d, float c, double rtol, int maxit, int predict, const NewtonDev *ns,
+            NewtonDev *hns, bool *newton_done, int *used, int *cols) {
     *used = 0;
-    hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, d, b, 0.0f);
-    if (bn == 0.0) return PTROM_OK;
+    *cols = 0;
+    *newton_done = false;
     const int R = restart;
-    double *d1 = dd, *d2 = dd + (R + 1), *dy = dd + 2 * (R + 1) + 1, *hy = hp + 2 * (R + 1) + 1;
-    std::vector<double> H((R + 1) * R), cs(R), sn(R), g(R + 1), y(R);
-    bool first = true;
-    while (*used < maxit) {
-      // V0 = residual / |residual|
-      double beta;
-      if (first) {
-        beta = bn;
-        hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V, b, float(1.0 / beta));
-        first = false;
-      } else {
-        if (int rc = apply(d, c, w)) return rc;
-        ++*used;
-        hipLaunchKernelGGL(lincomb_kernel, g1(m), dim3(256), 0, st, m, w, b, 1.0f, w);  // w = b - A d
-        if (int rc = norm(w, &beta)) return rc;
-        if (beta <= rtol * bn) break;
-        hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V, w, float(1.0 / beta));
-      }
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
+    double *d1 = dd, *d2 = dd + (R + 1);
+    hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, d, b, 0.0f);
+    hipLaunchKernelGGL(gmres_init_kernel, dim3(1), dim3(64), 0, st, gsd, gg, R, dd, 1, rtol, ns);
+    hipLaunchKernelGGL(scale_beta_kernel, g1(m), dim3(256), 0, st, m, V, b, gsd, ns);
+    int issued = 0;
+    for (int cycle = 0;; ++cycle) {
+      GmresDev hg{};
       int k = 0;
-      bool done = false;
-      for (; k < R && *used < maxit; ++k) {
-        float *vk = V + (size_t)k * m;
-        if (int rc = apply(vk, c, w)) return rc;
-        ++*used;
-        // classical Gram-Schmidt, applied twice, coefficients on the device
-        const bool fused = m <= kFusedGS;
-        if (fused) {
-          hipLaunchKernelGGL(gs_fused_kernel, dim3(1), dim3(kGSThreads), 0, st, int(m), k, V, w, d1, d2);
-        } else {
-          dots(V, k + 1, w, d1);
-          hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d1, -1.0f, w);
-          dots(V, k + 1, w, d2);
-          hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d2, -1.0f, w);
-          dots(w, 1, w, d2 + (k + 1));
+      for (;;) {
+        const int batch = k == 0 ? std::max(1, predict) : std::max(1, predict / 2);
+        for (int q = 0; q < batch && k < R && issued < maxit; ++q, ++k, ++issued) {
+          float *vk = V + (size_t)k * m;
+          if (m <= kFusedGS) {
+            // the Jacobian product, then one kernel for the rest of the step
+            const hipError_t e = launch_pair(OP_JVP, jcfg, ctx->num_cus, n, xi, gamma, vk, delta, tmp, nullptr, pws,
+                                             pwsf, st);
+            if (e != hipSuccess) return ctx->hip_fail(e, "jvp");
+            hipLaunchKernelGGL(gs_fused_kernel, dim3(1), dim3(kGSThreads), 0, st, int(m), k, V, tmp, c, d1, d2, ns,
+                               gsd, R, H, gcs, gsn, gg, rtol);
+            continue;
+          }
+          if (int rc = apply(vk, c, w)) return rc;
+          {
+            // classical Gram-Schmidt, applied twice, coefficients on the device
+            dots(V, k + 1, w, d1);
+            hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d1, -1.0f, w);
+            dots(V, k + 1, w, d2);
+            hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k + 1, V, m, d2, -1.0f, w);
+            dots(w, 1, w, d2 + (k + 1));
+            hipLaunchKernelGGL(scale_norm_kernel, g1(m), dim3(256), 0, st, m, V + (size_t)(k + 1) * m, w,
+                               d2 + (k + 1), gsd, ns);
+            hipLaunchKernelGGL(arnoldi_kernel, dim3(1), dim3(64), 0, st, k, R, gsd, H, gcs, gsn, gg, d1, d2, rtol,
+                               ns);
+          }
         }
-        // one copy covering d1 [0, k], d2 [0, k] and |w|^2 (d2 starts at R + 1)
-        if (int rc = fetch(dd, hp, R + k + 3)) return rc;
-        const double *h1 = hp, *h2 = hp + (R + 1);
-        const double hn = std::sqrt(h2[k + 1]);
-        for (int i = 0; i <= k; ++i) H[i * R + k] = h1[i] + h2[i];
-        H[(k + 1) * R + k] = hn;
-        if (hn > 0.0 && !fused)
-          hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, V + (size_t)(k + 1) * m, w, float(1.0 / hn));
-        for (int i = 0; i < k; ++i) {
-          const double a = H[i * R + k], bb = H[(i + 1) * R + k];
-          H[i * R + k] = cs[i] * a + sn[i] * bb;
-          H[(i + 1) * R + k] = -sn[i] * a + cs[i] * bb;
+        if (int rc = fetch_states(ns, hns, &hg)) return rc;
+        if (hns->done != 0.0) {
+          *newton_done = true;
+          return PTROM_OK;
         }
-        const double a = H[k * R + k], bb = H[(k + 1) * R + k];
-        const double rr = std::sqrt(a * a + bb * bb);
-        cs[k] = rr == 0.0 ? 1.0 : a / rr;
-        sn[k] = rr == 0.0 ? 0.0 : bb / rr;
-        H[k * R + k] = rr;
-        H[(k + 1) * R + k] = 0.0;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = cs[k] * g[k];
-        if (std::fabs(g[k + 1]) <= rtol * bn || hn == 0.0) {
-          ++k;
-          done = true;
-          break;
-        }
+        if (hg.done != 0.0 || k >= R || issued >= maxit) break;
       }
-      for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int j = i + 1; j < k; ++j) s -= H[i * R + j] * y[j];
-        y[i] = s / H[i * R + i];
-      }
-      // the pinned y is read by the copy before any later host write to it:
-      // every path to the next write passes a fetch (stream synchronisation)
-      std::copy(y.begin(), y.begin() + k, hy);
-      PTROM_CHECK_HIP(ctx, hipMemcpyAsync(dy, hy, sizeof(double) * k, hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(multi_axpy_kernel, g1(m), dim3(256), 0, st, m, k, V, m, dy, 1.0f, d);
-      if (done) break;
+      const int kd = int(hg.kdone);
+      *used += kd;
+      if (cycle == 0) *cols = kd;
+      hipLaunchKernelGGL(gmres_solve_kernel, dim3(1), dim3(64), 0, st, R, gsd, H, gg, gy, ns);
+      hipLaunchKernelGGL(update_kernel, g1(m), dim3(256), 0, st, m, V, gy, gsd, ns, d);
+      if (hg.done != 0.0 || issued >= maxit) break;
+      // restart from the true residual b - A d
+      if (int rc = apply(d, c, w)) return rc;
+      ++issued;
+      ++*used;
+      hipLaunchKernelGGL(lincomb_kernel, g1(m), dim3(256), 0, st, m, w, b, 1.0f, w);  // w = b - A d
+      dots(w, 1, w, dd);
+      hipLaunchKernelGGL(gmres_init_kernel, dim3(1), dim3(64), 0, st, gsd, gg, R, dd, 0, rtol, ns);
+      hipLaunchKernelGGL(scale_beta_kernel, g1(m), dim3(256), 0, st, m, V, w, gsd, ns);
+      if (int rc = fetch_states(ns, hns, &hg)) return rc;
+      if (hg.done != 0.0) break;
     }
     return PTROM_OK;
   }
@@ -517,7 +614,8 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   const size_t vb = align256(m * sizeof(float));
   const size_t need = vb * (9 + R + 1) + align256(pwsf * sizeof(float)) + align256(sizeof(double) * (3 * R + 4)) +
                       align256(sizeof(double) * (R + 2) * kDotParts) + align256(4 * n * sizeof(float)) +
-                      align256(sizeof(NewtonDev)) + 1024;
+                      align256(sizeof(NewtonDev)) + align256(sizeof(double) * (4 + (R + 1) * R + 4 * R + 1)) +
+                      1024;
   if (int rc = ctx->reserve(need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), ctx->ws_bytes};
   float *xprev = cv.take<float>(m), *D = cv.take<float>(m), *xi = cv.take<float>(m);
@@ -529,11 +627,18 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   double *dpart = cv.take<double>(size_t(R + 2) * kDotParts);
   float *Bj = cv.take<float>(4 * n);
   NewtonDev *nst = cv.take<NewtonDev>(1);
-  if (!w || !V || !pws || !dd || !dpart || !Bj || !nst) return ctx->fail(PTROM_ENOMEM, "workspace carve");
-  double *hp = ctx->pinned_doubles(3 * R + 8);  // GMRES scalars, then the Newton state
+  GmresDev *gdev = reinterpret_cast<GmresDev *>(cv.take<double>(4 + size_t(R + 1) * R + 4 * size_t(R) + 1));
+  if (!w || !V || !pws || !dd || !dpart || !Bj || !nst || !gdev) return ctx->fail(PTROM_ENOMEM, "workspace carve");
+  double *hp = ctx->pinned_doubles(3 * R + 12);  // the Newton and GMRES state copies at 3 R + 4
   if (!hp) return ctx->fail(PTROM_ENOMEM, "pinned host scratch");
   hipStream_t st = (hipStream_t)stream;
   Solver S{ctx, st, n, m, gamma, delta, jcfg, pws, pwsf, xi, tmp, w, V, dd, hp, dpart, R};
+  S.gsd = gdev;
+  S.H = reinterpret_cast<double *>(gdev + 1);
+  S.gcs = S.H + (R + 1) * R;
+  S.gsn = S.gcs + R;
+  S.gg = S.gsn + R;
+  S.gy = S.gg + (R + 1);
 
   // velocity at x (and, for the block model, the self blocks in the same pass)
   auto rhs = [&](const float *x, float *fo, bool blocks) -> int {
@@ -569,7 +674,7 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
         S.residual_state(r, D, fc, fp, dt * b0, dt * b1, uinf, dt * (b0 + b1), nst, o.newton_tol, o.max_newton);
         hipLaunchKernelGGL(block_solve_kernel, g1(n), dim3(256), 0, st, n, D, xi, xprev, r, Bj, dt * b0, nst);
       }
-      double *hst = ctx->pinned_doubles(3 * R + 8) + (3 * R + 4);
+      double *hst = hp + (3 * R + 4);
       PTROM_CHECK_HIP(ctx, hipMemcpyAsync(hst, nst, sizeof(NewtonDev), hipMemcpyDeviceToHost, st));
       PTROM_CHECK_HIP(ctx, hipStreamSynchronize(st));
       std::memcpy(&hs, hst, sizeof(NewtonDev));
@@ -583,32 +688,45 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
     predicted = it + 1;
     hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xy, xprev, D);
   }
+  // GMRES model: the Newton test runs on the device too.  The host issues an
+  // iteration's GMRES without waiting for its residual while the step is
+  // expected to continue (fewer iterations than the previous step took), and
+  // reads both states once per Newton iteration.
+  int predicted_newton = 1, predicted_cols = 4;
   for (int step = 0; !block && step < nsteps; ++step) {
     hipLaunchKernelGGL(step_start_kernel, g1(m), dim3(256), 0, st, m, xprev, D, xi, xy);
+    hipLaunchKernelGGL(newton_reset_kernel, dim3(1), dim3(64), 0, st, nst);
     if (int rc = rhs(xprev, fp, false)) return rc;
-    double r0 = -1.0, rn = 0.0;
-    int it = 0;
-    for (;; ++it) {
+    NewtonDev hs{};
+    for (int it = 0;; ++it) {
       if (it > 0) {
         hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xi, xprev, D);  // xi = x_prev + D
         if (int rc = rhs(xi, f, false)) return rc;
       }
-      if (int rc = S.residual(r, D, it == 0 ? fp : f, fp, dt * b0, dt * b1, uinf, dt * (b0 + b1), &rn)) return rc;
-      if (r0 < 0.0) r0 = rn;
-      if (rn <= o.newton_tol * r0 || r0 == 0.0) break;
-      if (it >= o.max_newton) {
-        stl.nonconverged_steps++;
-        break;
+      S.residual_state(r, D, it == 0 ? fp : f, fp, dt * b0, dt * b1, uinf, dt * (b0 + b1), nst, o.newton_tol,
+                       o.max_newton);
+      if (it >= predicted_newton) {
+        GmresDev hg{};
+        if (int rc = S.fetch_states(nst, &hs, &hg)) return rc;
+        if (hs.done != 0.0) break;
       }
       hipLaunchKernelGGL(scale_kernel, g1(m), dim3(256), 0, st, m, r, r, -1.0f);
-      int used = 0;
-      if (int rc = S.gmres(r, rn, d, dt * b0, o.gmres_tol, o.gmres_maxit, &used)) return rc;
+      int used = 0, cols = 0;
+      bool newton_done = false;
+      if (int rc = S.gmres(r, d, dt * b0, o.gmres_tol, o.gmres_maxit, predicted_cols, nst, &hs, &newton_done, &used,
+                           &cols))
+        return rc;
+      if (newton_done) break;
       stl.krylov_iters += used;
+      if (cols > 0) predicted_cols = cols;
       hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, D, D, d);
     }
+    const int it = int(hs.it);
+    if (hs.done != 1.0) stl.nonconverged_steps++;
     stl.newton_iters += it;
-    const double rel = r0 > 0.0 ? rn / r0 : 0.0;
+    const double rel = hs.r0sq > 0.0 ? std::sqrt(hs.rnsq / hs.r0sq) : 0.0;
     if (rel > stl.max_final_rel_residual) stl.max_final_rel_residual = rel;
+    predicted_newton = it;
     hipLaunchKernelGGL(add_kernel, g1(m), dim3(256), 0, st, m, xy, xprev, D);
   }
   PTROM_CHECK_HIP(ctx, hipGetLastError());
