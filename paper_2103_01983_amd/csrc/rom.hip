@@ -873,9 +873,14 @@ __host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, i
   return L;
 }
 
+// spill = 0: every array in LDS; 1: region 1 ([C | rbar], then N) of query q
+// at spill + q r1 in global memory (L2-resident), the rest in LDS; 2: all of
+// them at spill + q total.  __syncthreads orders the workgroup's global
+// accesses as it orders LDS ones (one CU, one vector cache).
 __global__ void __launch_bounds__(kRunThreads)
     rom_run_large_kernel(RomDev d, int nsteps, const float *__restrict__ gtq, double *__restrict__ xhat,
-                         double *__restrict__ hist, int *__restrict__ iters) {
+                         double *__restrict__ hist, int *__restrict__ iters, double *__restrict__ spill,
+                         int spill_mode) {
   __shared__ double xh[kMaxM + 32], xs[kMaxM];  // xh is zero beyond M
   __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
@@ -886,7 +891,8 @@ __global__ void __launch_bounds__(kRunThreads)
   const int nnz = (int)d.nnz;
   const double hdt = 0.5 * (double)d.dt;
   const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, d.Nc);
-  double *R1 = dyn, *R2 = dyn + L.r1;
+  double *R1 = spill_mode == 0 ? dyn : spill + blockIdx.x * (spill_mode == 1 ? L.r1 : L.total);
+  double *R2 = spill_mode == 1 ? dyn : R1 + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
   // region 1: [C | rbar_hi | rbar_lo | 0] as FP32 (ndp rows of stride ldcf,
   // zero padded; the two parts of rbar keep its FP64 value to 2^-48, and A
@@ -1541,12 +1547,20 @@ int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xha
   ptrom_ctx *ctx = rom->ctx;
   const RomDev &d = rom->d;
   if (d.M > kSmallM || d.Mr > kSmallMr) {
+    // the query's arrays in LDS when they fit; otherwise [C | rbar] and N
+    // (the largest) in global memory, or, if the rest still does not fit,
+    // every array there
     const BigLayout L = big_layout(d.M, d.Mr, d.nd, d.ns, d.nnz, d.Nc);
-    const size_t bytes = L.total * sizeof(double);
-    if (bytes > rom->max_dyn_lds_big)
-      return ctx->fail(PTROM_EINVAL, "basis, sample set and lists too large for one workgroup's LDS");
-    hipLaunchKernelGGL(rom_run_large_kernel, dim3(nq), dim3(kRunThreads), bytes, st, d, nsteps, gtq, xhat,
-                       xhat_hist, iters);
+    size_t lds = L.total * sizeof(double), glob = 0;
+    int mode = 0;
+    if (lds > rom->max_dyn_lds_big) {
+      mode = (L.total - L.r1) * sizeof(double) <= rom->max_dyn_lds_big ? 1 : 2;
+      glob = size_t(nq) * (mode == 1 ? L.r1 : L.total) * sizeof(double);
+      lds = mode == 1 ? (L.total - L.r1) * sizeof(double) : 0;
+      if (int rc = ctx->reserve(glob + 256)) return rc;
+    }
+    hipLaunchKernelGGL(rom_run_large_kernel, dim3(nq), dim3(kRunThreads), lds, st, d, nsteps, gtq, xhat, xhat_hist,
+                       iters, mode ? static_cast<double *>(ctx->ws) : nullptr, mode);
     PTROM_CHECK_HIP(ctx, hipGetLastError());
     return PTROM_OK;
   }

@@ -380,15 +380,12 @@ def test_edge_shapes_parity(dev, edge_shapes, shape):
     _run_check(dev, edge_shapes[shape])
 
 
-def test_largest_shape_over_lds_is_rejected(dev, edge_shapes):
-    # the gather entry point has no LDS limit; the online run refuses arrays
-    # that do not fit one workgroup
+def test_largest_shape_beyond_lds_runs_from_global_memory(dev, edge_shapes):
+    # arrays that do not fit one workgroup's LDS: [C | rbar] and the normal
+    # matrix go to global memory and the run matches the oracle
     art = edge_shapes[(112, 256, 128)]
     _hyperpair_check(dev, art, 8)
-    rom = native.Rom(art, tol=0.0, max_iter=2)
-    xh = torch.zeros(112, dtype=torch.float64, device=dev)
-    with pytest.raises(native.PtromError, match="LDS"):
-        rom.run(1, xh, None, None)
+    _run_check(dev, art)
 
 
 def _drop_list(art, t):
@@ -423,13 +420,22 @@ def trained_large():
     art, _ = off.train_parametric(vp, 0.01, 30, M=85, Mr=110, ns=60, depth=16, pc=1.0, tol=1e-4)
     out["vortex_pair"] = rounded(art)
     mc = [W.mushroom_cloud(m) for m in ((-200.0, 130.0), (-120.0, 210.0), (-170.0, 170.0), (-140.0, 120.0))]
-    art, _ = off.train_parametric(mc, 0.005, 30, M=110, Mr=185, ns=75, depth=16, pc=1.0, tol=1e-4,
-                                  u=W.mushroom_inflow(500))
+    u = W.mushroom_inflow(500)
+    art, ex = off.train_parametric(mc, 0.005, 30, M=110, Mr=185, ns=75, depth=16, pc=1.0, tol=1e-4, u=u)
     out["mushroom_cloud"] = rounded(art)
+    # the same training with n_s = 120 sampled bodies (2 n_s >= M_r): the
+    # query's arrays pass one workgroup's LDS, so [C | rbar] and the normal
+    # matrix live in global memory
+    sample = off.greedy_sample(ex["Phi_r"], 120)
+    A = off.gappy_operator(ex["Phi_r"], sample)
+    x0 = np.asarray(mc[0].xy, dtype=np.float64)
+    a120 = off.rom_artifacts(sample, ex["tree"], 1.0, x0, ex["Phi"], ex["weights"], float(mc[0].delta), 0.005,
+                             A=A, u=u)
+    out["mushroom_cloud_ns120"] = rounded(a120)
     return out
 
 
-@pytest.mark.parametrize("case", ["vortex_pair", "mushroom_cloud"])
+@pytest.mark.parametrize("case", ["vortex_pair", "mushroom_cloud", "mushroom_cloud_ns120"])
 def test_large_run_trained_artifacts(dev, trained_large, case):
     # the larger-basis path (normal equations of A C on the FP64 matrix cores,
     # blocked Gauss-Jordan, C held in FP32) on trained artifacts, fixed K
