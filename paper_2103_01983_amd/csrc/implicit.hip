@@ -692,7 +692,9 @@ extern "C" int ptrom_implicit_forced(ptrom_ctx *ctx, int64_t n, float *xy, const
   // iteration's GMRES without waiting for its residual while the step is
   // expected to continue (fewer iterations than the previous step took), and
   // reads both states once per Newton iteration.
-  int predicted_newton = 1, predicted_cols = 4;
+  // (speculative Arnoldi steps are cheap for short vectors; for long ones a
+  // wasted Jacobian product costs far more than a wait, so start from one)
+  int predicted_newton = 1, predicted_cols = m <= kFusedGS ? 4 : 1;
   for (int step = 0; !block && step < nsteps; ++step) {
     hipLaunchKernelGGL(step_start_kernel, g1(m), dim3(256), 0, st, m, xprev, D, xi, xy);
     hipLaunchKernelGGL(newton_reset_kernel, dim3(1), dim3(64), 0, st, nst);
