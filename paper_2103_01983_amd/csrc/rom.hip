@@ -68,7 +68,10 @@ struct RomDev {
   const int *etg, *eid;
   const float *gt0;
   double *pos;  // [P] point-form positions of the hook's last evaluation
-  double *spk;  // [Nc][4] the same surrogate positions packed with Gamma~: x, y, Gamma~, 0
+  double *spk;  // [Nc][4] the same surrogate positions packed with Gamma~: x, y, Gamma~, 0,
+                // surrogate c at record rec[c] (Morton order of the reference positions)
+  const int *rec;   // [Nc]
+  const int *erec;  // [nnz] records of each target's surrogates, ascending within the target
   const double *A;              // [Mr][nd]
   // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
   // leading dimension ldc
@@ -389,12 +392,13 @@ __global__ void __launch_bounds__(256)
   for (int m = 0; m < d.M; ++m) v = fma(d.pt[(size_t)m * d.P + q], xh[m], v);
   pos[q] = v;
   if (q >= d.nd) {
-    // one 32-byte record per surrogate: a list entry touches one cache line
-    const int c = (q - d.nd) >> 1, k = (q - d.nd) & 1;
-    d.spk[4 * c + k] = v;
+    // one 32-byte record per surrogate: a list entry touches one cache line,
+    // and spatially close surrogates (a target's near field) share lines
+    const int c = (q - d.nd) >> 1, k = (q - d.nd) & 1, rc = d.rec[c];
+    d.spk[4 * rc + k] = v;
     if (k == 0) {
-      d.spk[4 * c + 2] = (double)d.gt0[c];
-      d.spk[4 * c + 3] = 0.0;
+      d.spk[4 * rc + 2] = (double)d.gt0[c];
+      d.spk[4 * rc + 3] = 0.0;
     }
   }
 }
@@ -416,7 +420,10 @@ __device__ __forceinline__ void point_terms(double tx, double ty, const dbl4 p, 
   a.bc = fmaf(g2, dd + d2, a.bc);
 }
 
-__global__ void __launch_bounds__(256)
+constexpr int kGatherU = 4;
+
+// (at most 64 VGPRs: eight waves per SIMD to hide the dependent loads)
+__global__ void __launch_bounds__(256, 8)
     gather_point_kernel(RomDev d, const double *__restrict__ pos, const double *__restrict__ xbar_prev,
                         const double *__restrict__ fbar_prev, double *xbar, double *fbar, double *rbar, double *C) {
   const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -425,23 +432,25 @@ __global__ void __launch_bounds__(256)
   const int ns = d.ns, M = d.M;
   const double tx = pos[t], ty = pos[ns + t];
   const dbl4 *sp = reinterpret_cast<const dbl4 *>(d.spk);
+  const double hdt = 0.5 * (double)d.dt;
   GatherAcc<false> a;
   const int e1 = d.off[t + 1];
-  int e = d.off[t] + lane;
-  // four entries in flight per lane: the ids, then the records they name,
-  // are all requested before any is used
-  for (; e + 192 < e1; e += 256) {
-    const int c0 = d.eid[e], c1 = d.eid[e + 64], c2 = d.eid[e + 128], c3 = d.eid[e + 192];
-    const dbl4 p0 = sp[c0], p1 = sp[c1], p2 = sp[c2], p3 = sp[c3];
-    point_terms(tx, ty, p0, d.d2, a);
-    point_terms(tx, ty, p1, d.d2, a);
-    point_terms(tx, ty, p2, d.d2, a);
-    point_terms(tx, ty, p3, d.d2, a);
+  // kGatherU entries in flight per lane: the ids, then the records they
+  // name, are requested before any is used; an entry past the list's end
+  // reads record 0 and adds nothing
+  for (int e = d.off[t] + lane; e < e1; e += 64 * kGatherU) {
+    int c[kGatherU];
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u) c[u] = e + 64 * u < e1 ? d.erec[e + 64 * u] : -1;
+    dbl4 p[kGatherU];
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u) p[u] = sp[c[u] < 0 ? 0 : c[u]];
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u)
+      if (c[u] >= 0) point_terms(tx, ty, p[u], d.d2, a);
   }
-  for (; e < e1; e += 64) point_terms(tx, ty, sp[d.eid[e]], d.d2, a);
   const double Fx = gsum(a.fx, 64) * kInv2PiD + d.ubar[t];
   const double Fy = gsum(a.fy, 64) * kInv2PiD + d.ubar[ns + t];
-  const double hdt = 0.5 * (double)d.dt;
   if (lane == 0) {
     if (xbar) {
       xbar[t] = tx;
@@ -1393,6 +1402,42 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       etg[e] = i;
       eid[e] = int(s.ids[e]);
     }
+  // record order of the hook's surrogate table: Morton order of the
+  // reference positions (16 bits per axis over their bounding box)
+  std::vector<int> rec(size_t(s.Nc > 0 ? s.Nc : 1), 0), erec(etg.size(), 0);
+  if (s.Nc > 0) {
+    double lo[2] = {s.xqt0[0], s.xqt0[1]}, hi[2] = {s.xqt0[0], s.xqt0[1]};
+    for (int64_t c = 0; c < s.Nc; ++c)
+      for (int k = 0; k < 2; ++k) {
+        lo[k] = std::min(lo[k], s.xqt0[2 * c + k]);
+        hi[k] = std::max(hi[k], s.xqt0[2 * c + k]);
+      }
+    auto spread = [](uint32_t v) {
+      uint64_t x = v & 0xFFFFu;
+      x = (x | (x << 8)) & 0x00FF00FFull;
+      x = (x | (x << 4)) & 0x0F0F0F0Full;
+      x = (x | (x << 2)) & 0x33333333ull;
+      x = (x | (x << 1)) & 0x55555555ull;
+      return x;
+    };
+    std::vector<std::pair<uint64_t, int>> key(size_t(s.Nc));
+    for (int64_t c = 0; c < s.Nc; ++c) {
+      uint32_t g[2];
+      for (int k = 0; k < 2; ++k) {
+        const double w = hi[k] > lo[k] ? (s.xqt0[2 * c + k] - lo[k]) / (hi[k] - lo[k]) : 0.0;
+        g[k] = uint32_t(std::min(65535.0, std::max(0.0, std::floor(w * 65536.0))));
+      }
+      key[c] = {spread(g[0]) | (spread(g[1]) << 1), int(c)};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t r = 0; r < s.Nc; ++r) rec[key[r].second] = int(r);
+    // each target's entries in record order: neighbouring lanes read
+    // neighbouring records (the hook's sums run in this order)
+    for (int i = 0; i < s.ns; ++i) {
+      for (int64_t e = s.off[i]; e < s.off[i + 1]; ++e) erec[e] = rec[s.ids[e]];
+      std::sort(erec.begin() + s.off[i], erec.begin() + s.off[i + 1]);
+    }
+  }
   std::vector<double> ubar(nd, 0.0);
   if (s.ubar)
     for (int q = 0; q < nd; ++q) ubar[q] = s.ubar[q];
@@ -1464,7 +1509,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
                           align256(size_t(nd) * ((M + 4) / 4 * 4) * 8), align256(pt.size() * 8),
                           align256(p0.size() * 8), align256(etg.size() * 4), align256(eid.size() * 4),
                           align256(gt0.size() * 4), align256(ubar.size() * 8), align256(size_t(P) * 8),
-                          align256(size_t(s.Nc > 0 ? s.Nc : 1) * 32)};
+                          align256(size_t(s.Nc > 0 ? s.Nc : 1) * 32), align256(rec.size() * 4),
+                          align256(erec.size() * 4)};
   constexpr int NB = sizeof(bytes) / sizeof(bytes[0]);
   size_t total = 0;
   for (size_t b : bytes) total += b;
@@ -1484,6 +1530,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.P = int(P); d.pt = (double *)ptrs[9]; d.p0 = (double *)ptrs[10]; d.etg = (int *)ptrs[11];
   d.eid = (int *)ptrs[12]; d.gt0 = (float *)ptrs[13]; d.ubar = (double *)ptrs[14]; d.pos = (double *)ptrs[15];
   d.spk = (double *)ptrs[16];
+  d.rec = (int *)ptrs[17];
+  d.erec = (int *)ptrs[18];
   hipError_t e = hipMemcpy(ptrs[0], phibar.data(), phibar.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[1], xbar0.data(), xbar0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[2], ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
@@ -1495,6 +1543,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   if (e == hipSuccess) e = hipMemcpy(ptrs[12], eid.data(), eid.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[13], gt0.data(), gt0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[14], ubar.data(), ubar.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[17], rec.data(), rec.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[18], erec.data(), erec.size() * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(rom->buf);
     delete rom;
