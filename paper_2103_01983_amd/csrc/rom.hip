@@ -519,9 +519,11 @@ __device__ __forceinline__ double sum8(double v) {
   return v;
 }
 
-template <bool EXACT>
+// LDSA: the arrays' LDS copies are used (a compile-time choice, so every
+// access to them is an LDS instruction); otherwise they are read in place.
+template <bool EXACT, bool LDSA>
 __global__ void __launch_bounds__(kRunThreads)
-    rom_run_kernel(RomDev d, int nsteps, int lds_arrays, int entry_par, const float *__restrict__ gtq,
+    rom_run_kernel(RomDev d, int nsteps, int entry_par, const float *__restrict__ gtq,
                    double *__restrict__ xhat, double *__restrict__ hist, int *__restrict__ iters) {
   __shared__ double xh[kSmallM];
   __shared__ float xf[kSmallM];
@@ -548,7 +550,7 @@ __global__ void __launch_bounds__(kRunThreads)
   xhat += (size_t)blockIdx.x * M;
   if (hist) hist += (size_t)blockIdx.x * nsteps * M;
   if (iters) iters += (size_t)blockIdx.x * nsteps;
-  if (lds_arrays) {
+  if constexpr (LDSA) {
     double *p = T0 + (size_t)kSmallM * 64;
     double *Al = p; p += (size_t)Mr * nd;
     Cp = p; p += (size_t)nd * ldc;
@@ -882,14 +884,14 @@ __host__ __device__ inline BigLayout big_layout(int M, int Mr, int nd, int ns, i
   return L;
 }
 
-// spill = 0: every array in LDS; 1: region 1 ([C | rbar], then N) of query q
+// SPILL = 0: every array in LDS; 1: region 1 ([C | rbar], then N) of query q
 // at spill + q r1 in global memory (L2-resident), the rest in LDS; 2: all of
 // them at spill + q total.  __syncthreads orders the workgroup's global
 // accesses as it orders LDS ones (one CU, one vector cache).
+template <int SPILL>
 __global__ void __launch_bounds__(kRunThreads)
     rom_run_large_kernel(RomDev d, int nsteps, const float *__restrict__ gtq, double *__restrict__ xhat,
-                         double *__restrict__ hist, int *__restrict__ iters, double *__restrict__ spill,
-                         int spill_mode) {
+                         double *__restrict__ hist, int *__restrict__ iters, double *__restrict__ spill) {
   __shared__ double xh[kMaxM + 32], xs[kMaxM];  // xh is zero beyond M
   __shared__ double s_eps, s_g1, s_gn;
   extern __shared__ double dyn[];
@@ -900,8 +902,10 @@ __global__ void __launch_bounds__(kRunThreads)
   const int nnz = (int)d.nnz;
   const double hdt = 0.5 * (double)d.dt;
   const BigLayout L = big_layout(M, Mr, nd, ns, d.nnz, d.Nc);
-  double *R1 = spill_mode == 0 ? dyn : spill + blockIdx.x * (spill_mode == 1 ? L.r1 : L.total);
-  double *R2 = spill_mode == 1 ? dyn : R1 + L.r1;
+  // (a compile-time choice: with every array in LDS the compiler emits LDS
+  // instructions for all of them)
+  double *R1 = SPILL == 0 ? dyn : spill + blockIdx.x * (SPILL == 1 ? L.r1 : L.total);
+  double *R2 = SPILL == 1 ? dyn : R1 + L.r1;
   double *fbar = R2 + L.r2, *fbar_prev = fbar + nd, *xbar_prev = fbar_prev + nd;
   // region 1: [C | rbar_hi | rbar_lo | 0] as FP32 (ndp rows of stride ldcf,
   // zero padded; the two parts of rbar keep its FP64 value to 2^-48, and A
@@ -1290,7 +1294,7 @@ __global__ void __launch_bounds__(kRunThreads)
 }
 
 // dynamic LDS of the run kernel: G' and the tableaux always; the copies of
-// the arrays when lds_arrays; the per-entry terms only in the entry-parallel
+// the arrays in the LDS-copy variant; the per-entry terms only in the entry-parallel
 // gather
 size_t solve_lds_bytes(int M, int Mr) {
   return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)kSmallM * 64);
@@ -1453,8 +1457,10 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
     if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
       maxsh = 64 * 1024;
     size_t stat = 0;
-    const void *kernels[2] = {reinterpret_cast<const void *>(rom_run_kernel<false>),
-                              reinterpret_cast<const void *>(rom_run_kernel<true>)};
+    const void *kernels[4] = {reinterpret_cast<const void *>(rom_run_kernel<false, true>),
+                              reinterpret_cast<const void *>(rom_run_kernel<true, true>),
+                              reinterpret_cast<const void *>(rom_run_kernel<false, false>),
+                              reinterpret_cast<const void *>(rom_run_kernel<true, false>)};
     for (const void *k : kernels) {
       hipFuncAttributes fa{};
       if (hipFuncGetAttributes(&fa, k) == hipSuccess) stat = std::max(stat, fa.sharedSizeBytes);
@@ -1467,14 +1473,19 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
         break;
       }
     hipFuncAttributes fb{};
-    const void *big = reinterpret_cast<const void *>(rom_run_large_kernel);
+    const void *bigs[3] = {reinterpret_cast<const void *>(rom_run_large_kernel<0>),
+                           reinterpret_cast<const void *>(rom_run_large_kernel<1>),
+                           reinterpret_cast<const void *>(rom_run_large_kernel<2>)};
     size_t sb = 0;
-    if (hipFuncGetAttributes(&fb, big) == hipSuccess) sb = fb.sharedSizeBytes;
+    for (const void *k : bigs)
+      if (hipFuncGetAttributes(&fb, k) == hipSuccess) sb = std::max(sb, fb.sharedSizeBytes);
     size_t dynb = size_t(maxsh) > sb ? size_t(maxsh) - sb : 0;
-    if (hipFuncSetAttribute(big, hipFuncAttributeMaxDynamicSharedMemorySize, int(dynb)) != hipSuccess) {
-      dynb = 64 * 1024 > sb ? 64 * 1024 - sb : 0;
-      (void)hipGetLastError();
-    }
+    for (const void *k : bigs)
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(dynb)) != hipSuccess) {
+        dynb = 64 * 1024 > sb ? 64 * 1024 - sb : 0;
+        (void)hipGetLastError();
+        break;
+      }
     rom->max_dyn_lds_big = dynb;
     rom->max_dyn_lds = dyn;
   }
@@ -1609,8 +1620,16 @@ int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xha
       lds = mode == 1 ? (L.total - L.r1) * sizeof(double) : 0;
       if (int rc = ctx->reserve(glob + 256)) return rc;
     }
-    hipLaunchKernelGGL(rom_run_large_kernel, dim3(nq), dim3(kRunThreads), lds, st, d, nsteps, gtq, xhat, xhat_hist,
-                       iters, mode ? static_cast<double *>(ctx->ws) : nullptr, mode);
+    double *sp = mode ? static_cast<double *>(ctx->ws) : nullptr;
+    if (mode == 0)
+      hipLaunchKernelGGL(rom_run_large_kernel<0>, dim3(nq), dim3(kRunThreads), lds, st, d, nsteps, gtq, xhat,
+                         xhat_hist, iters, sp);
+    else if (mode == 1)
+      hipLaunchKernelGGL(rom_run_large_kernel<1>, dim3(nq), dim3(kRunThreads), lds, st, d, nsteps, gtq, xhat,
+                         xhat_hist, iters, sp);
+    else
+      hipLaunchKernelGGL(rom_run_large_kernel<2>, dim3(nq), dim3(kRunThreads), lds, st, d, nsteps, gtq, xhat,
+                         xhat_hist, iters, sp);
     PTROM_CHECK_HIP(ctx, hipGetLastError());
     return PTROM_OK;
   }
@@ -1628,12 +1647,20 @@ int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xha
       return ctx->fail(PTROM_EINVAL, "batched queries need the run arrays to fit in LDS (sample set too large)");
   }
   const size_t shmem = use_lds ? lds : solve_lds_bytes(d.M, d.Mr);
-  if (d.jac_mode == PTROM_JAC_EXACT)
-    hipLaunchKernelGGL(rom_run_kernel<true>, dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, 0, gtq,
+  const bool ex = d.jac_mode == PTROM_JAC_EXACT;
+  const int ep = ex ? 0 : entry_par;
+  if (ex && use_lds)
+    hipLaunchKernelGGL((rom_run_kernel<true, true>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq, xhat,
+                       xhat_hist, iters);
+  else if (ex)
+    hipLaunchKernelGGL((rom_run_kernel<true, false>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq,
+                       xhat, xhat_hist, iters);
+  else if (use_lds)
+    hipLaunchKernelGGL((rom_run_kernel<false, true>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq,
                        xhat, xhat_hist, iters);
   else
-    hipLaunchKernelGGL(rom_run_kernel<false>, dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, use_lds, entry_par,
-                       gtq, xhat, xhat_hist, iters);
+    hipLaunchKernelGGL((rom_run_kernel<false, false>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq,
+                       xhat, xhat_hist, iters);
   PTROM_CHECK_HIP(ctx, hipGetLastError());
   return PTROM_OK;
 }
