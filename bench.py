@@ -209,6 +209,8 @@ def roofline_entry(native, op, n, pairs, launch_ms):
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": ach / PEAK_FP32_TFLOPS,
+        "frac_basis": "algorithmic FLOP (FLOP per ordered pair x N(N-1)) / launch time; executed_frac "
+                      "counts the FP32 work the each-pair-once kernel issues",
         "avg_launch_ms": launch_ms,
         "flop_per_pair": FLOP_PER_PAIR[op],
         "traffic": traffic_for(op, cfg),
@@ -565,6 +567,8 @@ def cpu_baseline(cl, f_gpu, native, x0, g, d):
     except OSError:
         pass
     return {"value": done * (n - 1) / sec, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+            "build": "gcc -O2 -fopenmp, x86-64 baseline ISA (the oracle as the tests use it; built where the "
+                     "library is built, so no -march=native)",
             "sample": "FP64 oracle velocity at %d random targets (batches of 8192) of the N=65536 Gaussian "
                       "patch, each against all sources" % done,
             "seconds": sec, "gpu_rel_err_on_sample_max": max(errs),
