@@ -327,6 +327,33 @@ int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const double *xbar_p
 int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, int32_t *iters,
                   ptrom_stream stream);
 
+/* Workgroups per query of the small-basis runs with the paper's Jacobian
+ * (ptrom_rom_run, ptrom_rom_run_batched; M <= 32, M_r <= 64, arrays in LDS).
+ * With W > 1 each of a query's W workgroups keeps a contiguous slice of the
+ * interaction-list entries in LDS and sums its slice's HyperPair terms per
+ * target; the W partial sums meet at a device-side counter barrier once per
+ * HyperPair evaluation and are added in slice order, and every workgroup then
+ * runs the same least-squares step, so all of them hold the same xhat.  The
+ * launch is cooperative (all W x nq workgroups resident).  workgroups: 0 =
+ * automatic (about 1024 entries per slice, at most 16, widened until a slice
+ * fits in LDS; no split for 1024 entries or fewer), 1 = one workgroup per
+ * query, 2..64 = that many (widened if a slice does not fit).  The split is
+ * skipped, silently, where the device takes no cooperative launch or the grid
+ * would not be resident at once.  A barrier wait that fails max_polls checks
+ * (0: the default, 2^20 checks, about a second, which a resident grid never
+ * reaches; a small value forces the path) stops every workgroup of the
+ * launch at its next barrier and reports iters = -1 for every step of each
+ * affected query and a NaN xhat.  Calls on one context share its workspace,
+ * which holds the partial sums and counters; runs that overlap on one
+ * context race.  EINVAL for workgroups outside 0..64. */
+int ptrom_rom_set_split(ptrom_rom *rom, int workgroups, uint32_t max_polls);
+
+/* The workgroups per query (1 = no split) that ptrom_rom_run (batched_nq = 0)
+ * or ptrom_rom_run_batched with batched_nq queries would use for nsteps
+ * steps, written to *workgroups (host int32).  Launches nothing.  EINVAL for
+ * a NULL output or negative counts. */
+int ptrom_rom_split_plan(ptrom_rom *rom, int batched_nq, int nsteps, int32_t *workgroups);
+
 /* Parametric queries (online computations: the tree keeps the bodies of each
  * cluster, so the clustered circulations are reloaded for a new parameter
  * without retraining).

@@ -164,17 +164,21 @@ __device__ __forceinline__ void load_entry(const float *ent, int ew, int64_t nnz
   }
 }
 
-template <bool EXACT>
+// MB: the compile-time bound on the basis size (8, 16 or 32) of the small
+// kernels, which sizes every unrolled mode loop, so a small basis runs
+// proportionally less code
+template <bool EXACT, int MB = kSmallM>
 struct GatherAcc {
   float fx = 0.f, fy = 0.f, ba = 0.f, bb = 0.f, bc = 0.f;
-  float ex[EXACT ? kSmallM : 1] = {}, ey[EXACT ? kSmallM : 1] = {};
+  float ex[EXACT ? MB : 1] = {}, ey[EXACT ? MB : 1] = {};
 };
 
 // Velocity and Jacobian terms of one (target, surrogate) entry at xhat:
 // r = r0 + D xhat; the 2x2 block (or, exact mode, its product with D).
-template <bool EXACT, int EW>
+template <bool EXACT, int EW, int MB>
 __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *ent, int ew, int e, const float *xf,
-                                            const float *gt, int M, float d2, GatherAcc<EXACT> &a) {
+                                            const float *gt, int M, float d2, GatherAcc<EXACT, MB> &a) {
+  static_assert(!EXACT || (EW - 4) / 2 <= MB, "accumulators for every mode of the row");
   float rx = v[0], ry = v[1];
 #pragma unroll
   for (int m = 0; m < (EW - 4) / 2; ++m)
@@ -198,7 +202,7 @@ __device__ __forceinline__ void entry_terms(const float (&v)[EW], const float *e
     const float h00 = g2 * a2, h01 = g2 * (dd - d2), h10 = g2 * (dd + d2);
     const float *row = ent + (size_t)e * ew;
 #pragma unroll
-    for (int m = 0; m < kSmallM; ++m)
+    for (int m = 0; m < (EW - 4) / 2; ++m)
       if (m < M) {
         const float dx = row[4 + 2 * m], dy = row[5 + 2 * m];
         a.ex[m] = fmaf(h00, dx, fmaf(h01, dy, a.ex[m]));
@@ -261,13 +265,14 @@ __device__ __forceinline__ float gsum(float v, int G) {
 // group sums only.  xh: FP64 xhat, xf: FP32 copy; Phibar / xbar0 may be LDS
 // copies.  Any output pointer may be null.  Row q of rbar is rbar_out[q * rs],
 // row q of C is C_out[q * ldc .. + M).
-template <bool EXACT>
+template <bool EXACT, int MB = kSmallM>
 __device__ void gather_group(const RomDev &d, const float *Phibar, const float *xbar0, const float *gt, int t,
                              bool valid, int gl, int G, const double *xh, const float *xf, const double *xbar_prev,
                              const double *fbar_prev, double *xbar_out, double *fbar_out, double *rbar_out, int rs,
-                             double *C_out, int ldc) {
+                             double *C_out, int ldc, const double *ubar) {
   const int M = d.M, ns = d.ns;
-  GatherAcc<EXACT> a;
+  constexpr int EWB = 4 + 2 * MB;  // the longest row of the bound
+  GatherAcc<EXACT, MB> a;
   if (valid) {
     // two (four for M <= 8) entries per lane per pass: the rows are
     // requested before any is used, cutting the exposed load latency on long
@@ -275,9 +280,14 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
     const int e1 = d.off[t + 1];
     int e = d.off[t] + gl;
     if constexpr (!EXACT) {
-      if (M > kSmallM) {
-        for (; e < e1; e += G) entry_terms_stream(d.ent, d.nnz, e, xf, gt, M, d.d2, a);
-      } else if (d.ew <= kShortEw) {
+      bool streamed = false;
+      if constexpr (MB == kSmallM) {
+        if (M > kSmallM) {
+          for (; e < e1; e += G) entry_terms_stream(d.ent, d.nnz, e, xf, gt, M, d.d2, a);
+          streamed = true;
+        }
+      }
+      if (!streamed && d.ew <= kShortEw) {
         if (d.ew <= kTinyEw) {
           // four rows in flight per lane for the smallest bases
           for (; e + 3 * G < e1; e += 4 * G) {
@@ -292,23 +302,25 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
             entry_terms<false>(v3, nullptr, 0, 0, xf, gt, M, d.d2, a);
           }
         }
-        for (; e + G < e1; e += 2 * G) {
-          float v0[kShortEw], v1[kShortEw];
-          load_entry<true>(d.ent, d.ew, d.nnz, e, v0);
-          load_entry<true>(d.ent, d.ew, d.nnz, e + G, v1);
-          entry_terms<false>(v0, nullptr, 0, 0, xf, gt, M, d.d2, a);
-          entry_terms<false>(v1, nullptr, 0, 0, xf, gt, M, d.d2, a);
+        if constexpr (MB > 8) {
+          for (; e + G < e1; e += 2 * G) {
+            float v0[kShortEw], v1[kShortEw];
+            load_entry<true>(d.ent, d.ew, d.nnz, e, v0);
+            load_entry<true>(d.ent, d.ew, d.nnz, e + G, v1);
+            entry_terms<false>(v0, nullptr, 0, 0, xf, gt, M, d.d2, a);
+            entry_terms<false>(v1, nullptr, 0, 0, xf, gt, M, d.d2, a);
+          }
         }
       }
     }
     for (; e < e1; e += G) {
-      float v[kMaxEw];
+      float v[EWB];
       load_entry<!EXACT>(d.ent, d.ew, d.nnz, e, v);
       entry_terms<EXACT>(v, d.ent, d.ew, e, xf, gt, M, d.d2, a);
     }
   }
-  const double Fx = gsum(a.fx, G) * kInv2PiD + (valid ? d.ubar[t] : 0.0);
-  const double Fy = gsum(a.fy, G) * kInv2PiD + (valid ? d.ubar[ns + t] : 0.0);
+  const double Fx = gsum(a.fx, G) * kInv2PiD + (valid ? ubar[t] : 0.0);
+  const double Fy = gsum(a.fy, G) * kInv2PiD + (valid ? ubar[ns + t] : 0.0);
   const double hdt = 0.5 * (double)d.dt;
   if (valid && gl == 0) {
     double tx, ty;
@@ -330,7 +342,7 @@ __device__ void gather_group(const RomDev &d, const float *Phibar, const float *
     if constexpr (EXACT) {
       // C_t = Phibar_t - dt/2 sum_e G_e (Phibar_t - Phit_c)
 #pragma unroll
-      for (int m = 0; m < kSmallM; ++m) {
+      for (int m = 0; m < MB; ++m) {
         if (m < M) {
           const double jx = gsum(a.ex[m], G) * kInv2PiD, jy = gsum(a.ey[m], G) * kInv2PiD;
           if (valid && gl == (m & (G - 1))) {
@@ -371,7 +383,7 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63;
   if (wave >= d.ns) return;
   gather_group<EXACT>(d, d.Phibar, d.xbar0, nullptr, wave, true, lane, 64, xh, xf, xbar_prev, fbar_prev, xbar, fbar,
-                      rbar, 1, C, d.M);
+                      rbar, 1, C, d.M, d.ubar);
 }
 
 // Point form of the hook (paper Jacobian).  First every coordinate of the
@@ -519,24 +531,58 @@ __device__ __forceinline__ double sum8(double v) {
   return v;
 }
 
+// Split runs (paper Jacobian, arrays in LDS): the W workgroups of one query
+// each hold a contiguous slice of the entry rows in LDS (slice w: entries
+// [w L, (w + 1) L)).  Per HyperPair evaluation b every workgroup sums its
+// slice's terms for each target whose list meets the slice and publishes the
+// five sums, each as one 64-bit word (FP32 bits, and b + 1 in the high half);
+// then it reads, for every target, the words of the slices its list spans,
+// until all carry b + 1, and adds them in slice order.  The tags make each
+// word its own completion flag: no counter, no fences.  Words alternate
+// between two buffers by the parity of b: a workgroup writes evaluation b + 2
+// only after it has read everyone's b + 1, which each wrote after reading b.
+// Each workgroup then runs the whole solve itself.  The workgroups run the
+// same instructions on the same data, so their xhat, and with it every
+// convergence decision, agree bit for bit, and they take part in the same
+// evaluations.  A workgroup whose wait fails max_polls checks (the grid is
+// launched cooperatively, so every workgroup is resident and a wait ends)
+// raises the abort flag; every workgroup of the launch then leaves at its
+// next wait, and the query reports iters = -1.
+struct SplitArgs {
+  int W = 1;                           // workgroups per query
+  int L = 0;                           // entries per slice, ceil(nnz / W)
+  unsigned long long *part = nullptr;  // [2][nq][W][5 ns] tagged slice sums, zero at launch
+  unsigned *abort = nullptr;           // [1] zero at launch
+  unsigned max_polls = 0;              // failed checks of one wait before the abort
+  int nt = 0;                          // most targets whose lists meet one slice
+};
+constexpr unsigned kSplitPolls = 1u << 20;  // about a second of polling
+
 // LDSA: the arrays' LDS copies are used (a compile-time choice, so every
 // access to them is an LDS instruction); otherwise they are read in place.
-template <bool EXACT, bool LDSA>
+// SPLIT: the split form above (requires !EXACT and LDSA).  MB: the basis
+// bound (M <= MB).
+template <bool EXACT, bool LDSA, bool SPLIT, int MB>
 __global__ void __launch_bounds__(kRunThreads)
     rom_run_kernel(RomDev d, int nsteps, int entry_par, const float *__restrict__ gtq,
-                   double *__restrict__ xhat, double *__restrict__ hist, int *__restrict__ iters) {
+                   double *__restrict__ xhat, double *__restrict__ hist, int *__restrict__ iters, SplitArgs sp) {
+  static_assert(!SPLIT || (!EXACT && LDSA), "split runs use the paper Jacobian with LDS copies");
   __shared__ double xh[kSmallM];
   __shared__ float xf[kSmallM];
   __shared__ double rr[kSmallMr], gq[kSmallM], xs[kSmallM], gvec[kSmallM];
   __shared__ double s_eps, s_g1, s_gn;
-  extern __shared__ double dyn[];
+  __shared__ int s_ab[2];  // split: the abort flag as read at each poll (alternating)
+  extern __shared__ __align__(16) double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kRunThreads / 64;
+  // query and slice of this workgroup
+  const int qi = SPLIT ? (int)blockIdx.x / sp.W : (int)blockIdx.x;
+  const int wpart = SPLIT ? (int)blockIdx.x - qi * sp.W : 0;
   const int M = d.M, Mr = d.Mr, nd = d.nd, ns = d.ns, ldc = d.ldc, M1 = M + 1;
   const int lg = M1;  // row stride of G'
   const double hdt = 0.5 * (double)d.dt;
   // G' = A [C | rbar] (Mr x (M + 1)) and the Gauss-Jordan tableau [N | I]
-  // (rows padded to kSmallM, columns to 64: one column per lane of a wave) at
-  // the front of the dynamic LDS
+  // (rows padded to MB, columns to 64: one column per lane of a wave) at the
+  // front of the dynamic LDS
   double *Gp = dyn, *T0 = Gp + (size_t)Mr * lg;
 
   // A, [C | rbar], fbar, fbar_prev, xbar_prev, the per-target 2x2 blocks,
@@ -547,11 +593,18 @@ __global__ void __launch_bounds__(kRunThreads)
          *xcur = nullptr;
   float *ct = nullptr;
   const float *gt = nullptr;
-  xhat += (size_t)blockIdx.x * M;
-  if (hist) hist += (size_t)blockIdx.x * nsteps * M;
-  if (iters) iters += (size_t)blockIdx.x * nsteps;
+  const double *ubar = d.ubar;
+  double *psum = nullptr;            // split: [5][ns] sums over all slices
+  int *wsp = nullptr;                // split: [ns][4] first and last slice of each target's list, and
+                                     // the list's local range in this slice (empty when it misses it)
+  float *wp = nullptr;               // split: [8 waves][sp.nt][5] each wave's sums per slice target
+  const float *rows = nullptr;       // split: this slice's entry rows, chunk-major, stride sp.L
+  int e0 = 0, ln = 0, ta = 0, tb = -1;  // split: entries [e0, e0 + ln), of targets ta..tb
+  xhat += (size_t)qi * M;
+  if (hist) hist += (size_t)qi * nsteps * M;
+  if (iters) iters += (size_t)qi * nsteps;
   if constexpr (LDSA) {
-    double *p = T0 + (size_t)kSmallM * 64;
+    double *p = T0 + (size_t)MB * 64;
     double *Al = p; p += (size_t)Mr * nd;
     Cp = p; p += (size_t)nd * ldc;
     fbar = p; p += nd;
@@ -559,15 +612,74 @@ __global__ void __launch_bounds__(kRunThreads)
     xbar_prev = p; p += nd;
     bt = p; p += 3 * (size_t)ns;
     xcur = p; p += nd;
+    {
+      double *ul = p;
+      p += nd;
+      for (int t = tid; t < nd; t += kRunThreads) ul[t] = d.ubar[t];
+      ubar = ul;
+    }
+    if constexpr (SPLIT) {
+      psum = p;
+      p += 5 * (size_t)ns;
+      wsp = reinterpret_cast<int *>(p);
+      p += 2 * (size_t)ns;
+    }
     float *f = reinterpret_cast<float *>(p);
     float *Pl = f; f += (size_t)nd * M;
     float *xl = f; f += nd;
-    ct = f; f += entry_par ? 5 * (size_t)d.nnz : 0;
+    ct = f; f += SPLIT ? 5 * (size_t)sp.L : entry_par ? 5 * (size_t)d.nnz : 0;
+    if constexpr (SPLIT) {
+      wp = f;
+      f += (size_t)nwaves * sp.nt * 5;
+    }
     if (gtq) {
       // this query's clustered circulations (one workgroup per query)
       float *gl_ = f;
-      for (int t = tid; t < d.Nc; t += kRunThreads) gl_[t] = gtq[(size_t)blockIdx.x * d.Nc + t];
+      for (int t = tid; t < d.Nc; t += kRunThreads) gl_[t] = gtq[(size_t)qi * d.Nc + t];
       gt = gl_;
+      f += d.Nc;
+    }
+    if constexpr (SPLIT) {
+      // the slice's rows, 16-byte aligned, chunk c of local entry l at
+      // float4 index c * L + l (the table's chunk-major form)
+      // (offsets from the 16-byte aligned base, so the pointer stays an LDS one)
+      const size_t fo = (reinterpret_cast<char *>(f) - reinterpret_cast<char *>(dyn) + 15) & ~size_t(15);
+      float4 *r4 = reinterpret_cast<float4 *>(reinterpret_cast<char *>(dyn) + fo);
+      const int nnz = (int)d.nnz;
+      e0 = min(wpart * sp.L, nnz);
+      ln = min(sp.L, nnz - e0);
+      const int nch = d.ew / 4;
+      const float4 *g4 = reinterpret_cast<const float4 *>(d.ent);
+      for (int t = tid; t < nch * ln; t += kRunThreads) {
+        const int c = t / ln, l = t - c * ln;
+        r4[(size_t)c * sp.L + l] = g4[(size_t)c * nnz + e0 + l];
+      }
+      rows = reinterpret_cast<const float *>(r4);
+      for (int t = tid; t < ns; t += kRunThreads) {
+        const int a = d.off[t], b = d.off[t + 1];
+        wsp[4 * t] = b > a ? a / sp.L : 1;
+        wsp[4 * t + 1] = b > a ? (b - 1) / sp.L : 0;
+        wsp[4 * t + 2] = min(max(a - e0, 0), ln);
+        wsp[4 * t + 3] = min(max(b - e0, 0), ln);
+      }
+      if (ln > 0) {
+        // first target whose list ends past e0, last one whose list starts
+        // before e0 + ln
+        int lo = 0, hi = ns - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (d.off[mid + 1] > e0) hi = mid;
+          else lo = mid + 1;
+        }
+        ta = lo;
+        hi = ns - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (d.off[mid] < e0 + ln) lo = mid;
+          else hi = mid - 1;
+        }
+        tb = lo;
+      }
     }
     for (int t = tid; t < Mr * nd; t += kRunThreads) Al[t] = d.A[t];
     for (int t = tid; t < nd * M; t += kRunThreads) Pl[t] = d.Phibar[t];
@@ -584,10 +696,108 @@ __global__ void __launch_bounds__(kRunThreads)
   __syncthreads();
   // targets are taken by groups of G lanes, 64 / G per wave
   const int G = d.glanes, tpw = 64 / G, gl = lane & (G - 1), slot = lane / G;
+
+  // split: the slice's terms at xhat, its per-target sums, the barrier, then
+  // psum[k * ns + t] = the sums of all slices (FP64, added in slice order).
+  // Returns false when the launch is aborted.
+  int nbar = 0;
+  auto split_sums = [&]() -> bool {
+    const int L = sp.L;
+    for (int l = tid; l < ln; l += kRunThreads) {
+      float v[4 + 2 * MB];
+      load_entry<true>(rows, d.ew, L, l, v);
+      GatherAcc<false> a;
+      entry_terms<false>(v, nullptr, 0, 0, xf, gt, M, d.d2, a);
+      ct[l] = a.fx;
+      ct[L + l] = a.fy;
+      ct[2 * L + l] = a.ba;
+      ct[3 * L + l] = a.bb;
+      ct[4 * L + l] = a.bc;
+    }
+    __syncthreads();
+    // this evaluation's buffer; words of slice w of this query at [w][5 ns]
+    unsigned long long *par = sp.part + ((size_t)(nbar & 1) * gridDim.x + (size_t)qi * sp.W) * 5 * (size_t)ns;
+    const unsigned long long tag = (unsigned long long)(unsigned)(nbar + 1) << 32;
+    unsigned long long *mine = par + (size_t)wpart * 5 * ns;
+    // each wave sums its share [c0, c1) of the slice per target; the waves'
+    // sums are then added in wave order
+    {
+      const int cw = (ln + nwaves - 1) / nwaves, c0 = min(wave * cw, ln), c1 = min(c0 + cw, ln);
+      for (int i = 0; i <= tb - ta; ++i) {
+        const int t = ta + i, r0 = max(wsp[4 * t + 2], c0), r1 = min(wsp[4 * t + 3], c1);
+        float sv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        if (r0 < r1) {
+          for (int e = r0 + lane; e < r1; e += 64)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sv[k] += ct[k * L + e];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) sv[k] = gsum(sv[k], 64);
+        }
+        if (lane == 0)
+#pragma unroll
+          for (int k = 0; k < 5; ++k) wp[((size_t)wave * sp.nt + i) * 5 + k] = sv[k];
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < 5 * (tb - ta + 1); q += kRunThreads) {
+      const int i = q / 5, k = q - 5 * i;
+      float sm = 0.f;
+      for (int v = 0; v < nwaves; ++v) sm += wp[((size_t)v * sp.nt + i) * 5 + k];
+      __hip_atomic_store(mine + k * ns + ta + i, tag | __float_as_uint(sm), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // every target's sums from the slices its list spans, in slice order,
+    // once all of them carry this evaluation's tag
+    for (unsigned polls = 0;; ++polls) {
+      if (tid == 0) s_ab[polls & 1] = (int)__hip_atomic_load(sp.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int ok = 1;
+      for (int q = tid; q < 5 * ns; q += kRunThreads) {
+        const int t = q - (q / ns) * ns;
+        double s = 0.0;
+        for (int w = wsp[4 * t]; w <= wsp[4 * t + 1]; ++w) {
+          const unsigned long long v =
+              __hip_atomic_load(par + (size_t)w * 5 * ns + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok &= (v >> 32) == (tag >> 32);
+          s += (double)__uint_as_float((unsigned)v);
+        }
+        psum[q] = s;
+      }
+      if (__syncthreads_and(ok)) break;
+      if (s_ab[polls & 1] || polls + 1 >= sp.max_polls) {
+        if (tid == 0) __hip_atomic_store(sp.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ++nbar;
+    return true;
+  };
+  // an aborted split launch: the query reports iters = -1 and a NaN xhat
+  auto split_abort = [&]() {
+    if (wpart != 0) return;
+    if (iters)
+      for (int s = tid; s < nsteps; s += kRunThreads) iters[s] = -1;
+    if (tid < M) xhat[tid] = __builtin_nan("");
+  };
+
   // previous-step terms for the first step: HyperPair at the initial xhat
-  for (int base = wave * tpw; base < ns; base += nwaves * tpw)
-    gather_group<EXACT>(d, Phibar, xbar0, gt, base + slot, base + slot < ns, gl, G, xh, xf, nullptr, nullptr,
-                        xbar_prev, fbar_prev, nullptr, 0, nullptr, 0);
+  if constexpr (SPLIT) {
+    if (!split_sums()) {
+      split_abort();
+      return;
+    }
+    for (int q = tid; q < nd; q += kRunThreads) {
+      const int i = q < ns ? q : q - ns;
+      double tx, ty;
+      sampled_position(Phibar, xbar0, M, ns, i, xh, tx, ty);
+      xbar_prev[q] = q < ns ? tx : ty;
+      fbar_prev[q] = psum[q] * kInv2PiD + ubar[q];
+    }
+  } else {
+    for (int base = wave * tpw; base < ns; base += nwaves * tpw)
+      gather_group<EXACT, MB>(d, Phibar, xbar0, gt, base + slot, base + slot < ns, gl, G, xh, xf, nullptr, nullptr,
+                              xbar_prev, fbar_prev, nullptr, 0, nullptr, 0, ubar);
+  }
   __syncthreads();
 
   const int tr = (Mr + 15) / 16, tc = (M1 + 15) / 16;
@@ -596,20 +806,27 @@ __global__ void __launch_bounds__(kRunThreads)
     int k = 1;
     for (;;) {
       // ---- HyperPair: velocity rows, residual rows (column M of [C | rbar]) and C
-      if (!EXACT && entry_par) {
-        // one thread per entry; the five per-entry terms go to LDS.  The
-        // sampled rows at the current xhat are formed alongside.
-        for (int e = tid; e < nnz; e += kRunThreads) {
-          float v[kMaxEw];
-          load_entry<true>(d.ent, d.ew, d.nnz, e, v);
-          GatherAcc<false> a;
-          entry_terms<false>(v, nullptr, 0, 0, xf, gt, M, d.d2, a);
-          ct[e] = a.fx;
-          ct[nnz + e] = a.fy;
-          ct[2 * nnz + e] = a.ba;
-          ct[3 * nnz + e] = a.bb;
-          ct[4 * nnz + e] = a.bc;
+      if (!EXACT && (SPLIT || entry_par)) {
+        if constexpr (SPLIT) {
+          if (!split_sums()) {
+            split_abort();
+            return;
+          }
+        } else {
+          // one thread per entry; the five per-entry terms go to LDS
+          for (int e = tid; e < nnz; e += kRunThreads) {
+            float v[4 + 2 * MB];
+            load_entry<true>(d.ent, d.ew, d.nnz, e, v);
+            GatherAcc<false> a;
+            entry_terms<false>(v, nullptr, 0, 0, xf, gt, M, d.d2, a);
+            ct[e] = a.fx;
+            ct[nnz + e] = a.fy;
+            ct[2 * nnz + e] = a.ba;
+            ct[3 * nnz + e] = a.bb;
+            ct[4 * nnz + e] = a.bc;
+          }
         }
+        // the sampled rows at the current xhat
         for (int q = tid; q < nd; q += kRunThreads) {
           double x = xbar0[q];
           const float *ph = Phibar + (size_t)q * M;
@@ -619,8 +836,8 @@ __global__ void __launch_bounds__(kRunThreads)
         __syncthreads();
         // per-target sums (one thread per target for short lists, else
         // groups of G lanes), residual rows and the 2x2 blocks
-        auto finish = [&](int t, float s0, float s1, float s2, float s3, float s4) {
-          const double Fx = s0 * kInv2PiD + d.ubar[t], Fy = s1 * kInv2PiD + d.ubar[ns + t];
+        auto finish = [&](int t, double s0, double s1, double s2, double s3, double s4) {
+          const double Fx = s0 * kInv2PiD + ubar[t], Fy = s1 * kInv2PiD + ubar[ns + t];
           fbar[t] = Fx;
           fbar[ns + t] = Fy;
           Cp[(size_t)t * ldc + M] = (xcur[t] - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
@@ -629,7 +846,10 @@ __global__ void __launch_bounds__(kRunThreads)
           bt[3 * t + 1] = s3 * kInv2PiD;
           bt[3 * t + 2] = s4 * kInv2PiD;
         };
-        if (d.maxlen <= 64) {
+        if constexpr (SPLIT) {
+          for (int t = tid; t < ns; t += kRunThreads)
+            finish(t, psum[t], psum[ns + t], psum[2 * ns + t], psum[3 * ns + t], psum[4 * ns + t]);
+        } else if (d.maxlen <= 64) {
           for (int t = tid; t < ns; t += kRunThreads) {
             float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
             const int e1 = d.off[t + 1];
@@ -676,8 +896,8 @@ __global__ void __launch_bounds__(kRunThreads)
         }
       } else {
         for (int base = wave * tpw; base < ns; base += nwaves * tpw)
-          gather_group<EXACT>(d, Phibar, xbar0, gt, base + slot, base + slot < ns, gl, G, xh, xf, xbar_prev,
-                              fbar_prev, nullptr, fbar, Cp + M, ldc, Cp, ldc);
+          gather_group<EXACT, MB>(d, Phibar, xbar0, gt, base + slot, base + slot < ns, gl, G, xh, xf, xbar_prev,
+                                  fbar_prev, nullptr, fbar, Cp + M, ldc, Cp, ldc, ubar);
       }
       __syncthreads();
       // ---- G' = A [C | rbar] on the matrix cores (Mr x (M + 1))
@@ -707,7 +927,7 @@ __global__ void __launch_bounds__(kRunThreads)
         }
       }
       // identity block and zero padding of the tableau
-      for (int t = tid; t < kSmallM * 64; t += kRunThreads) {
+      for (int t = tid; t < MB * 64; t += kRunThreads) {
         const int i = t >> 6, j = t & 63;
         if (i >= M || j >= M) T0[t] = (i < M && j - M == i) ? 1.0 : 0.0;
       }
@@ -724,11 +944,11 @@ __global__ void __launch_bounds__(kRunThreads)
         const double gv = lane < M ? gvec[lane] : 0.0;
         const double gn = sqrt(wsumd(gv * gv));
         if (lane == 0) s_gn = gn;
-        double col[kSmallM];
+        double col[MB];
 #pragma unroll
-        for (int u = 0; u < kSmallM; ++u) col[u] = T0[u * 64 + lane];
+        for (int u = 0; u < MB; ++u) col[u] = T0[u * 64 + lane];
 #pragma unroll
-        for (int kk = 0; kk < kSmallM; ++kk) {
+        for (int kk = 0; kk < MB; ++kk) {
           if (kk < M) {
             const double piv = lane_d(col[kk], kk);
             double ip = 0.0;
@@ -741,7 +961,7 @@ __global__ void __launch_bounds__(kRunThreads)
             const double rk = col[kk] * ip;
             // rows in blocks of 8; blocks wholly past M are padding
 #pragma unroll
-            for (int i0 = 0; i0 < kSmallM; i0 += 8) {
+            for (int i0 = 0; i0 < MB; i0 += 8) {
               if (i0 < M) {
 #pragma unroll
                 for (int u = i0; u < i0 + 8; ++u) {
@@ -753,7 +973,7 @@ __global__ void __launch_bounds__(kRunThreads)
           }
         }
 #pragma unroll
-        for (int u = 0; u < kSmallM; ++u) T0[u * 64 + lane] = col[u];
+        for (int u = 0; u < MB; ++u) T0[u * 64 + lane] = col[u];
       }
       __syncthreads();
       // ---- x = N^+ g, then one refinement step: r' = b - G x, g' = G^T r',
@@ -810,8 +1030,8 @@ __global__ void __launch_bounds__(kRunThreads)
       if (!(s_eps > d.tol) || k > d.max_iter) break;
       __syncthreads();  // s_eps read by everyone before the next write
     }
-    if (tid < M && hist) hist[(size_t)step * M + tid] = xh[tid];
-    if (tid == 0 && iters) iters[step] = k - 1;
+    if (wpart == 0 && tid < M && hist) hist[(size_t)step * M + tid] = xh[tid];
+    if (wpart == 0 && tid == 0 && iters) iters[step] = k - 1;
     // previous-step terms: sampled rows at the accepted xhat, velocity of
     // the last HyperPair evaluation
     for (int q = tid; q < nd; q += kRunThreads) {
@@ -823,7 +1043,7 @@ __global__ void __launch_bounds__(kRunThreads)
     }
     __syncthreads();
   }
-  if (tid < M) xhat[tid] = xh[tid];
+  if (wpart == 0 && tid < M) xhat[tid] = xh[tid];
 }
 
 // ----------------------------------------------------------- larger bases
@@ -1296,14 +1516,57 @@ __global__ void __launch_bounds__(kRunThreads)
 // dynamic LDS of the run kernel: G' and the tableaux always; the copies of
 // the arrays in the LDS-copy variant; the per-entry terms only in the entry-parallel
 // gather
+// the basis bound of the small kernel that runs a basis of M modes
+int mb_of(int M) { return M <= 8 ? 8 : M <= 16 ? 16 : kSmallM; }
+
 size_t solve_lds_bytes(int M, int Mr) {
-  return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)kSmallM * 64);
+  return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)mb_of(M) * 64);
+}
+
+// the small run kernel for a basis of M modes
+template <int MB>
+const void *run_kernel_mb(bool exact, bool ldsa, bool split) {
+  if (split) return reinterpret_cast<const void *>(rom_run_kernel<false, true, true, MB>);
+  if (exact)
+    return ldsa ? reinterpret_cast<const void *>(rom_run_kernel<true, true, false, MB>)
+                : reinterpret_cast<const void *>(rom_run_kernel<true, false, false, MB>);
+  return ldsa ? reinterpret_cast<const void *>(rom_run_kernel<false, true, false, MB>)
+              : reinterpret_cast<const void *>(rom_run_kernel<false, false, false, MB>);
+}
+const void *run_kernel(int M, bool exact, bool ldsa, bool split) {
+  switch (mb_of(M)) {
+    case 8: return run_kernel_mb<8>(exact, ldsa, split);
+    case 16: return run_kernel_mb<16>(exact, ldsa, split);
+    default: return run_kernel_mb<kSmallM>(exact, ldsa, split);
+  }
 }
 
 size_t run_lds_bytes(int M, int Mr, int nd, int ns, int ldc, int64_t nnz, bool entry_par, int64_t nc_table) {
   return solve_lds_bytes(M, Mr) +
-         sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 4 * (size_t)nd + 3 * (size_t)ns) +
+         sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 5 * (size_t)nd + 3 * (size_t)ns) +
          sizeof(float) * ((size_t)nd * (M + 1) + (entry_par ? 5 * (size_t)nnz : 0) + (size_t)nc_table);
+}
+// split runs: the same copies without the whole table's terms, plus the
+// slice's terms (5 L floats), its rows (ew / 4 float4 chunks per entry,
+// 16-byte aligned), the summed slices (5 ns doubles), each list's slice span
+// and local range (4 ns ints) and the waves' sums (5 nt floats per wave)
+size_t split_lds_bytes(const RomDev &d, int L, int nt, int64_t nc_table) {
+  return run_lds_bytes(d.M, d.Mr, d.nd, d.ns, d.ldc, d.nnz, false, nc_table) + sizeof(double) * 7 * (size_t)d.ns +
+         sizeof(float) * 5 * ((size_t)L + (kRunThreads / 64) * (size_t)nt) + 16 + sizeof(float) * (size_t)d.ew * L;
+}
+
+// the most targets whose lists meet one slice of L entries
+int slice_targets(const std::vector<int> &off, int64_t nnz, int L) {
+  int best = 0;
+  const int ns = int(off.size()) - 1;
+  for (int64_t e0 = 0; e0 < nnz; e0 += L) {
+    const int64_t e1 = std::min<int64_t>(nnz, e0 + L);
+    // targets t with off[t] < e1 and off[t + 1] > e0
+    const int ta = int(std::upper_bound(off.begin() + 1, off.end(), int(e0)) - (off.begin() + 1));
+    const int tb = int(std::lower_bound(off.begin(), off.end() - 1, int(e1)) - off.begin()) - 1;
+    best = std::max(best, std::min(tb, ns - 1) - ta + 1);
+  }
+  return best;
 }
 
 // Gamma~ of every surrogate for every query: the sum of its members' Gamma
@@ -1330,6 +1593,10 @@ struct ptrom_rom {
   int64_t n_bodies = 0;
   size_t max_dyn_lds = 0;      // dynamic LDS the run kernel may take on this device
   size_t max_dyn_lds_big = 0;  // same for the larger-basis kernel
+  int coop = 0;                // the device takes cooperative launches
+  int split = 0;               // workgroups per query of split runs: 0 automatic, 1 never
+  unsigned split_polls = 0;    // failed barrier checks before a split run aborts (0: kSplitPolls)
+  std::vector<int> off;        // host copy of the list offsets [ns + 1]
 };
 
 extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptrom_rom **out) {
@@ -1450,6 +1717,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
 
   auto rom = new ptrom_rom();
   rom->ctx = ctx;
+  rom->off = off32;
   {
     // dynamic LDS the run kernel may request: the device's per-workgroup
     // limit minus the kernel's static LDS
@@ -1457,10 +1725,9 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
     if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
       maxsh = 64 * 1024;
     size_t stat = 0;
-    const void *kernels[4] = {reinterpret_cast<const void *>(rom_run_kernel<false, true>),
-                              reinterpret_cast<const void *>(rom_run_kernel<true, true>),
-                              reinterpret_cast<const void *>(rom_run_kernel<false, false>),
-                              reinterpret_cast<const void *>(rom_run_kernel<true, false>)};
+    std::vector<const void *> kernels;
+    for (int Mq : {8, 16, kSmallM})
+      for (int v = 0; v < 5; ++v) kernels.push_back(run_kernel(Mq, v & 1, v & 2, v == 4));
     for (const void *k : kernels) {
       hipFuncAttributes fa{};
       if (hipFuncGetAttributes(&fa, k) == hipSuccess) stat = std::max(stat, fa.sharedSizeBytes);
@@ -1488,6 +1755,8 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       }
     rom->max_dyn_lds_big = dynb;
     rom->max_dyn_lds = dyn;
+    if (hipDeviceGetAttribute(&rom->coop, hipDeviceAttributeCooperativeLaunch, ctx->device) != hipSuccess)
+      rom->coop = 0;
   }
   RomDev &d = rom->d;
   d.M = M; d.Mr = s.Mr; d.ns = s.ns; d.nd = nd; d.jac_mode = s.jac_mode; d.max_iter = s.max_iter;
@@ -1601,8 +1870,49 @@ extern "C" int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const dou
 
 namespace {
 
+__global__ void split_zero_kernel(unsigned *p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// Workgroups per query of a split run (paper Jacobian, small basis, arrays in
+// LDS): about kSplitEntries entries per slice, at most kSplitMaxW, widened
+// until the slice fits next to the other LDS copies; 1 (no split) when the
+// lists are short, the device takes no cooperative launch, the grid would
+// not be resident at once, or the barrier count would pass 2^32.  *lds: the
+// split launch's dynamic LDS.
+constexpr int64_t kSplitEntries = 1024;
+constexpr int kSplitMaxW = 64;
+int split_width(ptrom_rom *rom, int nq, int nsteps, int64_t table, int *W_out, size_t *lds) {
+  const RomDev &d = rom->d;
+  *W_out = 1;
+  if (rom->split == 1 || !rom->coop || d.nnz < 1 || d.jac_mode != PTROM_JAC_PAPER || d.M > kSmallM ||
+      d.Mr > kSmallMr || nq < 1)
+    return PTROM_OK;
+  int W = rom->split >= 2 ? rom->split : int(std::min<int64_t>(16, (d.nnz + kSplitEntries - 1) / kSplitEntries));
+  if (W < 2) return PTROM_OK;
+  auto L = [&](int w) { return int((d.nnz + w - 1) / w); };
+  auto bytes_at = [&](int w) { return split_lds_bytes(d, L(w), slice_targets(rom->off, d.nnz, L(w)), table); };
+  while (W <= kSplitMaxW && bytes_at(W) > rom->max_dyn_lds) ++W;
+  if (W > kSplitMaxW) return PTROM_OK;
+  const int64_t barriers = 1 + int64_t(nsteps) * d.max_iter;
+  if (int64_t(W) * barriers >= (int64_t(1) << 32) - 1) return PTROM_OK;
+  const size_t bytes = bytes_at(W);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, run_kernel(d.M, false, true, true),
+                                                   kRunThreads, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return PTROM_OK;
+  }
+  if (int64_t(W) * nq > int64_t(per_cu) * rom->ctx->num_cus) return PTROM_OK;
+  *W_out = W;
+  *lds = bytes;
+  return PTROM_OK;
+}
+
 // One launch of the device-resident loop over nq queries (one workgroup
-// each); gtq NULL means the training circulations of the entries.
+// each, or W per query in split runs); gtq NULL means the training
+// circulations of the entries.
 int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xhat, double *xhat_hist,
                int32_t *iters, hipStream_t st) {
   ptrom_ctx *ctx = rom->ctx;
@@ -1646,22 +1956,43 @@ int launch_run(ptrom_rom *rom, int nq, const float *gtq, int nsteps, double *xha
     if (nq != 1 || gtq)
       return ctx->fail(PTROM_EINVAL, "batched queries need the run arrays to fit in LDS (sample set too large)");
   }
-  const size_t shmem = use_lds ? lds : solve_lds_bytes(d.M, d.Mr);
   const bool ex = d.jac_mode == PTROM_JAC_EXACT;
+  if (!ex && use_lds) {
+    int W = 1;
+    size_t slds = 0;
+    if (int rc = split_width(rom, nq, nsteps, table, &W, &slds)) return rc;
+    if (W > 1) {
+      // tagged slice sums (two parities) and the abort flag in the
+      // workspace, zeroed before the launch (tags start at 1)
+      SplitArgs sp;
+      sp.W = W;
+      sp.L = int((d.nnz + W - 1) / W);
+      sp.nt = slice_targets(rom->off, d.nnz, sp.L);
+      const size_t npart = 2 * size_t(nq) * W * 5 * size_t(d.ns);
+      const size_t words = 2 * npart + 1;  // 32-bit words, abort flag last
+      if (int rc = ctx->reserve(words * sizeof(unsigned) + 256)) return rc;
+      unsigned *w32 = static_cast<unsigned *>(ctx->ws);
+      sp.part = reinterpret_cast<unsigned long long *>(w32);
+      sp.abort = w32 + 2 * npart;
+      sp.max_polls = rom->split_polls ? rom->split_polls : kSplitPolls;
+      const int zb = int(std::min<size_t>(1024, (words + 255) / 256));
+      hipLaunchKernelGGL(split_zero_kernel, dim3(zb), dim3(256), 0, st, w32, (long long)words);
+      PTROM_CHECK_HIP(ctx, hipGetLastError());
+      int ep = 0;
+      void *args[] = {const_cast<RomDev *>(&d), &nsteps, &ep, &gtq, &xhat, &xhat_hist, &iters, &sp};
+      PTROM_CHECK_HIP(ctx, hipLaunchCooperativeKernel(run_kernel(d.M, false, true, true),
+                                                      dim3(unsigned(nq) * W), dim3(kRunThreads), args,
+                                                      unsigned(slds), st));
+      return PTROM_OK;
+    }
+  }
+  const size_t shmem = use_lds ? lds : solve_lds_bytes(d.M, d.Mr);
   const int ep = ex ? 0 : entry_par;
-  if (ex && use_lds)
-    hipLaunchKernelGGL((rom_run_kernel<true, true>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq, xhat,
-                       xhat_hist, iters);
-  else if (ex)
-    hipLaunchKernelGGL((rom_run_kernel<true, false>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq,
-                       xhat, xhat_hist, iters);
-  else if (use_lds)
-    hipLaunchKernelGGL((rom_run_kernel<false, true>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq,
-                       xhat, xhat_hist, iters);
-  else
-    hipLaunchKernelGGL((rom_run_kernel<false, false>), dim3(nq), dim3(kRunThreads), shmem, st, d, nsteps, ep, gtq,
-                       xhat, xhat_hist, iters);
-  PTROM_CHECK_HIP(ctx, hipGetLastError());
+  SplitArgs one;
+  int epv = ep;
+  void *args[] = {const_cast<RomDev *>(&d), &nsteps, &epv, &gtq, &xhat, &xhat_hist, &iters, &one};
+  PTROM_CHECK_HIP(ctx, hipLaunchKernel(run_kernel(d.M, ex, use_lds != 0, false), dim3(nq), dim3(kRunThreads), args,
+                                       shmem, st));
   return PTROM_OK;
 }
 
@@ -1675,6 +2006,29 @@ extern "C" int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *x
   if (!xhat || nsteps < 0) return ctx->fail(PTROM_EINVAL, "xhat required and nsteps >= 0");
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(PTROM_EHIP, "hipSetDevice");
   return launch_run(rom, 1, nullptr, nsteps, xhat, xhat_hist, iters, (hipStream_t)stream);
+}
+
+extern "C" int ptrom_rom_set_split(ptrom_rom *rom, int workgroups, uint32_t max_polls) {
+  if (!rom) return PTROM_EINVAL;
+  rom->ctx->err.clear();
+  if (workgroups < 0 || workgroups > kSplitMaxW)
+    return rom->ctx->fail(PTROM_EINVAL, "workgroups per query must be 0 (automatic) .. 64");
+  rom->split = workgroups;
+  rom->split_polls = max_polls;
+  return PTROM_OK;
+}
+
+extern "C" int ptrom_rom_split_plan(ptrom_rom *rom, int batched_nq, int nsteps, int32_t *workgroups) {
+  if (!rom) return PTROM_EINVAL;
+  ptrom_ctx *ctx = rom->ctx;
+  ctx->err.clear();
+  if (!workgroups || batched_nq < 0 || nsteps < 0) return ctx->fail(PTROM_EINVAL, "workgroups required, nq and nsteps >= 0");
+  int W = 1;
+  size_t lds = 0;
+  const int nq = batched_nq > 0 ? batched_nq : 1;
+  if (int rc = split_width(rom, nq, nsteps, batched_nq > 0 ? rom->d.Nc : 0, &W, &lds)) return rc;
+  *workgroups = W;
+  return PTROM_OK;
 }
 
 extern "C" int ptrom_rom_members(ptrom_rom *rom, int64_t n, const int64_t *mem_off, const int64_t *mem_ids) {

@@ -89,6 +89,8 @@ SIGNATURES = {
     "ptrom_cluster_fetch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptrom_cluster_destroy": (None, [_vp]),
     "ptrom_cluster_members": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), _vp, _vp]),
+    "ptrom_rom_set_split": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint32]),
+    "ptrom_rom_split_plan": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp]),
     "ptrom_rom_members": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "ptrom_rom_reassign": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "ptrom_rom_run_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
@@ -499,6 +501,19 @@ class Rom:
                                               _ptr(iters, torch.int32, nsteps, "iters"), _stream(xhat)),
                "ptrom_rom_run")
         return xhat
+
+    def set_split(self, workgroups, max_polls=0):
+        """Workgroups per query of the small-basis paper-Jacobian runs (0 automatic, 1 none);
+        max_polls: failed barrier checks before a split run aborts (0 default)."""
+        _check(self._ctx, lib().ptrom_rom_set_split(self._h, int(workgroups), int(max_polls)),
+               "ptrom_rom_set_split")
+
+    def split_plan(self, nsteps, batched_nq=0):
+        """Workgroups per query that run (batched_nq = 0) or run_batched would use."""
+        w = ctypes.c_int32(0)
+        _check(self._ctx, lib().ptrom_rom_split_plan(self._h, int(batched_nq), int(nsteps), ctypes.byref(w)),
+               "ptrom_rom_split_plan")
+        return int(w.value)
 
     def set_members(self, mem_off, mem_ids, n):
         """Bodies of each surrogate (CSR, host), for parametric queries."""

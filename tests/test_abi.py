@@ -88,7 +88,8 @@ def test_binding_argument_types_match_the_header():
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     decls = dict(re.findall(r"\b(ptrom_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S))
     scalar = {"float": ctypes.c_float, "double": ctypes.c_double, "int": ctypes.c_int, "int32_t": ctypes.c_int32,
-              "int64_t": ctypes.c_int64, "uint64_t": ctypes.c_uint64, "size_t": ctypes.c_size_t}
+              "int64_t": ctypes.c_int64, "uint32_t": ctypes.c_uint32, "uint64_t": ctypes.c_uint64,
+              "size_t": ctypes.c_size_t}
     for name, params in decls.items():
         params = " ".join(params.split())
         if params in ("", "void"):
