@@ -586,8 +586,11 @@ __global__ void __launch_bounds__(kRunThreads)
   double *Gp = dyn, *T0 = Gp + (size_t)Mr * lg;
 
   // A, [C | rbar], fbar, fbar_prev, xbar_prev, the per-target 2x2 blocks,
-  // Phibar, xbar0 and the per-entry terms: LDS copies when they fit
+  // Phibar, xbar0 and the per-entry terms: LDS copies when they fit.  The
+  // copy of A has an odd row stride (n_d + 1 doubles), so the 16 lanes that
+  // read one matrix-core operand column hit distinct banks.
   const double *A = d.A;
+  const int lda = LDSA ? nd + 1 : nd;
   const float *Phibar = d.Phibar, *xbar0 = d.xbar0;
   double *Cp = d.C, *fbar = d.fbar, *fbar_prev = d.fbar_prev, *xbar_prev = d.xbar_prev, *bt = nullptr,
          *xcur = nullptr;
@@ -605,7 +608,7 @@ __global__ void __launch_bounds__(kRunThreads)
   if (iters) iters += (size_t)qi * nsteps;
   if constexpr (LDSA) {
     double *p = T0 + (size_t)MB * 64;
-    double *Al = p; p += (size_t)Mr * nd;
+    double *Al = p; p += (size_t)Mr * (nd + 1);
     Cp = p; p += (size_t)nd * ldc;
     fbar = p; p += nd;
     fbar_prev = p; p += nd;
@@ -681,7 +684,7 @@ __global__ void __launch_bounds__(kRunThreads)
         tb = lo;
       }
     }
-    for (int t = tid; t < Mr * nd; t += kRunThreads) Al[t] = d.A[t];
+    for (int t = tid; t < Mr * nd; t += kRunThreads) Al[(t / nd) * (nd + 1) + t % nd] = d.A[t];
     for (int t = tid; t < nd * M; t += kRunThreads) Pl[t] = d.Phibar[t];
     for (int t = tid; t < nd; t += kRunThreads) xl[t] = d.xbar0[t];
     A = Al;
@@ -904,7 +907,7 @@ __global__ void __launch_bounds__(kRunThreads)
       for (int tile = wave; tile < tr * tc; tile += nwaves) {
         const int i0 = (tile / tc) * 16, j0 = (tile % tc) * 16;
         const dbl4 acc = mfma_tile(
-            nd, lane, [&](int i, int q) { return i0 + i < Mr ? A[(size_t)(i0 + i) * nd + q] : 0.0; },
+            nd, lane, [&](int i, int q) { return i0 + i < Mr ? A[(size_t)(i0 + i) * lda + q] : 0.0; },
             [&](int q, int j) { return j0 + j < ldc ? Cp[(size_t)q * ldc + j0 + j] : 0.0; });
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1543,7 +1546,7 @@ const void *run_kernel(int M, bool exact, bool ldsa, bool split) {
 
 size_t run_lds_bytes(int M, int Mr, int nd, int ns, int ldc, int64_t nnz, bool entry_par, int64_t nc_table) {
   return solve_lds_bytes(M, Mr) +
-         sizeof(double) * ((size_t)Mr * nd + (size_t)nd * ldc + 5 * (size_t)nd + 3 * (size_t)ns) +
+         sizeof(double) * ((size_t)Mr * (nd + 1) + (size_t)nd * ldc + 5 * (size_t)nd + 3 * (size_t)ns) +
          sizeof(float) * ((size_t)nd * (M + 1) + (entry_par ? 5 * (size_t)nnz : 0) + (size_t)nc_table);
 }
 // split runs: the same copies without the whole table's terms, plus the
