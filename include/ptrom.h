@@ -310,8 +310,9 @@ int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const double *xbar_p
                         const double *fbar_prev, double *xbar, double *fbar, double *rbar,
                         double *C, ptrom_stream stream);
 
-/* nsteps online time steps in one device-resident launch (one workgroup),
- * starting from xhat (device FP64 [M], updated in place).  Per step:
+/* nsteps online time steps in one device-resident launch (one workgroup, or
+ * for long lists several, see ptrom_rom_set_split), starting from xhat
+ * (device FP64 [M], updated in place).  Per step:
  * Gauss-Newton iterations (Algorithm "Gauss-Newton") of HyperPair + the FP64
  * least-squares step dxhat = -argmin |A C nu + A rbar|, solved through the
  * normal equations (AC)^T (AC) by Gauss-Jordan elimination with one
@@ -368,7 +369,7 @@ int ptrom_rom_split_plan(ptrom_rom *rom, int batched_nq, int nsteps, int32_t *wo
  * [nq][Nc] (sums accumulated in FP64).  Asynchronous.
  *
  * ptrom_rom_run_batched: nq independent online runs in one launch, one
- * workgroup per query, query q using the circulations gt_q[q] (device FP32
+ * workgroup per query (or several, as for ptrom_rom_run), query q using the circulations gt_q[q] (device FP32
  * [nq][Nc]) and its own xhat[q] (device FP64 [nq][M], in place), xhat_hist
  * [nq][nsteps][M] and iters [nq][nsteps] (both may be NULL).  Surrogate
  * positions and rows are those of the artifacts.  EINVAL when the run arrays
