@@ -57,13 +57,22 @@ def parse():
     p.add_argument("--only", default="", help="comma list of forms to run (batched,adjoint,implicit,rom,next)")
     p.add_argument("--gather-ns", default="16,256,2048,16384",
                    help="sample-set sizes of the HyperPair gather sweep (rom form)")
+    p.add_argument("--rom-workgroups", type=int, default=0,
+                   help="workgroups per query of the small-basis online runs (0 automatic, 1 no split: "
+                        "for profilers that do not follow cooperative launches)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (HBM counter calibration)")
     return p.parse_args()
 
 
+# workgroups per query of the small-basis online runs (--rom-workgroups)
+ROM_WORKGROUPS = 0
+
+
 def main():
+    global ROM_WORKGROUPS
     args = parse()
+    ROM_WORKGROUPS = args.rom_workgroups
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -424,6 +433,7 @@ def next_rows(native, W, dev, timed):
                                   criterion=crit, theta=theta)
         t_off = time.perf_counter() - t0
         rom = native.Rom(art, tol=c3["tol"], max_iter=c3["max_iter"])
+        rom.set_split(ROM_WORKGROUPS)
         steps = c3["steps"]
         xh = torch.zeros(art["M"], dtype=torch.float64, device=dev)
         hist = torch.empty(steps * art["M"], dtype=torch.float64, device=dev)
@@ -457,6 +467,7 @@ def rom_form(native, W, dev, timed, gather_ns=(16, 256, 2048, 16384)):
                               depth=c3["depth"], pc=c3["pc"], tol=c3["tol"], max_iter=c3["max_iter"], device=dev)
     t_off = time.perf_counter() - t0
     rom = native.Rom(art, tol=c3["tol"], max_iter=c3["max_iter"])
+    rom.set_split(ROM_WORKGROUPS)
     steps = c3["steps"]
     xh = torch.zeros(art["M"], dtype=torch.float64, device=dev)
     hist = torch.empty(steps * art["M"], dtype=torch.float64, device=dev)
@@ -469,7 +480,8 @@ def rom_form(native, W, dev, timed, gather_ns=(16, 256, 2048, 16384)):
     res = {"N": cl.n, "M": art["M"], "Mr": art["Mr"], "ns": int(len(art["off"]) - 1), "Nc": int(np.asarray(art["Gt"]).size),
            "nnz": nnz, "steps": steps, "offline_seconds": t_off, "online_seconds": sec,
            "us_per_step": 1e6 * sec / steps, "us_per_gn_iteration": 1e6 * sec / max(int(its.sum()), 1),
-           "mean_gn_iterations": float(its.mean()), "pairs_per_s": float(its.sum()) * nnz / sec}
+           "mean_gn_iterations": float(its.mean()), "pairs_per_s": float(its.sum()) * nnz / sec,
+           "workgroups_per_query": rom.split_plan(steps)}
     res.update(info.get("report", {}))
     # accuracy against the trapezoid FOM snapshots (reported, not a gate)
     Phi, S = info["Phi"], info["S"]

@@ -28,7 +28,9 @@
 // they fit.  ptrom_rom_hyperpair runs the gather over many workgroups, one
 // wave per target (large sample sets).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <functional>
 #include <cstring>
 #include <vector>
 
@@ -71,7 +73,17 @@ struct RomDev {
   double *spk;  // [Nc][4] the same surrogate positions packed with Gamma~: x, y, Gamma~, 0,
                 // surrogate c at record rec[c] (Morton order of the reference positions)
   const int *rec;   // [Nc]
-  const int *erec;  // [nnz] records of each target's surrogates, ascending within the target
+  const int *erec;  // [nnz] records of each target's surrogates, ascending within the target,
+                    // targets in the hook's order (tord), target tord[r] at toff[r] .. toff[r + 1)
+  const int *toff;  // [ns + 1]
+  const int *tord;  // [ns] the order in which the hook takes the sampled targets (lists sharing
+                    // their far-field surrogates adjacent)
+  // the hook's target groups: group g holds targets tord[gstart[g] .. gstart[g + 1]) (at most
+  // kGroupTargets) and the union of their records urec[ustart[g] .. ustart[g + 1]) (ascending);
+  // eloc[e] is entry e's record (erec[e]) as an index into its group's union
+  int ngroups, umax;  // umax: the largest union held in LDS (the launch's LDS, in records)
+  const int *gstart, *ustart, *urec;
+  const unsigned short *eloc;
   const double *A;              // [Mr][nd]
   // scratch used when the LDS copies do not fit; C holds [C | rbar | 0] with
   // leading dimension ldc
@@ -432,37 +444,90 @@ __device__ __forceinline__ void point_terms(double tx, double ty, const dbl4 p, 
   a.bc = fmaf(g2, dd + d2, a.bc);
 }
 
-constexpr int kGatherU = 4;
+constexpr int kGroupTargets = 8;   // targets per group: one wave each
+constexpr int kUnionCap = 1024;    // records of a group held in LDS (at most 32 KB)
 
-// (at most 64 VGPRs: eight waves per SIMD to hide the dependent loads)
-__global__ void __launch_bounds__(256, 8)
+// One workgroup per target group: the union of the group's records is
+// copied to LDS once (targets whose lists share their far-field surrogates
+// are grouped, so the union is a fraction of the lists' total), then one
+// wave per target walks its list by 2-byte union indices.  The entries are
+// stored in group order, so a wave's index loads depend on nothing but its
+// slot; they, the target's own operands and the union copy are all in
+// flight before the barrier.  A group whose union passes kUnionCap (a single
+// target's long list) reads its records from the global table instead.
+constexpr int kGatherKU = 6;  // list entries per lane in flight
+__global__ void __launch_bounds__(64 * kGroupTargets) __attribute__((amdgpu_waves_per_eu(8, 8)))
     gather_point_kernel(RomDev d, const double *__restrict__ pos, const double *__restrict__ xbar_prev,
                         const double *__restrict__ fbar_prev, double *xbar, double *fbar, double *rbar, double *C) {
-  const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (t >= d.ns) return;
-  const int ns = d.ns, M = d.M;
-  const double tx = pos[t], ty = pos[ns + t];
+  extern __shared__ __align__(16) double ulds[];
+  dbl4 *ur = reinterpret_cast<dbl4 *>(ulds);
   const dbl4 *sp = reinterpret_cast<const dbl4 *>(d.spk);
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int ns = d.ns, M = d.M;
+  const int r = d.gstart[g] + (tid >> 6);
+  const bool valid = r < d.gstart[g + 1];
+  const int u0 = d.ustart[g], nu = d.ustart[g + 1] - u0;
+  const bool in_lds = nu <= kUnionCap;
+  int t = 0, e0 = 0, e1 = 0;
+  if (valid) {
+    t = d.tord[r];
+    e0 = d.toff[r];
+    e1 = d.toff[r + 1];
+  }
+  if (in_lds)
+    for (int u = tid; u < nu; u += 64 * kGroupTargets) ur[u] = sp[d.urec[u0 + u]];
+  // the first round of this lane's entries (lane + 64 k of the list)
+  int c[kGatherKU];
+#pragma unroll
+  for (int k = 0; k < kGatherKU; ++k) {
+    const int e = e0 + lane + 64 * k;
+    c[k] = e < e1 ? (in_lds ? (int)d.eloc[e] : d.erec[e]) : -1;
+  }
+  // the target's own operands
+  double tx = 0.0, ty = 0.0, u_x = 0.0, u_y = 0.0, xp_x = 0.0, xp_y = 0.0, fp_x = 0.0, fp_y = 0.0;
+  float phx = 0.f, phy = 0.f;
+  if (valid) {
+    tx = pos[t];
+    ty = pos[ns + t];
+    u_x = d.ubar[t];
+    u_y = d.ubar[ns + t];
+    if (rbar) {
+      xp_x = xbar_prev[t];
+      xp_y = xbar_prev[ns + t];
+      fp_x = fbar_prev[t];
+      fp_y = fbar_prev[ns + t];
+    }
+    if (C && lane < M) {
+      phx = d.Phibar[(size_t)t * M + lane];
+      phy = d.Phibar[(size_t)(ns + t) * M + lane];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
   const double hdt = 0.5 * (double)d.dt;
   GatherAcc<false> a;
-  const int e1 = d.off[t + 1];
-  // kGatherU entries in flight per lane: the ids, then the records they
-  // name, are requested before any is used; an entry past the list's end
-  // reads record 0 and adds nothing
-  for (int e = d.off[t] + lane; e < e1; e += 64 * kGatherU) {
-    int c[kGatherU];
+  // each lane adds its entries in list order (the two record sources in
+  // separate loops, so each keeps its own address space)
+  auto walk = [&](auto rec_at, auto idx_at) {
+    for (int eb = e0;;) {
 #pragma unroll
-    for (int u = 0; u < kGatherU; ++u) c[u] = e + 64 * u < e1 ? d.erec[e + 64 * u] : -1;
-    dbl4 p[kGatherU];
+      for (int k = 0; k < kGatherKU; ++k)
+        if (c[k] >= 0) point_terms(tx, ty, rec_at(c[k]), d.d2, a);
+      eb += 64 * kGatherKU;
+      if (eb >= e1) break;
 #pragma unroll
-    for (int u = 0; u < kGatherU; ++u) p[u] = sp[c[u] < 0 ? 0 : c[u]];
-#pragma unroll
-    for (int u = 0; u < kGatherU; ++u)
-      if (c[u] >= 0) point_terms(tx, ty, p[u], d.d2, a);
-  }
-  const double Fx = gsum(a.fx, 64) * kInv2PiD + d.ubar[t];
-  const double Fy = gsum(a.fy, 64) * kInv2PiD + d.ubar[ns + t];
+      for (int k = 0; k < kGatherKU; ++k) {
+        const int e = eb + lane + 64 * k;
+        c[k] = e < e1 ? idx_at(e) : -1;
+      }
+    }
+  };
+  if (in_lds)
+    walk([&](int q) { return ur[q]; }, [&](int e) { return (int)d.eloc[e]; });
+  else
+    walk([&](int q) { return sp[q]; }, [&](int e) { return d.erec[e]; });
+  const double Fx = gsum(a.fx, 64) * kInv2PiD + u_x;
+  const double Fy = gsum(a.fy, 64) * kInv2PiD + u_y;
   if (lane == 0) {
     if (xbar) {
       xbar[t] = tx;
@@ -473,14 +538,16 @@ __global__ void __launch_bounds__(256, 8)
       fbar[ns + t] = Fy;
     }
     if (rbar) {
-      rbar[t] = (tx - xbar_prev[t]) - hdt * (Fx + fbar_prev[t]);
-      rbar[ns + t] = (ty - xbar_prev[ns + t]) - hdt * (Fy + fbar_prev[ns + t]);
+      rbar[t] = (tx - xp_x) - hdt * (Fx + fp_x);
+      rbar[ns + t] = (ty - xp_y) - hdt * (Fy + fp_y);
     }
   }
   if (C) {
     const double B00 = gsum(a.ba, 64) * kInv2PiD, B01 = gsum(a.bb, 64) * kInv2PiD, B10 = gsum(a.bc, 64) * kInv2PiD;
     for (int m = lane; m < M; m += 64) {
-      const double px = d.Phibar[(size_t)t * M + m], py = d.Phibar[(size_t)(ns + t) * M + m];
+      // the lane's first mode was loaded above
+      const double px = m == lane ? (double)phx : (double)d.Phibar[(size_t)t * M + m];
+      const double py = m == lane ? (double)phy : (double)d.Phibar[(size_t)(ns + t) * M + m];
       C[(size_t)t * M + m] = px - hdt * (B00 * px + B01 * py);
       C[(size_t)(ns + t) * M + m] = py - hdt * (B10 * px - B00 * py);
     }
@@ -1676,41 +1743,123 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       etg[e] = i;
       eid[e] = int(s.ids[e]);
     }
-  // record order of the hook's surrogate table: Morton order of the
-  // reference positions (16 bits per axis over their bounding box)
-  std::vector<int> rec(size_t(s.Nc > 0 ? s.Nc : 1), 0), erec(etg.size(), 0);
-  if (s.Nc > 0) {
-    double lo[2] = {s.xqt0[0], s.xqt0[1]}, hi[2] = {s.xqt0[0], s.xqt0[1]};
-    for (int64_t c = 0; c < s.Nc; ++c)
-      for (int k = 0; k < 2; ++k) {
-        lo[k] = std::min(lo[k], s.xqt0[2 * c + k]);
-        hi[k] = std::max(hi[k], s.xqt0[2 * c + k]);
-      }
+  // Morton order (16 bits per axis over the points' bounding box) of n
+  // points x[i * stride], x[i * stride + off2]: order[r] = the r-th point
+  auto morton_order = [](int64_t n, const double *x, int64_t stride, int64_t off2) {
     auto spread = [](uint32_t v) {
-      uint64_t x = v & 0xFFFFu;
-      x = (x | (x << 8)) & 0x00FF00FFull;
-      x = (x | (x << 4)) & 0x0F0F0F0Full;
-      x = (x | (x << 2)) & 0x33333333ull;
-      x = (x | (x << 1)) & 0x55555555ull;
-      return x;
+      uint64_t u = v & 0xFFFFu;
+      u = (u | (u << 8)) & 0x00FF00FFull;
+      u = (u | (u << 4)) & 0x0F0F0F0Full;
+      u = (u | (u << 2)) & 0x33333333ull;
+      u = (u | (u << 1)) & 0x55555555ull;
+      return u;
     };
-    std::vector<std::pair<uint64_t, int>> key(size_t(s.Nc));
-    for (int64_t c = 0; c < s.Nc; ++c) {
+    double lo[2] = {x[0], x[off2]}, hi[2] = {x[0], x[off2]};
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < 2; ++k) {
+        const double v = x[i * stride + k * off2];
+        lo[k] = std::min(lo[k], v);
+        hi[k] = std::max(hi[k], v);
+      }
+    std::vector<std::pair<uint64_t, int>> key(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) {
       uint32_t g[2];
       for (int k = 0; k < 2; ++k) {
-        const double w = hi[k] > lo[k] ? (s.xqt0[2 * c + k] - lo[k]) / (hi[k] - lo[k]) : 0.0;
+        const double w = hi[k] > lo[k] ? (x[i * stride + k * off2] - lo[k]) / (hi[k] - lo[k]) : 0.0;
         g[k] = uint32_t(std::min(65535.0, std::max(0.0, std::floor(w * 65536.0))));
       }
-      key[c] = {spread(g[0]) | (spread(g[1]) << 1), int(c)};
+      key[i] = {spread(g[0]) | (spread(g[1]) << 1), int(i)};
     }
     std::sort(key.begin(), key.end());
-    for (int64_t r = 0; r < s.Nc; ++r) rec[key[r].second] = int(r);
+    std::vector<int> order(static_cast<size_t>(n));
+    for (int64_t r = 0; r < n; ++r) order[r] = key[r].second;
+    return order;
+  };
+  // the hook's target order: lexicographic in each list's eight largest
+  // surrogate ids, so targets whose lists share their far-field clusters sit
+  // together and neighbouring waves read the same records
+  std::vector<int> tord(size_t(s.ns));
+  {
+    constexpr int kKey = 8;
+    std::vector<std::array<int64_t, kKey>> key(size_t(s.ns));
+    for (int i = 0; i < s.ns; ++i) {
+      std::vector<int64_t> l(s.ids + s.off[i], s.ids + s.off[i + 1]);
+      const size_t k = std::min<size_t>(kKey, l.size());
+      std::partial_sort(l.begin(), l.begin() + k, l.end(), std::greater<int64_t>());
+      key[i].fill(-1);
+      for (size_t j = 0; j < k; ++j) key[i][j] = l[j];
+      tord[i] = i;
+    }
+    std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) { return key[a] > key[b]; });
+  }
+  // record order of the hook's surrogate table: Morton order of the
+  // surrogates' reference positions
+  std::vector<int> rec(size_t(s.Nc > 0 ? s.Nc : 1), 0), erec(etg.size(), 0);
+  if (s.Nc > 0) {
+    const std::vector<int> order = morton_order(s.Nc, s.xqt0, 2, 1);
+    for (int64_t r = 0; r < s.Nc; ++r) rec[order[r]] = int(r);
     // each target's entries in record order: neighbouring lanes read
     // neighbouring records (the hook's sums run in this order)
     for (int i = 0; i < s.ns; ++i) {
       for (int64_t e = s.off[i]; e < s.off[i + 1]; ++e) erec[e] = rec[s.ids[e]];
       std::sort(erec.begin() + s.off[i], erec.begin() + s.off[i + 1]);
     }
+  }
+  // the hook's target groups: consecutive targets of tord, at most
+  // kGroupTargets, closed early when the union of their records would pass
+  // kUnionCap (a target whose own list passes it forms a group alone and
+  // reads the global table)
+  std::vector<int> gstart{0}, ustart{0}, urec;
+  std::vector<unsigned short> eloc(erec.size(), 0);
+  {
+    std::vector<int> stamp(size_t(s.Nc > 0 ? s.Nc : 1), -1), loc(size_t(s.Nc > 0 ? s.Nc : 1), 0);
+    int r = 0;
+    while (r < s.ns) {
+      const int g = int(gstart.size()) - 1;
+      std::vector<int> u;
+      int r1 = r;
+      while (r1 < s.ns && r1 - r < kGroupTargets) {
+        const int t = tord[r1];
+        size_t add = 0;
+        for (int64_t e = s.off[t]; e < s.off[t + 1]; ++e) add += stamp[erec[e]] != g;
+        if (r1 > r && u.size() + add > size_t(kUnionCap)) break;
+        for (int64_t e = s.off[t]; e < s.off[t + 1]; ++e)
+          if (stamp[erec[e]] != g) {
+            stamp[erec[e]] = g;
+            u.push_back(erec[e]);
+          }
+        ++r1;
+      }
+      std::sort(u.begin(), u.end());
+      if (u.size() <= size_t(kUnionCap)) {
+        for (size_t k = 0; k < u.size(); ++k) loc[u[k]] = int(k);
+        for (int q = r; q < r1; ++q)
+          for (int64_t e = s.off[tord[q]]; e < s.off[tord[q] + 1]; ++e) eloc[e] = (unsigned short)loc[erec[e]];
+      }
+      urec.insert(urec.end(), u.begin(), u.end());
+      gstart.push_back(r1);
+      ustart.push_back(int(urec.size()));
+      r = r1;
+    }
+    if (urec.empty()) urec.push_back(0);
+  }
+  // the hook's entries in target order tord: toff[r] .. toff[r + 1) are
+  // those of target tord[r]
+  std::vector<int> toff(size_t(s.ns) + 1, 0);
+  {
+    std::vector<int> erec_t(erec.size(), 0);
+    std::vector<unsigned short> eloc_t(eloc.size(), 0);
+    for (int q = 0; q < s.ns; ++q) {
+      const int t = tord[q];
+      int64_t k = toff[q];
+      for (int64_t e = s.off[t]; e < s.off[t + 1]; ++e, ++k) {
+        erec_t[k] = erec[e];
+        eloc_t[k] = eloc[e];
+      }
+      toff[q + 1] = int(k);
+    }
+    erec.swap(erec_t);
+    eloc.swap(eloc_t);
   }
   std::vector<double> ubar(nd, 0.0);
   if (s.ubar)
@@ -1793,7 +1942,9 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
                           align256(p0.size() * 8), align256(etg.size() * 4), align256(eid.size() * 4),
                           align256(gt0.size() * 4), align256(ubar.size() * 8), align256(size_t(P) * 8),
                           align256(size_t(s.Nc > 0 ? s.Nc : 1) * 32), align256(rec.size() * 4),
-                          align256(erec.size() * 4)};
+                          align256(erec.size() * 4), align256(tord.size() * 4), align256(gstart.size() * 4),
+                          align256(ustart.size() * 4), align256(urec.size() * 4), align256(eloc.size() * 2),
+                          align256(toff.size() * 4)};
   constexpr int NB = sizeof(bytes) / sizeof(bytes[0]);
   size_t total = 0;
   for (size_t b : bytes) total += b;
@@ -1815,6 +1966,16 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   d.spk = (double *)ptrs[16];
   d.rec = (int *)ptrs[17];
   d.erec = (int *)ptrs[18];
+  d.tord = (int *)ptrs[19];
+  d.ngroups = int(gstart.size()) - 1;
+  d.umax = 1;
+  for (int g = 0; g < d.ngroups; ++g)
+    if (ustart[g + 1] - ustart[g] <= kUnionCap) d.umax = std::max(d.umax, ustart[g + 1] - ustart[g]);
+  d.gstart = (int *)ptrs[20];
+  d.ustart = (int *)ptrs[21];
+  d.urec = (int *)ptrs[22];
+  d.eloc = (unsigned short *)ptrs[23];
+  d.toff = (int *)ptrs[24];
   hipError_t e = hipMemcpy(ptrs[0], phibar.data(), phibar.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[1], xbar0.data(), xbar0.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[2], ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
@@ -1828,6 +1989,12 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
   if (e == hipSuccess) e = hipMemcpy(ptrs[14], ubar.data(), ubar.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[17], rec.data(), rec.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ptrs[18], erec.data(), erec.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[19], tord.data(), tord.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[20], gstart.data(), gstart.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[21], ustart.data(), ustart.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[22], urec.data(), urec.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !eloc.empty()) e = hipMemcpy(ptrs[23], eloc.data(), eloc.size() * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ptrs[24], toff.data(), toff.size() * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(rom->buf);
     delete rom;
@@ -1864,8 +2031,8 @@ extern "C" int ptrom_rom_hyperpair(ptrom_rom *rom, const double *xhat, const dou
     // point form: positions once per surrogate, 4 bytes per list entry
     hipLaunchKernelGGL(point_positions_kernel, dim3((unsigned)((d.P + 255) / 256)), dim3(256), 0, st, d, xhat,
                        d.pos);
-    hipLaunchKernelGGL(gather_point_kernel, dim3(gg), dim3(256), 0, st, d, d.pos, xbar_prev, fbar_prev, xbar, fbar,
-                       rbar, C);
+    hipLaunchKernelGGL(gather_point_kernel, dim3((unsigned)d.ngroups), dim3(64 * kGroupTargets),
+                       d.umax * sizeof(dbl4), st, d, d.pos, xbar_prev, fbar_prev, xbar, fbar, rbar, C);
   }
   PTROM_CHECK_HIP(ctx, hipGetLastError());
   return PTROM_OK;
