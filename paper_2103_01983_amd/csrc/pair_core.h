@@ -6,6 +6,13 @@
 
 namespace ptrom {
 
+// The work-item's index in its workgroup and the workgroup's index, read
+// from their hardware registers.  The each-pair-once kernels are built with
+// IEEE mode off, and the device library's id functions (threadIdx,
+// blockIdx) are then not inlined into them.
+__device__ __forceinline__ int local_id() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int group_id() { return (int)__builtin_amdgcn_workgroup_id_x(); }
+
 constexpr float kInv2Pi = 0.159154943091895335768883763372514362f;
 
 template <int OP> struct Traits;
@@ -144,7 +151,7 @@ __device__ __forceinline__ void pair_block(int n, const float *__restrict__ xy,
                                            float (&res)[K][Traits<OP>::NACC]) {
   using T = Traits<OP>;
   constexpr int NS = T::NSRC, NT = T::NTGT, NA = T::NACC;
-  const int tid = threadIdx.x;
+  const int tid = local_id();
   float tg[K][NT];
   int ti[K];
 #pragma unroll

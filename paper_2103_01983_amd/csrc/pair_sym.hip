@@ -24,7 +24,7 @@ namespace ptrom {
 namespace {
 
 __global__ void sym_reset_kernel(unsigned long long *__restrict__ counter) {
-  if (threadIdx.x == 0) counter[0] = 0;
+  if (local_id() == 0) counter[0] = 0;
 }
 
 // Block pair of item q: with e = floor((sqrt(8 q + 1) - 1) / 2) the items
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ float racc_lds[kBlock / 64][NA][64];
   __shared__ float lds_diag[NS * kTile];
   __shared__ unsigned long long item_s;
-  const int tid = threadIdx.x;
+  const int tid = local_id();
   const long long items = (long long)nb * (nb + 1) / 2;
 
   for (;;) {
@@ -95,10 +95,10 @@ __global__ void __launch_bounds__(64 * kSlices)
                       float *__restrict__ out, float *__restrict__ out2) {
   constexpr int NA = Traits<OP>::NACC;
   __shared__ float part[NA][kSlices][64];
-  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
-  const int b = blockIdx.x * 64 + lane;
+  const int lane = local_id() & 63, slice = local_id() >> 6;
+  const int b = group_id() * 64 + lane;
   const bool ok = b < n;
-  const int B = (blockIdx.x * 64) / tb;
+  const int B = (group_id() * 64) / tb;
   const int nf = nb - B;  // forward slots come first
   const int q0 = (slice * nb) / kSlices, q1 = ((slice + 1) * nb) / kSlices;
 #pragma unroll

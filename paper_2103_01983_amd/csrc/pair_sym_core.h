@@ -21,6 +21,12 @@ namespace ptrom {
 constexpr float kFar = 1.0e15f;  // position of padding bodies (never coincides with a real one)
 
 // Forward and reaction terms of one pair; t: target data, s: source data.
+// Factors of 2 and 1/2 are written as scalings of one operation's result
+// (2 * (a * b), 0.5f * (a * b)).  Where a translation unit is built with
+// FP32 denormals flushed and IEEE mode off (the single-system kernels), the
+// compiler folds such a scaling into the instruction's output modifier at no
+// cost.  Scaling by a power of two is exact, so the values are those of the
+// plain expressions.
 template <int OP>
 __device__ __forceinline__ void interact_sym(const float *t, const float *s, float d2, float *acc,
                                              float *react) {
@@ -37,10 +43,11 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
   } else if constexpr (OP == OP_JVP) {
     const float ex = t[2] - s[3];
     const float ey = t[3] - s[4];
-    const float c = fmaf(dx, ex, dy * ey) * (r + r);
+    const float r2 = 2.0f * r;  // 2 / q
+    const float c = fmaf(dx, ex, dy * ey) * r2;
     const float wx = fmaf(-c, dx, ex);
     const float wy = fmaf(-c, dy, ey);
-    const float gj = s[2] * r, gi = t[4] * r;
+    const float gj = 0.5f * (s[2] * r2), gi = 0.5f * (t[4] * r2);
     acc[0] = fmaf(-gj, wy, acc[0]);
     acc[1] = fmaf(gj, wx, acc[1]);
     react[0] = fmaf(gi, wy, react[0]);
@@ -49,7 +56,7 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
     // entries 0..2 of q^-2 [2 rx ry, ry^2 - rx^2 - d^2; ry^2 - rx^2 + d^2, -2 rx ry]
     // (Gamma r) r as in the one-sided kernel, which keeps Gamma / q^2 finite
     // wherever that one is
-    const float h0 = (dx + dx) * dy;
+    const float h0 = 2.0f * (dx * dy);
     const float m = fmaf(dy, dy, -dx * dx);
     const float h1 = m - d2, h2 = m + d2;
     const float gj = (s[2] * r) * r, gi = (t[4] * r) * r;
@@ -66,7 +73,7 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
     acc[1] = fmaf(dx, gj, acc[1]);
     react[0] = fmaf(dy, gi, react[0]);
     react[1] = fmaf(-dx, gi, react[1]);
-    const float h0 = (dx + dx) * dy;
+    const float h0 = 2.0f * (dx * dy);
     const float m = fmaf(dy, dy, -dx * dx);
     const float h1 = m - d2, h2 = m + d2;
     const float gj2 = gj * r, gi2 = gi * r;
@@ -111,7 +118,7 @@ __device__ __forceinline__ void sym_block_pair(int n, const float *__restrict__ 
   using T = Traits<OP>;
   constexpr int NA = T::NACC, NS = T::NSRC;
   constexpr int TB = kBlock * K;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = local_id(), lane = tid & 63, wave = tid >> 6;
   // targets of block I: x, y, aux0, aux1, Gamma (padding: far away, no strength)
   float tg[K][5];
 #pragma unroll

@@ -77,6 +77,32 @@ def test_gnat_limit_matches_pair_sum(dev, trained):
     assert rel(gf.cpu().numpy(), oracle.velocity_at(full, f32(cl.gamma), a2["delta"], sample)) <= 1e-5
 
 
+def test_hook_lists_longer_than_the_lds_union(dev):
+    # no clustering over 1600 bodies: every list holds 1599 surrogates, more
+    # than a target group's union may hold in LDS, so each target forms a
+    # group alone and reads the records from the global table
+    cl = W.counter_rotating_patches(1600, seed=47, delta=0.02)
+    n, M = cl.n, 8
+    rng = np.random.default_rng(48)
+    Phi = np.linalg.qr(rng.standard_normal((2 * n, M)))[0]
+    sig = np.sort(rng.uniform(1.0, 10.0, M))[::-1]
+    tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+    sample = np.sort(rng.choice(n, 12, replace=False))
+    A = off.gappy_operator(np.linalg.qr(rng.standard_normal((2 * n, 16)))[0], sample)
+    art = rounded(off.rom_artifacts(sample, tree, np.inf, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A))
+    assert np.min(np.diff(art["off"])) > 1024
+    nd = 2 * sample.size
+    xh = rng.standard_normal(M) * 0.05
+    xp, fp = rng.standard_normal(nd) * 0.1 + art["xbar0"], rng.standard_normal(nd) * 0.1
+    xb, fb, rb, C = oracle.Rom(art).hyperpair(xh, xp, fp)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    gx, gf, gr, gC = native.Rom(art).hyperpair(t(xh), t(xp), t(fp))
+    assert rel(gx.cpu().numpy(), xb) <= 1e-14
+    assert rel(gf.cpu().numpy(), fb) <= 1e-5
+    assert rel(gr.cpu().numpy(), rb) <= 1e-5
+    assert rel(gC.cpu().numpy() - art["Phibar"], C - art["Phibar"]) <= 1e-5
+
+
 @pytest.mark.parametrize("mode", [native.JAC_PAPER, native.JAC_EXACT])
 def test_rom_run_fixed_iterations(dev, trained, mode):
     # tol = 0 forces exactly max_iter Gauss-Newton iterations per step on both
