@@ -337,7 +337,7 @@ int ptrom_rom_run(ptrom_rom *rom, int nsteps, double *xhat, double *xhat_hist, i
  * runs the same least-squares step, so all of them hold the same xhat.  The
  * launch is cooperative (all W x nq workgroups resident).  workgroups: 0 =
  * automatic (about 1024 entries per slice, at most 16, widened until a slice
- * fits in LDS; no split for 1024 entries or fewer), 1 = one workgroup per
+ * fits in LDS; no split below 4096 entries), 1 = one workgroup per
  * query, 2..64 = that many (widened if a slice does not fit).  The split is
  * skipped, silently, where the device takes no cooperative launch or the grid
  * would not be resident at once.  A barrier wait that fails max_polls checks

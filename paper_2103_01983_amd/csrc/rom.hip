@@ -176,7 +176,7 @@ __device__ __forceinline__ void load_entry(const float *ent, int ew, int64_t nnz
   }
 }
 
-// MB: the compile-time bound on the basis size (8, 16 or 32) of the small
+// MB: the compile-time bound on the basis size (8, 16, 24 or 32) of the small
 // kernels, which sizes every unrolled mode loop, so a small basis runs
 // proportionally less code
 template <bool EXACT, int MB = kSmallM>
@@ -1587,7 +1587,7 @@ __global__ void __launch_bounds__(kRunThreads)
 // the arrays in the LDS-copy variant; the per-entry terms only in the entry-parallel
 // gather
 // the basis bound of the small kernel that runs a basis of M modes
-int mb_of(int M) { return M <= 8 ? 8 : M <= 16 ? 16 : kSmallM; }
+int mb_of(int M) { return M <= 8 ? 8 : M <= 16 ? 16 : M <= 24 ? 24 : kSmallM; }
 
 size_t solve_lds_bytes(int M, int Mr) {
   return sizeof(double) * ((size_t)Mr * (M + 1) + (size_t)mb_of(M) * 64);
@@ -1607,6 +1607,7 @@ const void *run_kernel(int M, bool exact, bool ldsa, bool split) {
   switch (mb_of(M)) {
     case 8: return run_kernel_mb<8>(exact, ldsa, split);
     case 16: return run_kernel_mb<16>(exact, ldsa, split);
+    case 24: return run_kernel_mb<24>(exact, ldsa, split);
     default: return run_kernel_mb<kSmallM>(exact, ldsa, split);
   }
 }
@@ -1878,7 +1879,7 @@ extern "C" int ptrom_rom_create(ptrom_ctx *ctx, const ptrom_rom_desc *desc, ptro
       maxsh = 64 * 1024;
     size_t stat = 0;
     std::vector<const void *> kernels;
-    for (int Mq : {8, 16, kSmallM})
+    for (int Mq : {8, 16, 24, kSmallM})
       for (int v = 0; v < 5; ++v) kernels.push_back(run_kernel(Mq, v & 1, v & 2, v == 4));
     for (const void *k : kernels) {
       hipFuncAttributes fa{};
@@ -2048,10 +2049,12 @@ __global__ void split_zero_kernel(unsigned *p, long long n) {
 // Workgroups per query of a split run (paper Jacobian, small basis, arrays in
 // LDS): about kSplitEntries entries per slice, at most kSplitMaxW, widened
 // until the slice fits next to the other LDS copies; 1 (no split) when the
-// lists are short, the device takes no cooperative launch, the grid would
-// not be resident at once, or the barrier count would pass 2^32.  *lds: the
-// split launch's dynamic LDS.
+// automatic choice meets fewer than kSplitMinEntries entries (below that
+// the exchange costs more than the slices save), the device takes no
+// cooperative launch, the grid would not be resident at once, or the
+// barrier count would pass 2^32.  *lds: the split launch's dynamic LDS.
 constexpr int64_t kSplitEntries = 1024;
+constexpr int64_t kSplitMinEntries = 4096;  // automatic splits start here
 constexpr int kSplitMaxW = 64;
 int split_width(ptrom_rom *rom, int nq, int nsteps, int64_t table, int *W_out, size_t *lds) {
   const RomDev &d = rom->d;
@@ -2059,6 +2062,7 @@ int split_width(ptrom_rom *rom, int nq, int nsteps, int64_t table, int *W_out, s
   if (rom->split == 1 || !rom->coop || d.nnz < 1 || d.jac_mode != PTROM_JAC_PAPER || d.M > kSmallM ||
       d.Mr > kSmallMr || nq < 1)
     return PTROM_OK;
+  if (rom->split == 0 && d.nnz < kSplitMinEntries) return PTROM_OK;
   int W = rom->split >= 2 ? rom->split : int(std::min<int64_t>(16, (d.nnz + kSplitEntries - 1) / kSplitEntries));
   if (W < 2) return PTROM_OK;
   auto L = [&](int w) { return int((d.nnz + w - 1) / w); };
