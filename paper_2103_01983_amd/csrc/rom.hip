@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(kRunThreads)
           xcur[q] = x;
         }
         __syncthreads();
-        // per-target sums (one thread per target for short lists, else
+        // per-target sums (one thread per target for lists of at most 8, else
         // groups of G lanes), residual rows and the 2x2 blocks
         auto finish = [&](int t, double s0, double s1, double s2, double s3, double s4) {
           const double Fx = s0 * kInv2PiD + ubar[t], Fy = s1 * kInv2PiD + ubar[ns + t];
@@ -919,7 +919,7 @@ __global__ void __launch_bounds__(kRunThreads)
         if constexpr (SPLIT) {
           for (int t = tid; t < ns; t += kRunThreads)
             finish(t, psum[t], psum[ns + t], psum[2 * ns + t], psum[3 * ns + t], psum[4 * ns + t]);
-        } else if (d.maxlen <= 64) {
+        } else if (d.maxlen <= 8) {
           for (int t = tid; t < ns; t += kRunThreads) {
             float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
             const int e1 = d.off[t + 1];
