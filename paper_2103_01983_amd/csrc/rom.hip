@@ -1029,15 +1029,18 @@ __global__ void __launch_bounds__(kRunThreads)
               ip = fma(ip, fma(-piv, ip, 1.0), ip);
             }
             const double rk = col[kk] * ip;
-            // rows in blocks of 8; blocks wholly past M are padding
+            // rows in blocks of 8; blocks wholly past M are padding.  A
+            // block's pivot-column entries are all read before any is used,
+            // so the scalar-register hazard of each read is hidden.
 #pragma unroll
             for (int i0 = 0; i0 < MB; i0 += 8) {
               if (i0 < M) {
+                double cb[8];
 #pragma unroll
-                for (int u = i0; u < i0 + 8; ++u) {
-                  const double c = lane_d(col[u], kk);
-                  col[u] = u == kk ? rk : fma(-c, rk, col[u]);
-                }
+                for (int u = 0; u < 8; ++u) cb[u] = lane_d(col[i0 + u], kk);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                  col[i0 + u] = i0 + u == kk ? rk : fma(-cb[u], rk, col[i0 + u]);
               }
             }
           }
