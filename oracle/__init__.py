@@ -77,6 +77,7 @@ def lib():
         L.or_hamiltonian.argtypes = [i64, _dp, _dp, dbl]
         L.or_hamiltonian.restype = dbl
         L.or_stream_function.argtypes = [i64, _dp, _dp, dbl, _dp]
+        L.or_stream_function_at.argtypes = [i64, _dp, _dp, dbl, i64, _i64p, _dp]
         L.or_velocity_points.argtypes = [i64, _dp, i64, _dp, _dp, dbl, _dp]
         L.or_rk4.argtypes = [i64, _dp, _dp, dbl, dbl, i32]
         L.or_implicit.argtypes = [i64, _dp, _dp, dbl, dbl, i32, i32, dbl, i32, dbl, i32, i32,
@@ -198,6 +199,15 @@ def stream_function(xy, gamma, delta):
     xy, pxy = _d(xy); g, pg = _d(gamma)
     out = np.empty(n)
     lib().or_stream_function(n, pxy, pg, float(delta), out.ctypes.data_as(_dp))
+    return out
+
+
+def stream_function_at(xy, gamma, delta, idx):
+    """psi at the targets ``idx`` only."""
+    n = _n(xy)
+    xy, pxy = _d(xy); g, pg = _d(gamma); idx, pi = _i(idx)
+    out = np.empty(idx.size)
+    lib().or_stream_function_at(n, pxy, pg, float(delta), idx.size, pi, out.ctypes.data_as(_dp))
     return out
 
 

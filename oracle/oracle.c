@@ -215,18 +215,28 @@ double or_hamiltonian(int64_t n, const double *xy, const double *gam, double del
  * others: psi_i = -(1/4pi) sum_{j != i} G_j log(|r|^2 + d^2).  The velocity is
  * its perpendicular gradient in the target position, f_i = (d psi_i/dy_i,
  * -d psi_i/dx_i), and the Hamiltonian is H = 1/2 sum_i G_i psi_i. */
+static double psi_one(int64_t n, const double *xy, const double *gam, double d2, int64_t i) {
+  double acc = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (j == i) continue;
+    const double rx = xy[i] - xy[j], ry = xy[n + i] - xy[n + j];
+    acc += gam[j] * log(rx * rx + ry * ry + d2);
+  }
+  return -acc / OR_FOUR_PI;
+}
+
 void or_stream_function(int64_t n, const double *xy, const double *gam, double delta, double *psi) {
   const double d2 = delta * delta;
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i) {
-    double acc = 0.0;
-    for (int64_t j = 0; j < n; ++j) {
-      if (j == i) continue;
-      const double rx = xy[i] - xy[j], ry = xy[n + i] - xy[n + j];
-      acc += gam[j] * log(rx * rx + ry * ry + d2);
-    }
-    psi[i] = -acc / OR_FOUR_PI;
-  }
+  for (int64_t i = 0; i < n; ++i) psi[i] = psi_one(n, xy, gam, d2, i);
+}
+
+/* stream function at a subset of targets */
+void or_stream_function_at(int64_t n, const double *xy, const double *gam, double delta, int64_t nt,
+                           const int64_t *idx, double *out) {
+  const double d2 = delta * delta;
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nt; ++t) out[t] = psi_one(n, xy, gam, d2, idx[t]);
 }
 
 /* Velocity induced at nt arbitrary points p [2][nt] by all n bodies (no

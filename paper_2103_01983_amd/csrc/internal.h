@@ -20,8 +20,6 @@ constexpr int64_t kMaxN = int64_t(1) << 30;
 
 enum PairOp { OP_VEL = 0, OP_BJAC = 1, OP_JVP = 2, OP_VJP = 3, OP_PSI = 4, OP_VBJ = 5, OP_COUNT = 6 };
 
-// operations with an each-unordered-pair-once variant
-inline bool has_sym(int op) { return op != OP_PSI; }
 
 // Source staging of the pair kernels.
 //  LDS:    the workgroup stages a tile of sources in LDS; every lane reads it

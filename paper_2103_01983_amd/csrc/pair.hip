@@ -83,17 +83,6 @@ __global__ void __launch_bounds__(256)
   store_final<OP>(n, i, v, out, out2);
 }
 
-int nacc(int op) {
-  switch (op) {
-    case OP_VEL: return Traits<OP_VEL>::NACC;
-    case OP_BJAC: return Traits<OP_BJAC>::NACC;
-    case OP_JVP: return Traits<OP_JVP>::NACC;
-    case OP_PSI: return Traits<OP_PSI>::NACC;
-    case OP_VBJ: return Traits<OP_VBJ>::NACC;
-    default: return Traits<OP_VJP>::NACC;
-  }
-}
-
 // Velocity at arbitrary points: kPtsK points per lane, sources read at
 // wave-uniform addresses (full tiles unrolled so the scalar loads batch),
 // 256-source tiles added with Kahan compensation.
@@ -242,9 +231,7 @@ PairCfg large_n_cfg() {
 
 PairCfg Tuning::get(int op, int64_t n) const {
   PairCfg c = get_table(op, n);
-  if (c.sym && has_sym(op) && uint64_t(pair_sym_ws_floats(op, c.k, n)) * sizeof(float) > ws_cap_bytes)
-    c = large_n_cfg();
-  if (!has_sym(op)) c.sym = 0;
+  if (c.sym && uint64_t(pair_sym_ws_floats(op, c.k, n)) * sizeof(float) > ws_cap_bytes) c = large_n_cfg();
   return c;
 }
 
@@ -317,7 +304,7 @@ int pair_splits(int op, const PairCfg &cfg, int num_cus, int64_t n) {
 }
 
 size_t pair_ws_floats(int op, const PairCfg &cfg, int num_cus, int64_t n) {
-  if (cfg.sym && has_sym(op)) return pair_sym_ws_floats(op, cfg.k, n);
+  if (cfg.sym) return pair_sym_ws_floats(op, cfg.k, n);
   const int s = pair_splits(op, cfg, num_cus, n);
   return s > 1 ? size_t(s) * nacc(op) * size_t(n) : 0;
 }
@@ -325,7 +312,7 @@ size_t pair_ws_floats(int op, const PairCfg &cfg, int num_cus, int64_t n) {
 hipError_t launch_pair(int op, const PairCfg &cfg, int num_cus, int64_t n64, const float *xy,
                        const float *gamma, const float *aux, float delta, float *out, float *out2,
                        float *ws, size_t ws_floats, hipStream_t stream) {
-  if (cfg.sym && has_sym(op))
+  if (cfg.sym)
     return launch_pair_sym(op, cfg.k, cfg.waves_per_simd, num_cus, n64, xy, gamma, aux, delta, out, out2, ws,
                            ws_floats, stream);
   const int n = int(n64);

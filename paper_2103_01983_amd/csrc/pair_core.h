@@ -24,6 +24,18 @@ template <> struct Traits<OP_PSI> { static constexpr int NSRC = 3, NTGT = 2, NAC
 // velocity and the self block in one pass: fx, fy, then the block's B00, B01, B10
 template <> struct Traits<OP_VBJ> { static constexpr int NSRC = 3, NTGT = 2, NACC = 5; };
 
+// accumulators of an operation (host side)
+inline int nacc(int op) {
+  switch (op) {
+    case OP_VEL: return Traits<OP_VEL>::NACC;
+    case OP_BJAC: return Traits<OP_BJAC>::NACC;
+    case OP_JVP: return Traits<OP_JVP>::NACC;
+    case OP_PSI: return Traits<OP_PSI>::NACC;
+    case OP_VBJ: return Traits<OP_VBJ>::NACC;
+    default: return Traits<OP_VJP>::NACC;
+  }
+}
+
 // -ln(2)/(4 pi): the stream-function sum is accumulated with log2
 constexpr float kPsiScale = -0.0551589363396979447f;
 

@@ -5,7 +5,8 @@
 // Gamma_j replaced by Gamma_i and the sign flipped (velocity: u(-r) = -u(r);
 // Jacobian product: H(-r) = H(r) and v_j - v_i = -(v_i - v_j); adjoint:
 // q_ji = -q_ij).  The self blocks of the Jacobian are symmetric instead:
-// H(-r) = H(r), so body j's block gains Gamma_i H(r) with the same sign.
+// H(-r) = H(r), so body j's block gains Gamma_i H(r) with the same sign; so
+// is the stream function's log(|r|^2 + delta^2).
 // The body index range is cut into blocks of 256*K; block pairs (I, J) with
 // J > I are evaluated once, each interaction adding the forward term to the
 // target (registers) and the reaction term to the source; diagonal blocks
@@ -156,8 +157,7 @@ hipError_t launch_sym_op(int k, int n, const float *xy, const float *gam, const 
 size_t pair_sym_ws_floats(int op, int k, int64_t n) {
   const int64_t tb = kBlock * int64_t(k);
   const int64_t nb = (n + tb - 1) / tb;
-  const int na = op == OP_VBJ ? Traits<OP_VBJ>::NACC : (op == OP_VJP || op == OP_BJAC) ? 3 : 2;
-  return size_t(2 * nb * na * n + 64);
+  return size_t(2 * nb * nacc(op) * n + 64);
 }
 
 hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64_t n64, const float *xy,
@@ -173,6 +173,7 @@ hipError_t launch_pair_sym(int op, int k, int waves_per_simd, int num_cus, int64
     case OP_VJP: return launch_sym_op<OP_VJP>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     case OP_BJAC: return launch_sym_op<OP_BJAC>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     case OP_VBJ: return launch_sym_op<OP_VBJ>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
+    case OP_PSI: return launch_sym_op<OP_PSI>(k, n, xy, gamma, aux, d2, grid, ws, out, out2, stream);
     default: return hipErrorInvalidValue;
   }
 }

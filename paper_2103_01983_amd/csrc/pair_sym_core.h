@@ -2,8 +2,9 @@
 // single-system kernels and the batched parametric kernel.
 //
 // The pair terms are antisymmetric (velocity, Jacobian product, adjoint) or
-// symmetric (the Jacobian's self blocks) under exchange of target and
-// source, so one evaluation of a pair gives both bodies' terms.  A
+// symmetric (the Jacobian's self blocks, the stream function) under exchange
+// of target and source, so one evaluation of a pair gives both bodies'
+// terms.  A
 // workgroup takes targets [tgt0, tgt0 + 256 K) and sources
 // [src0, src0 + 256 K) (disjoint ranges), stages 64 sources at a time in LDS
 // and sweeps them in 64 steps, lane l taking source (l + t) mod 64 at step t.
@@ -33,6 +34,13 @@ __device__ __forceinline__ void interact_sym(const float *t, const float *s, flo
   const float dx = t[0] - s[0];
   const float dy = t[1] - s[1];
   const float q = fmaf(dx, dx, fmaf(dy, dy, d2));
+  if constexpr (OP == OP_PSI) {
+    // the log is even in r: both bodies gain the other's Gamma times it
+    const float L = __builtin_amdgcn_logf(q);
+    acc[0] = fmaf(s[2], L, acc[0]);
+    react[0] = fmaf(t[4], L, react[0]);
+    return;
+  }
   const float r = __builtin_amdgcn_rcpf(q);
   if constexpr (OP == OP_VEL) {
     const float gj = s[2] * r, gi = t[4] * r;

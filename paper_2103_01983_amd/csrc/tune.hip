@@ -44,7 +44,7 @@ static int read_tuning(const char *path, Tuning &t) {
     c.staging = staging;
     c.k = k;
     c.waves_per_simd = waves;
-    c.sym = (op == OP_BATCH || has_sym(op)) ? sym : 0;
+    c.sym = sym;
     t.table[{op, cls}] = c;
     ++loaded;
   }
@@ -204,16 +204,15 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
             c.waves_per_simd = waves;
             cands.push_back(c);
           }
-      if (has_sym(op))
-        for (int k : {2, 4})
-          for (int waves : {2, 4, 8}) {
-            PairCfg c;
-            c.staging = STAGE_LDS;
-            c.k = k;
-            c.waves_per_simd = waves;
-            c.sym = 1;
-            cands.push_back(c);
-          }
+      for (int k : {2, 4})
+        for (int waves : {2, 4, 8}) {
+          PairCfg c;
+          c.staging = STAGE_LDS;
+          c.k = k;
+          c.waves_per_simd = waves;
+          c.sym = 1;
+          cands.push_back(c);
+        }
       for (const PairCfg &c : cands) {
             if (pair_ws_floats(op, c, ctx->num_cus, n) > wsf) continue;
             for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
@@ -262,7 +261,7 @@ extern "C" int ptrom_autotune(ptrom_ctx *ctx, const char *cache_path) {
 }
 
 static void describe(const PairCfg &c, int op, int num_cus, int64_t n, int32_t *out) {
-  const bool sym = c.sym && has_sym(op);
+  const bool sym = c.sym != 0;
   out[0] = c.staging;
   out[1] = c.k;
   out[2] = c.waves_per_simd;

@@ -25,7 +25,7 @@ def vctx(request, dev):
     st, k, w, sym = request.param
     fd, path = tempfile.mkstemp(suffix=".txt")
     with os.fdopen(fd, "w") as fh:
-        for op in ("velocity", "jvp", "vjp", "block_jacobian", "velocity_block_jacobian"):
+        for op in ("velocity", "jvp", "vjp", "block_jacobian", "velocity_block_jacobian", "stream_function"):
             fh.write("%s 16 %d %d %d %d\n" % (op, st, k, w, sym))
     h = native.make_context(0, path)
     os.unlink(path)
@@ -66,6 +66,9 @@ def test_variant_parity(dev, vctx, n, delta):
     f2, B2 = native.velocity_block_jacobian(xd, gd, d, ctx=vctx)
     assert rel(f2.cpu().numpy(), oracle.velocity(xy, g, d)) <= 1e-5
     assert rel(B2.cpu().numpy(), ob) <= 1e-5
+    psi = native.stream_function(xd, gd, d, ctx=vctx).cpu().numpy()
+    assert np.all(np.isfinite(psi))
+    assert rel(psi, oracle.stream_function(xy, g, d)) <= 1e-5
 
 
 def test_variant_deterministic(dev, vctx):
@@ -101,3 +104,5 @@ def test_variant_full_size_sampled(dev, vctx):
     f2, B2 = native.velocity_block_jacobian(xd, gd, d, ctx=vctx)
     assert rel(f2.cpu().numpy()[sel], oracle.velocity_at(xy, g, d, idx)) <= 1e-5
     assert rel(B2.cpu().numpy().reshape(4, n)[:, idx].ravel(), ob) <= 1e-5
+    psi = native.stream_function(xd, gd, d, ctx=vctx).cpu().numpy()
+    assert rel(psi[idx], oracle.stream_function_at(xy, g, d, idx)) <= 1e-5

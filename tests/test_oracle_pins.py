@@ -429,6 +429,13 @@ def test_stream_function_two_bodies_and_hamiltonian():
     assert H == pytest.approx(oracle.hamiltonian(cl.xy, cl.gamma, 0.02), rel=1e-12)
 
 
+def test_stream_function_at_matches_full():
+    cl = W.disk_cloud(257, seed=4)
+    psi = oracle.stream_function(cl.xy, cl.gamma, 0.02)
+    idx = np.array([256, 0, 17, 130])
+    np.testing.assert_array_equal(oracle.stream_function_at(cl.xy, cl.gamma, 0.02, idx), psi[idx])
+
+
 def test_velocity_at_points_matches_bodies_and_far_field():
     cl = W.gaussian_patch(120, seed=17, delta=0.02)
     n = cl.n
