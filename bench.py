@@ -319,7 +319,9 @@ def run_forms(native, W, dev, only, plain_pairs_per_s, gather_ns=(16, 256, 2048,
         forms["adjoint"] = {"N": n, "rk4_steps": steps, "checkpoint_every": every,
                             "forward_seconds": sec_f, "backward_seconds": sec_b,
                             "forward_pairs_per_s": 4 * steps * pairs / sec_f,
-                            "backward_pairs_per_s": 4 * steps * 2 * pairs / sec_b,
+                            # recompute: 4 velocities per step but 3 on each segment's last step;
+                            # then 4 vector-Jacobian products per step
+                            "backward_pairs_per_s": (8 * steps - -(-steps // every)) * pairs / sec_b,
                             "backward_over_forward_time": sec_b / sec_f,
                             "note": "backward = recompute (velocity) + vector-Jacobian pair kernels"}
         del holder

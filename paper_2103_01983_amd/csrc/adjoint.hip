@@ -148,7 +148,10 @@ extern "C" int ptrom_rk4_bwd(ptrom_ctx *ctx, int64_t n, const float *ckpt, const
     for (int s = 0; s < len; ++s) {
       float *s0 = S + (size_t)(4 * s) * m;
       float *sq[4] = {s0, s0 + m, s0 + 2 * m, s0 + 3 * m};
-      for (int q = 0; q < 4; ++q) {
+      // k4 only feeds the next step's start, so the segment's last step
+      // skips it
+      const int nk = s + 1 < len ? 4 : 3;
+      for (int q = 0; q < nk; ++q) {
         if (int rc = vel(sq[q], k[q])) return rc;
         if (q < 3) PTROM_CHECK_HIP(ctx, launch_axpy(m, sq[q + 1], s0, (q < 2 ? 0.5f : 1.0f) * h, k[q], st));
       }

@@ -182,12 +182,15 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     x1 = torch.zeros((1, M), dtype=torch.float64, device=dev)
+    i1 = torch.empty((1, steps), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rom.run_batched(gt[:1], steps, x1)
+    rom.run_batched(gt[:1], steps, x1, None, i1)
     torch.cuda.synchronize()
     t_one = time.perf_counter() - t0
-    log("online: %d queries in %.3f s, one query %.3f s" % (nq, t_batch, t_one))
+    its_one = int(i1.sum().item())
+    log("online: %d queries in %.3f s, one query %.3f s (%d GN iterations, %.1f us each)"
+        % (nq, t_batch, t_one, its_one, 1e6 * t_one / max(its_one, 1)))
 
     # trapezoid FOM of every query (timed per query) and the QoIs
     Phi = info["Phi"]
@@ -239,6 +242,7 @@ def parametric_study(case="vortex_pair", n=500, M=None, Mr=None, ns=None, pc=1.0
                 mu_lo=lo.tolist(), mu_hi=hi.tolist(), train_mu=mus_train.tolist(), queries=nq,
                 Nc=int(np.asarray(art["Gt"]).size), nnz=int(np.asarray(art["ids"]).size), offline_seconds=t_off,
                 online_batched_seconds=t_batch, online_one_query_seconds=t_one,
+                online_one_query_gn_iterations=its_one, online_one_query_us_per_gn_iteration=1e6 * t_one / max(its_one, 1),
                 batched_queries_per_one_query_time=nq * t_one / t_batch,
                 fom_seconds_per_query=float(np.mean(t_fom)), speedup_SF_per_query=float(np.mean(t_fom)) / (t_batch / nq),
                 fom_block_seconds_per_query=float(np.mean(t_fom_block)),
