@@ -12,9 +12,10 @@
 // target (registers) and the reaction term to the source; diagonal blocks
 // (I, I) use the ordinary one-sided tile.
 // Workgroups pop items from a device counter (persistent launch).  Item q
-// of the nb (nb + 1) / 2 block pairs is decoded arithmetically: the items
-// run by decreasing block distance d = J - I, so the cheaper diagonal items
-// (d = 0) come last and fill the launch's tail.  Forward sums land in
+// of the nb (nb - 1) / 2 off-diagonal block pairs is decoded arithmetically:
+// the items run by decreasing block distance d = J - I.  The diagonal blocks
+// come last, each cut into K slices of 256 targets, so that the small
+// slices fill the launch's tail.  Forward sums land in
 // F[J][.][N], reactions in R[I][.][N]; a final kernel adds, per body, its
 // forward slots J >= block(b) and reaction slots I < block(b) in a fixed
 // order (Kahan compensated sums over 8 contiguous slot ranges, combined in
@@ -55,7 +56,10 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ float lds_diag[NS * kTile];
   __shared__ unsigned long long item_s;
   const int tid = local_id();
-  const long long items = (long long)nb * (nb + 1) / 2;
+  // the off-diagonal block pairs come first (the items of distance >= 1),
+  // then every diagonal block in K slices of 256 targets
+  const long long offd = (long long)nb * (nb - 1) / 2;
+  const long long items = offd + (long long)nb * K;
 
   for (;;) {
     if (tid == 0) item_s = atomicAdd(counter, 1ull);
@@ -63,22 +67,24 @@ __global__ void __launch_bounds__(kBlock)
     const long long it = (long long)item_s;
     __syncthreads();
     if (it >= items) break;
-    int I, J;
-    tri_item(it, nb, I, J);
-    const int tgt0 = I * TB;
-    if (J == I) {
-      float res[K][NA];
-      pair_block<OP, K, STAGE_LDS>(n, xy, gam, aux, d2, tgt0, tgt0, min(n, tgt0 + TB), lds_diag, res);
+    if (it >= offd) {
+      // diagonal block I, target slice h (one target per lane) against the
+      // block's sources: the one-sided tile, the self pair masked.  The
+      // slices write disjoint targets of the block's forward slot.
+      const int I = int((it - offd) / K), h = int((it - offd) % K);
+      const int tgt0 = I * TB + h * kBlock;
+      if (tgt0 >= n) continue;  // uniform: a slice past the last body
+      float res[1][NA];
+      pair_block<OP, 1, STAGE_LDS>(n, xy, gam, aux, d2, tgt0, I * TB, min(n, I * TB + TB), lds_diag, res);
+      const int i = tgt0 + tid;
+      if (i < n)
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int i = tgt0 + k * kBlock + tid;
-        if (i < n)
-#pragma unroll
-          for (int a = 0; a < NA; ++a) F[(size_t)(J * NA + a) * n + i] = res[k][a];
-      }
+        for (int a = 0; a < NA; ++a) F[(size_t)(I * NA + a) * n + i] = res[0][a];
       continue;
     }
-    sym_block_pair<OP, K>(n, xy, gam, aux, d2, tgt0, J * TB, s_src, racc_lds, F + (size_t)J * NA * n,
+    int I, J;
+    tri_item(it, nb, I, J);  // J > I
+    sym_block_pair<OP, K>(n, xy, gam, aux, d2, I * TB, J * TB, s_src, racc_lds, F + (size_t)J * NA * n,
                           R + (size_t)I * NA * n);
   }
 }
