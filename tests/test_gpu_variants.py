@@ -16,7 +16,8 @@ from paper_2103_01983_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 # staging k waves sym
-VARIANTS = [(0, 1, 16, 0), (1, 2, 8, 0), (0, 4, 4, 0), (1, 4, 16, 0), (0, 2, 4, 1), (0, 4, 2, 1), (0, 2, 8, 1)]
+VARIANTS = [(0, 1, 16, 0), (1, 2, 8, 0), (0, 4, 4, 0), (1, 4, 16, 0), (0, 2, 4, 1), (0, 4, 2, 1), (0, 2, 8, 1),
+            (0, 4, 4, 1)]
 SIZES = [2, 3, 513, 1024, 2500, 4099]
 
 
