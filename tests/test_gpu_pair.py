@@ -125,6 +125,36 @@ def test_full_size_gaussian_patch_sampled(dev):
     assert abs(np.dot(g, f[:n])) <= 1e-5 * np.abs(g).sum() * np.abs(f).max()
 
 
+def test_full_size_shear_layer_sampled(dev):
+    # N = 131072 (the adjoint configuration's shear layer), the launches the
+    # table picks at that size: every pair operation on 128 sampled targets
+    # against the oracle, and the stream function's Hamiltonian identity
+    c = W.config_cloud("c5_adjoint")
+    xy, g, d = f32(c.xy), f32(c.gamma), np.float32(c.delta)
+    n = g.size
+    idx = np.random.default_rng(5).choice(n, 128, replace=False)
+    sel = np.concatenate([idx, n + idx])
+    xd, gd = to_dev(xy, dev), to_dev(g, dev)
+    f = native.velocity(xd, gd, d).cpu().numpy()
+    assert rel(f[sel], oracle.velocity_at(xy, g, float(d), idx)) <= TOL
+    v = f32(W.unit_vectors(n, 1, 1005)[0])
+    jv = native.jvp(xd, gd, d, to_dev(v, dev)).cpu().numpy()
+    assert rel(jv[sel], oracle.jvp_at(xy, g, float(d), v, idx)) <= TOL
+    gx, gg = native.vjp(xd, gd, d, to_dev(v, dev))
+    ox, og = oracle.vjp_at(xy, g, float(d), v, idx)
+    assert rel(gx.cpu().numpy()[sel], ox) <= TOL
+    assert rel(gg.cpu().numpy()[idx], og) <= TOL
+    B = native.block_jacobian(xd, gd, d).cpu().numpy().reshape(4, n)
+    assert rel(B[:, idx].ravel(), oracle.block_jacobian_at(xy, g, float(d), idx)) <= TOL
+    psi = native.stream_function(xd, gd, d).cpu().numpy()
+    assert rel(psi[idx], oracle.stream_function_at(xy, g, float(d), idx)) <= TOL
+    # the library's FP64 reduction of the same launch's psi, up to summation
+    # order
+    H = native.hamiltonian(xd, gd, d).item()
+    gp = g * psi.astype(np.float64)
+    assert abs(H - 0.5 * gp.sum()) <= 1e-12 * 0.5 * np.abs(gp).sum()
+
+
 def test_deterministic(dev):
     xy, g, d = cloud(20000, 3, "gauss", 0.01)
     xd, gd = to_dev(xy, dev), to_dev(g, dev)
