@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 # staging k waves sym
 VARIANTS = [(0, 1, 16, 0), (1, 2, 8, 0), (0, 4, 4, 0), (1, 4, 16, 0), (0, 2, 4, 1), (0, 4, 2, 1), (0, 2, 8, 1),
             (0, 4, 4, 1)]
-SIZES = [2, 3, 513, 1024, 2500, 4099]
+SIZES = [1, 2, 3, 513, 1024, 2500, 4099]
 
 
 @pytest.fixture(scope="module", params=VARIANTS, ids=lambda v: "st%d_k%d_w%d_sym%d" % v)
@@ -52,6 +52,14 @@ def test_variant_parity(dev, vctx, n, delta):
     v = f32(W.random_vectors(n, 1, n)[0])
     t = lambda a: torch.tensor(a, dtype=torch.float32, device=dev)
     xd, gd, vd = t(xy), t(g), t(v)
+    if n == 1:
+        # a single body: no pair, every sum is exactly zero
+        outs = [native.velocity(xd, gd, d, ctx=vctx), native.jvp(xd, gd, d, vd, ctx=vctx),
+                *native.vjp(xd, gd, d, vd, ctx=vctx), native.block_jacobian(xd, gd, d, ctx=vctx),
+                *native.velocity_block_jacobian(xd, gd, d, ctx=vctx), native.stream_function(xd, gd, d, ctx=vctx)]
+        for o in outs:
+            assert torch.count_nonzero(o).item() == 0
+        return
     f = native.velocity(xd, gd, d, ctx=vctx).cpu().numpy()
     assert np.all(np.isfinite(f))
     assert rel(f, oracle.velocity(xy, g, d)) <= 1e-5
@@ -69,6 +77,34 @@ def test_variant_parity(dev, vctx, n, delta):
     assert rel(B2.cpu().numpy(), ob) <= 1e-5
     psi = native.stream_function(xd, gd, d, ctx=vctx).cpu().numpy()
     assert np.all(np.isfinite(psi))
+    assert rel(psi, oracle.stream_function(xy, g, d)) <= 1e-5
+
+
+def test_variant_coincident_bodies(dev, vctx):
+    # distinct bodies at the same position (every third body repeats the one
+    # before it): with delta > 0 each such pair adds nothing to the velocity
+    # and the Jacobians and log(delta^2) to the stream function
+    n = 1500
+    c = W.disk_cloud(n, seed=77, delta=0.01)
+    xy = f32(c.xy).copy()
+    g = f32(c.gamma)
+    for i in range(1, n, 3):
+        xy[i] = xy[i - 1]
+        xy[n + i] = xy[n + i - 1]
+    d = float(np.float32(0.01))
+    v = f32(W.random_vectors(n, 1, 77)[0])
+    t = lambda a: torch.tensor(a, dtype=torch.float32, device=dev)
+    xd, gd, vd = t(xy), t(g), t(v)
+    f = native.velocity(xd, gd, d, ctx=vctx).cpu().numpy()
+    assert rel(f, oracle.velocity(xy, g, d)) <= 1e-5
+    jv = native.jvp(xd, gd, d, vd, ctx=vctx).cpu().numpy()
+    assert rel(jv, oracle.jvp(xy, g, d, v)) <= 1e-5
+    gx, gg = native.vjp(xd, gd, d, vd, ctx=vctx)
+    ox, og = oracle.vjp(xy, g, d, v)
+    assert rel(gx.cpu().numpy(), ox) <= 1e-5
+    assert rel(gg.cpu().numpy(), og) <= 1e-5
+    assert rel(native.block_jacobian(xd, gd, d, ctx=vctx).cpu().numpy(), oracle.block_jacobian(xy, g, d)) <= 1e-5
+    psi = native.stream_function(xd, gd, d, ctx=vctx).cpu().numpy()
     assert rel(psi, oracle.stream_function(xy, g, d)) <= 1e-5
 
 
