@@ -406,6 +406,34 @@ def test_edge_shapes_parity(dev, edge_shapes, shape):
     _run_check(dev, edge_shapes[shape])
 
 
+BOUNDS = [(1, 2, 1), (9, 18, 9), (17, 34, 17), (25, 50, 25)]
+
+
+@pytest.fixture(scope="module")
+def bound_shapes():
+    """The degenerate one-mode, one-body case (M = 1, M_r = 2, n_s = 1) and
+    the first basis size of each of the small kernel's bounds 16, 24 and 32."""
+    out = {}
+    cl = W.counter_rotating_patches(640, seed=47, delta=0.02)
+    n = cl.n
+    rng = np.random.default_rng(48)
+    for M, Mr, ns in BOUNDS:
+        Phi = np.linalg.qr(rng.standard_normal((2 * n, M)))[0]
+        sig = np.sort(rng.uniform(1.0, 10.0, M))[::-1]
+        tree = off.QuadTree(off.weighted_points(Phi, sig), 6)
+        sample = np.sort(rng.choice(n, ns, replace=False))
+        Phi_r = np.linalg.qr(rng.standard_normal((2 * n, Mr)))[0]
+        A = off.gappy_operator(Phi_r, sample)
+        out[(M, Mr, ns)] = rounded(off.rom_artifacts(sample, tree, 1.0, cl.xy, Phi, cl.gamma, cl.delta, 1e-3, A=A))
+    return out
+
+
+@pytest.mark.parametrize("shape", BOUNDS)
+def test_basis_bound_shapes_parity(dev, bound_shapes, shape):
+    _hyperpair_check(dev, bound_shapes[shape], 11)
+    _run_check(dev, bound_shapes[shape])
+
+
 def test_largest_shape_beyond_lds_runs_from_global_memory(dev, edge_shapes):
     # arrays that do not fit one workgroup's LDS: [C | rbar] and the normal
     # matrix go to global memory and the run matches the oracle
