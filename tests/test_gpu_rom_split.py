@@ -204,6 +204,23 @@ def test_split_abort_path_exits_cleanly(dev, c3):
     rom.close()
 
 
+@pytest.mark.parametrize("shape,W_", [((13, 26, 26), 4), ((21, 42, 42), 3), ((32, 64, 32), 2)])
+def test_split_at_larger_basis_bounds(dev, shape, W_):
+    # forced splits of the single-vortex study's shapes, one per basis bound
+    # (16, 24, 32) of the small kernel
+    M, Mr, ns = shape
+    art = synth(W.counter_rotating_patches(640, seed=41, delta=0.02), M, Mr, ns, 6, 50 + M)
+    steps, K = 6, 3
+    o = oracle.Rom(art).run(steps, tol=0.0, max_iter=K)
+    p, h, it, _ = run(art, W_, steps, K)
+    assert p >= W_
+    assert np.all(it == K)
+    assert rel(h, o["hist"]) <= 1e-5
+    _, h1, i1, _ = run(art, 1, steps, K)
+    assert np.array_equal(it, i1)
+    assert rel(h, h1) <= 1e-6
+
+
 def test_set_split_rejects_out_of_range(dev, small):
     rom = native.Rom(small)
     for bad in (-1, 65):
