@@ -31,10 +31,11 @@ def test_noalloc_matches_velocity_on_two_calls(dev):
     h = native.make_context(0, native.TUNING_PATH)
     try:
         # 65536: the tuned each-pair-once workspace (67 MB) does not fit the
-        # 36 MB scratch, so the call takes the one-sided launch; 3001 (the second,
-        # smaller input): the tuned launch fits and the result is bitwise
-        # that of ptrom_velocity
-        for n, seed, bitwise in ((65536, 1002, False), (3001, 77, True)):
+        # 36 MB scratch, so the call takes the one-sided launch; 32768 (the
+        # second, smaller input): the tuned each-pair-once launch (34 MB of
+        # slots) fits and the result is bitwise that of ptrom_velocity; 3001:
+        # the tuned one-sided launch, bitwise too
+        for n, seed, bitwise in ((65536, 1002, False), (32768, 1003, True), (3001, 77, True)):
             xy, g, d, xd, gd = _inputs(n, seed, dev)
             out = torch.full_like(xd, float("nan"))
             if n == 65536:
