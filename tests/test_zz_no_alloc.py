@@ -80,3 +80,35 @@ def test_noalloc_rejects_bad_arguments(dev):
         assert L.ptrom_velocity_noalloc(h, 2**30 + 1, p(x), p(x), 0.01, p(x), s) == -1
     finally:
         native.destroy_context(h)
+
+
+@pytest.mark.parametrize("n", [32768, 3001])
+def test_noalloc_replays_in_a_captured_graph(dev, n):
+    # the call captured into a HIP graph (it allocates nothing, so capture
+    # allows it), replayed three times with new positions written eagerly
+    # into the captured input between replays; every replay is bitwise the
+    # allocating call on the same positions
+    h = native.make_context(0, native.TUNING_PATH)
+    try:
+        xy, g, d, xd, gd = _inputs(n, 200 + n, dev)
+        out = torch.empty_like(xd)
+        native.velocity_noalloc(xd, gd, d, out, ctx=h)  # the device's scratch address is looked up once
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            native.velocity_noalloc(xd, gd, d, out, ctx=h)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(n)
+        for rep in range(3):
+            moved = xy + rng.standard_normal(xy.size) * 1e-3
+            xd.copy_(torch.tensor(moved, dtype=torch.float32, device=dev))
+            out.fill_(float("nan"))
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            ref = native.velocity(xd, gd, d, ctx=h)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (n, rep)
+        del graph
+    finally:
+        native.destroy_context(h)
