@@ -112,9 +112,19 @@ __global__ void __launch_bounds__(64 * kSlices)
   for (int a = 0; a < NA; ++a) {
     float s = 0.0f, c = 0.0f;
     if (ok) {
-      for (int q = q0; q < q1; ++q) {
-        const float v = q < nf ? F[(size_t)((B + q) * NA + a) * n + b] : R[(size_t)((q - nf) * NA + a) * n + b];
-        kahan_add(s, c, v);
+      // eight slots' loads in flight, then their compensated sum in slot order
+      for (int q = q0; q < q1; q += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int qq = q + u;
+          v[u] = qq >= q1   ? 0.0f
+                 : qq < nf ? F[(size_t)((B + qq) * NA + a) * n + b]
+                           : R[(size_t)((qq - nf) * NA + a) * n + b];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (q + u < q1) kahan_add(s, c, v[u]);
       }
     }
     part[a][slice][lane] = s - c;
